@@ -1,0 +1,655 @@
+/*
+ * fmm_oracle.c -- CPU reference ("oracle") for the 3-D Laplace fast multipole
+ * method.  TEST INFRASTRUCTURE ONLY: this file is compiled into liboracle.so,
+ * which only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load.  The GPU library never links, includes or calls it, and it
+ * shares no code, header, table or generator with the GPU library.
+ *
+ * What is computed
+ * ----------------
+ *   Exact sum (the quantity the method approximates):
+ *       phi_i = sum_{j != i} q_j / |x_i - x_j|,    F_i = -q_i grad phi_i,
+ *       E     = 1/2 sum_i q_i phi_i.
+ *   Open boundary, pure 1/r kernel (no Coulomb constant), no softening.
+ *
+ *   FMM result: a uniform octree of depth L over a cube (root = level 0,
+ *   leaves = level L), well-separatedness 1 (near list = the 27 boxes at
+ *   Chebyshev index distance <= 1, interaction list = children of the parent's
+ *   near list that are not in the box's own near list), multipole and local
+ *   expansions of degree <= p about box centres, every (local degree <= p,
+ *   multipole degree <= p) pair kept in the multipole-to-local translation.
+ *   Steps in the method's order (Greengard, "The Rapid Evaluation of Potential
+ *   Fields in Particle Systems", MIT Press 1988, ch. 3; Cheng, Greengard &
+ *   Rokhlin, J. Comput. Phys. 155:468 (1999), sec. 2-3):
+ *       P2M -> M2M (leaf level up to level 2) -> M2L (levels 2..L)
+ *       -> L2L (level 2 down to the leaves) -> L2P, plus the P2P near sum.
+ *
+ * Basis
+ * -----
+ *   Complex solid harmonics with the Epton-Dembart normalisation
+ *   (SIAM J. Sci. Comput. 16:865 (1995)):
+ *       R_n^m(x) = r^n P_n^m(cos t) e^{i m f} / (n+m)!       (regular)
+ *       I_n^m(x) = (n-m)! P_n^m(cos t) e^{i m f} / r^{n+1}    (irregular)
+ *   with the Condon-Shortley phase in P_n^m and, for negative orders,
+ *   R_n^{-m} = (-1)^m conj(R_n^m), I_n^{-m} = (-1)^m conj(I_n^m).
+ *   All orders -n..n are stored and summed (no real-charge symmetry is used),
+ *   so each sum below is the textbook formula written out.
+ *   Addition theorems used:
+ *     (A1) 1/|x-y|      = sum_{n,m} conj(R_n^m(y)) I_n^m(x),           |y|<|x|
+ *     (A2) R_n^m(x+y)   = sum_{k<=n,l} R_k^l(x) R_{n-k}^{m-l}(y)
+ *     (A3) I_n^m(x-y)   = sum_{k,l} conj(R_k^l(y)) I_{n+k}^{m+l}(x),    |y|<|x|
+ *     (A4) d/dz R_n^m = R_{n-1}^m,  d/dx R_n^m = (R_{n-1}^{m+1} - R_{n-1}^{m-1})/2,
+ *          d/dy R_n^m = -i (R_{n-1}^{m-1} + R_{n-1}^{m+1})/2
+ *   giving the operators
+ *     P2M  M_n^m  = sum_j q_j conj(R_n^m(y_j - c))
+ *     M2P  phi(x) = sum M_n^m I_n^m(x - c)
+ *     M2M  M'_n^m = sum_{k,l} M_k^l conj(R_{n-k}^{m-l}(c - c'))          (A2)
+ *     M2L  L_k^l  = (-1)^{k+l} sum_{n,m} M_n^m I_{n+k}^{m-l}(c_t - c_s)   (A3)
+ *     L2L  L'_j^i = sum_{k>=j,l} L_k^l R_{k-j}^{l-i}(c' - c)              (A2)
+ *     L2P  phi(x) = Re sum L_k^l R_k^l(x - c), gradient by (A4).
+ *
+ * Tree conventions (readings where the problem statement is silent)
+ * -----------------------------------------------------------------
+ *   cube: [lo, lo+side]^3 as given; if side <= 0 it is derived as
+ *         lo_a = min_i x_ia, side = max_a (max_i x_ia - lo_a) (1 if that is 0).
+ *   leaf cell per axis: floor(((x - lo)/side) * 2^L), clamped to [0, 2^L - 1]
+ *         (a point on an internal face belongs to the upper cell; the top face
+ *         is clamped into the last cell).  A given cube that does not contain
+ *         a point is an error (ORACLE_E_OUT_OF_CUBE).
+ *   particles are ordered by lexicographic leaf index (ix, iy, iz), stable.
+ *   box centre at level l: lo + (i + 1/2) side / 2^l.
+ *
+ * Parity status: every function here is pinned by tests that do not re-use
+ * its formulas (brute-force truncated Taylor kernel, Legendre closed forms,
+ * direct-sum invariants, finite differences); none is "parity unpinned".
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef double complex cplx;
+
+enum {
+  ORACLE_OK = 0,
+  ORACLE_E_INVALID_ARG = 1,
+  ORACLE_E_OUT_OF_CUBE = 3,
+  ORACLE_E_NONFINITE = 4,
+  ORACLE_E_COINCIDENT = 5,
+  ORACLE_E_NOMEM = 8
+};
+
+#define ORACLE_PMAX 20
+#define ORACLE_LMAX 10
+
+static inline int hidx(int n, int m) { return n * n + n + m; }
+static inline int nharm(int p) { return (p + 1) * (p + 1); }
+
+/* ------------------------------------------------------------------------ */
+/* Solid harmonics by the three-term Legendre recurrences.                   */
+/* ------------------------------------------------------------------------ */
+
+/* R_n^m(x) for 0 <= n <= p, -n <= m <= n. */
+static void regular_harmonics(double x, double y, double z, int p, cplx *R) {
+  const double r2 = x * x + y * y + z * z;
+  const cplx xy = x + I * y;
+  R[hidx(0, 0)] = 1.0;
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) R[hidx(m, m)] = -xy / (2.0 * m) * R[hidx(m - 1, m - 1)];
+    if (m + 1 <= p) R[hidx(m + 1, m)] = z * R[hidx(m, m)];
+    for (int n = m + 2; n <= p; ++n)
+      R[hidx(n, m)] = ((2.0 * n - 1.0) * z * R[hidx(n - 1, m)] - r2 * R[hidx(n - 2, m)]) /
+                      ((double)(n - m) * (double)(n + m));
+  }
+  for (int n = 1; n <= p; ++n)
+    for (int m = 1; m <= n; ++m)
+      R[hidx(n, -m)] = ((m & 1) ? -1.0 : 1.0) * conj(R[hidx(n, m)]);
+}
+
+/* I_n^m(x) for 0 <= n <= p, -n <= m <= n; x != 0. */
+static void irregular_harmonics(double x, double y, double z, int p, cplx *Ih) {
+  const double r2 = x * x + y * y + z * z;
+  const cplx xy = x + I * y;
+  Ih[hidx(0, 0)] = 1.0 / sqrt(r2);
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) Ih[hidx(m, m)] = -(2.0 * m - 1.0) * xy / r2 * Ih[hidx(m - 1, m - 1)];
+    if (m + 1 <= p) Ih[hidx(m + 1, m)] = (2.0 * m + 1.0) * z / r2 * Ih[hidx(m, m)];
+    for (int n = m + 2; n <= p; ++n)
+      Ih[hidx(n, m)] = ((2.0 * n - 1.0) * z * Ih[hidx(n - 1, m)] -
+                        (double)(n + m - 1) * (double)(n - m - 1) * Ih[hidx(n - 2, m)]) / r2;
+  }
+  for (int n = 1; n <= p; ++n)
+    for (int m = 1; m <= n; ++m)
+      Ih[hidx(n, -m)] = ((m & 1) ? -1.0 : 1.0) * conj(Ih[hidx(n, m)]);
+}
+
+static inline cplx harm_get(const cplx *H, int pmax, int n, int m) {
+  if (n < 0 || n > pmax || m < -n || m > n) return 0.0;
+  return H[hidx(n, m)];
+}
+
+/* ------------------------------------------------------------------------ */
+/* The six operators, one call = one translation (no batching or fusion).    */
+/* ------------------------------------------------------------------------ */
+
+/* P2M: M += q conj(R(y - c)). */
+static void op_p2m(int p, const double y[3], double q, const double c[3], cplx *M) {
+  cplx R[(ORACLE_PMAX + 1) * (ORACLE_PMAX + 1)];
+  regular_harmonics(y[0] - c[0], y[1] - c[1], y[2] - c[2], p, R);
+  for (int i = 0; i < nharm(p); ++i) M[i] += q * conj(R[i]);
+}
+
+/* M2M: multipole M about c -> added into Mp about cp. */
+static void op_m2m(int p, const cplx *M, const double c[3], const double cp[3], cplx *Mp) {
+  cplx R[(ORACLE_PMAX + 1) * (ORACLE_PMAX + 1)];
+  regular_harmonics(c[0] - cp[0], c[1] - cp[1], c[2] - cp[2], p, R);
+  for (int n = 0; n <= p; ++n)
+    for (int m = -n; m <= n; ++m) {
+      cplx acc = 0.0;
+      for (int k = 0; k <= n; ++k)
+        for (int l = -k; l <= k; ++l)
+          acc += M[hidx(k, l)] * conj(harm_get(R, p, n - k, m - l));
+      Mp[hidx(n, m)] += acc;
+    }
+}
+
+/* M2L: multipole M about cs -> added into local L about ct. */
+static void op_m2l(int p, const cplx *M, const double cs[3], const double ct[3], cplx *L) {
+  cplx Ih[(2 * ORACLE_PMAX + 1) * (2 * ORACLE_PMAX + 1)];
+  irregular_harmonics(ct[0] - cs[0], ct[1] - cs[1], ct[2] - cs[2], 2 * p, Ih);
+  for (int k = 0; k <= p; ++k)
+    for (int l = -k; l <= k; ++l) {
+      cplx acc = 0.0;
+      for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m)
+          acc += M[hidx(n, m)] * harm_get(Ih, 2 * p, n + k, m - l);
+      L[hidx(k, l)] += (((k + l) & 1) ? -1.0 : 1.0) * acc;
+    }
+}
+
+/* L2L: local L about c -> added into local Lc about cc. */
+static void op_l2l(int p, const cplx *L, const double c[3], const double cc[3], cplx *Lc) {
+  cplx R[(ORACLE_PMAX + 1) * (ORACLE_PMAX + 1)];
+  regular_harmonics(cc[0] - c[0], cc[1] - c[1], cc[2] - c[2], p, R);
+  for (int j = 0; j <= p; ++j)
+    for (int i = -j; i <= j; ++i) {
+      cplx acc = 0.0;
+      for (int k = j; k <= p; ++k)
+        for (int l = -k; l <= k; ++l)
+          acc += L[hidx(k, l)] * harm_get(R, p, k - j, l - i);
+      Lc[hidx(j, i)] += acc;
+    }
+}
+
+/* L2P: potential and gradient of the local expansion L about c at x. */
+static void op_l2p(int p, const cplx *L, const double c[3], const double x[3], double *phi,
+                   double grad[3]) {
+  cplx R[(ORACLE_PMAX + 1) * (ORACLE_PMAX + 1)];
+  regular_harmonics(x[0] - c[0], x[1] - c[1], x[2] - c[2], p, R);
+  cplx f = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+  for (int n = 0; n <= p; ++n)
+    for (int m = -n; m <= n; ++m) {
+      const cplx a = L[hidx(n, m)];
+      f += a * R[hidx(n, m)];
+      if (n == 0) continue;
+      const cplx rm = harm_get(R, p, n - 1, m - 1), rp = harm_get(R, p, n - 1, m + 1);
+      gz += a * harm_get(R, p, n - 1, m);
+      gx += a * 0.5 * (rp - rm);
+      gy += a * (-0.5 * I) * (rm + rp);
+    }
+  *phi = creal(f);
+  grad[0] = creal(gx);
+  grad[1] = creal(gy);
+  grad[2] = creal(gz);
+}
+
+/* M2P: potential of the multipole M about c at x (used by the operator pins). */
+static double op_m2p(int p, const cplx *M, const double c[3], const double x[3]) {
+  cplx Ih[(ORACLE_PMAX + 1) * (ORACLE_PMAX + 1)];
+  irregular_harmonics(x[0] - c[0], x[1] - c[1], x[2] - c[2], p, Ih);
+  cplx f = 0.0;
+  for (int i = 0; i < nharm(p); ++i) f += M[i] * Ih[i];
+  return creal(f);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neumaier-compensated accumulation.                                        */
+/* ------------------------------------------------------------------------ */
+typedef struct { double s, c; } ksum;
+static inline void ksum_add(ksum *k, double v) {
+  const double t = k->s + v;
+  if (fabs(k->s) >= fabs(v)) k->c += (k->s - t) + v;
+  else k->c += (v - t) + k->s;
+  k->s = t;
+}
+static inline double ksum_val(const ksum *k) { return k->s + k->c; }
+
+/* ------------------------------------------------------------------------ */
+/* Direct sum.                                                               */
+/* ------------------------------------------------------------------------ */
+
+/* phi/force for the targets listed (all particles when targets == NULL);
+ * energy (when non-NULL and targets == NULL) = 1/2 sum q_i phi_i. */
+int oracle_direct(int64_t n, const double *pos, const double *q, int64_t nt,
+                  const int64_t *targets, double *phi, double *force, double *energy) {
+  if (n < 0 || !pos || !q) return ORACLE_E_INVALID_ARG;
+  if (!targets) nt = n;
+  double *phi_tmp = NULL;
+  if (!phi && energy && !targets) {
+    phi_tmp = malloc(sizeof(double) * (n ? n : 1));
+    if (!phi_tmp) return ORACLE_E_NOMEM;
+    phi = phi_tmp;
+  }
+  int status = ORACLE_OK;
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t i = targets ? targets[t] : t;
+    ksum f = {0, 0}, gx = {0, 0}, gy = {0, 0}, gz = {0, 0};
+    for (int64_t j = 0; j < n; ++j) {
+      if (j == i) continue;
+      const double dx = pos[3 * i] - pos[3 * j], dy = pos[3 * i + 1] - pos[3 * j + 1],
+                   dz = pos[3 * i + 2] - pos[3 * j + 2];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      if (r2 == 0.0) {
+#pragma omp atomic write
+        status = ORACLE_E_COINCIDENT;
+        continue;
+      }
+      const double r = sqrt(r2);
+      const double qr = q[j] / r, qr3 = qr / r2;
+      ksum_add(&f, qr);
+      /* grad phi_i = -sum_j q_j (x_i - x_j) / r^3 */
+      ksum_add(&gx, -qr3 * dx);
+      ksum_add(&gy, -qr3 * dy);
+      ksum_add(&gz, -qr3 * dz);
+    }
+    if (phi) phi[t] = ksum_val(&f);
+    if (force) {
+      force[3 * t] = -q[i] * ksum_val(&gx);
+      force[3 * t + 1] = -q[i] * ksum_val(&gy);
+      force[3 * t + 2] = -q[i] * ksum_val(&gz);
+    }
+  }
+  if (energy && !targets) {
+    ksum e = {0, 0};
+    for (int64_t i = 0; i < n; ++i) ksum_add(&e, q[i] * phi[i]);
+    *energy = 0.5 * ksum_val(&e);
+  }
+  free(phi_tmp);
+  return status;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tree.                                                                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int L, p, nh;
+  double lo[3], side;
+  int64_t n;
+  int32_t *cell;    /* n x 3 leaf cell per particle (user order) */
+  int64_t *order;   /* particles sorted by lexicographic leaf index */
+  int64_t *start;   /* leaf start in order[], 8^L + 1 entries */
+  int64_t lvl_off[ORACLE_LMAX + 2]; /* box offset of each level in the arrays below */
+  cplx *M, *Lc;     /* expansions for every box of every level */
+} otree;
+
+static inline int64_t box_lin(int l, int ix, int iy, int iz) {
+  const int64_t nb = (int64_t)1 << l;
+  return ((int64_t)ix * nb + iy) * nb + iz;
+}
+
+static void box_centre(const otree *T, int l, int ix, int iy, int iz, double c[3]) {
+  const double h = T->side / (double)((int64_t)1 << l);
+  c[0] = T->lo[0] + (ix + 0.5) * h;
+  c[1] = T->lo[1] + (iy + 0.5) * h;
+  c[2] = T->lo[2] + (iz + 0.5) * h;
+}
+
+static int resolve_cube(int64_t n, const double *pos, const double lo_in[3], double side_in,
+                        double lo[3], double *side) {
+  for (int64_t i = 0; i < 3 * n; ++i)
+    if (!isfinite(pos[i])) return ORACLE_E_NONFINITE;
+  if (side_in > 0) {
+    if (!lo_in) return ORACLE_E_INVALID_ARG;
+    for (int a = 0; a < 3; ++a) lo[a] = lo_in[a];
+    *side = side_in;
+    for (int64_t i = 0; i < n; ++i)
+      for (int a = 0; a < 3; ++a) {
+        const double t = (pos[3 * i + a] - lo[a]) / side_in;
+        if (!(t >= 0.0 && t <= 1.0)) return ORACLE_E_OUT_OF_CUBE;
+      }
+    return ORACLE_OK;
+  }
+  double hi[3];
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = n ? pos[a] : 0.0;
+    hi[a] = lo[a];
+  }
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) {
+      if (pos[3 * i + a] < lo[a]) lo[a] = pos[3 * i + a];
+      if (pos[3 * i + a] > hi[a]) hi[a] = pos[3 * i + a];
+    }
+  double s = 0.0;
+  for (int a = 0; a < 3; ++a)
+    if (hi[a] - lo[a] > s) s = hi[a] - lo[a];
+  *side = (s > 0.0) ? s : 1.0;
+  return ORACLE_OK;
+}
+
+static int leaf_cell_axis(double x, double lo, double side, int L) {
+  const double t = (x - lo) / side;
+  const int64_t nb = (int64_t)1 << L;
+  double f = floor(t * (double)nb);
+  int64_t c = (int64_t)f;
+  if (c < 0) c = 0;
+  if (c > nb - 1) c = nb - 1;
+  return (int)c;
+}
+
+static void otree_free(otree *T) {
+  free(T->cell);
+  free(T->order);
+  free(T->start);
+  free(T->M);
+  free(T->Lc);
+}
+
+static int otree_build(otree *T, int64_t n, const double *pos, int L, int p,
+                       const double lo_in[3], double side_in) {
+  memset(T, 0, sizeof(*T));
+  T->L = L;
+  T->p = p;
+  T->nh = nharm(p);
+  T->n = n;
+  int st = resolve_cube(n, pos, lo_in, side_in, T->lo, &T->side);
+  if (st) return st;
+  const int64_t nleaf = (int64_t)1 << (3 * L);
+  T->cell = malloc(sizeof(int32_t) * 3 * (n ? n : 1));
+  T->order = malloc(sizeof(int64_t) * (n ? n : 1));
+  T->start = calloc(nleaf + 1, sizeof(int64_t));
+  if (!T->cell || !T->order || !T->start) return ORACLE_E_NOMEM;
+  int64_t *leaf = malloc(sizeof(int64_t) * (n ? n : 1));
+  if (!leaf) return ORACLE_E_NOMEM;
+  for (int64_t i = 0; i < n; ++i) {
+    int c[3];
+    for (int a = 0; a < 3; ++a) {
+      c[a] = leaf_cell_axis(pos[3 * i + a], T->lo[a], T->side, L);
+      T->cell[3 * i + a] = c[a];
+    }
+    leaf[i] = box_lin(L, c[0], c[1], c[2]);
+    T->start[leaf[i] + 1]++;
+  }
+  for (int64_t b = 0; b < nleaf; ++b) T->start[b + 1] += T->start[b];
+  int64_t *fill = malloc(sizeof(int64_t) * nleaf);
+  if (!fill) { free(leaf); return ORACLE_E_NOMEM; }
+  memcpy(fill, T->start, sizeof(int64_t) * nleaf);
+  for (int64_t i = 0; i < n; ++i) T->order[fill[leaf[i]]++] = i; /* stable */
+  free(fill);
+  free(leaf);
+  int64_t off = 0;
+  for (int l = 0; l <= L; ++l) {
+    T->lvl_off[l] = off;
+    off += (int64_t)1 << (3 * l);
+  }
+  T->lvl_off[L + 1] = off;
+  T->M = calloc((size_t)off * T->nh, sizeof(cplx));
+  T->Lc = calloc((size_t)off * T->nh, sizeof(cplx));
+  if (!T->M || !T->Lc) return ORACLE_E_NOMEM;
+  return ORACLE_OK;
+}
+
+static inline cplx *exp_at(const otree *T, cplx *base, int l, int64_t b) {
+  return base + (size_t)(T->lvl_off[l] + b) * T->nh;
+}
+
+/* Upward pass: P2M at the leaves, then M2M from level L-1 up to level 2. */
+static void upward_pass(otree *T, const double *pos, const double *q) {
+  const int L = T->L, p = T->p;
+  const int nb = 1 << L;
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t b = 0; b < (int64_t)nb * nb * nb; ++b) {
+    const int ix = (int)(b / ((int64_t)nb * nb)), iy = (int)((b / nb) % nb), iz = (int)(b % nb);
+    double c[3];
+    box_centre(T, L, ix, iy, iz, c);
+    cplx *M = exp_at(T, T->M, L, b);
+    for (int64_t k = T->start[b]; k < T->start[b + 1]; ++k) {
+      const int64_t j = T->order[k];
+      op_p2m(p, pos + 3 * j, q[j], c, M);
+    }
+  }
+  for (int l = L - 1; l >= 2; --l) {
+    const int nl = 1 << l;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t b = 0; b < (int64_t)nl * nl * nl; ++b) {
+      const int ix = (int)(b / ((int64_t)nl * nl)), iy = (int)((b / nl) % nl), iz = (int)(b % nl);
+      double cp[3];
+      box_centre(T, l, ix, iy, iz, cp);
+      cplx *Mp = exp_at(T, T->M, l, b);
+      for (int ch = 0; ch < 8; ++ch) {
+        const int cx = 2 * ix + (ch >> 2), cy = 2 * iy + ((ch >> 1) & 1), cz = 2 * iz + (ch & 1);
+        double cc[3];
+        box_centre(T, l + 1, cx, cy, cz, cc);
+        op_m2m(p, exp_at(T, T->M, l + 1, box_lin(l + 1, cx, cy, cz)), cc, cp, Mp);
+      }
+    }
+  }
+}
+
+static inline int iabs_(int a) { return a < 0 ? -a : a; }
+
+/* Interaction list of box (ix,iy,iz) at level l >= 2: children of the
+ * parent's near boxes that are not adjacent to the box.  M2L of each of them
+ * into the box's local expansion. */
+static void m2l_box(otree *T, int l, int ix, int iy, int iz) {
+  const int nl = 1 << l, p = T->p;
+  double ct[3];
+  box_centre(T, l, ix, iy, iz, ct);
+  cplx *Lt = exp_at(T, T->Lc, l, box_lin(l, ix, iy, iz));
+  const int px = ix >> 1, py = iy >> 1, pz = iz >> 1;
+  for (int ax = px - 1; ax <= px + 1; ++ax)
+    for (int ay = py - 1; ay <= py + 1; ++ay)
+      for (int az = pz - 1; az <= pz + 1; ++az) {
+        if (ax < 0 || ay < 0 || az < 0 || 2 * ax >= nl || 2 * ay >= nl || 2 * az >= nl) continue;
+        for (int ch = 0; ch < 8; ++ch) {
+          const int sx = 2 * ax + (ch >> 2), sy = 2 * ay + ((ch >> 1) & 1), sz = 2 * az + (ch & 1);
+          if (iabs_(sx - ix) <= 1 && iabs_(sy - iy) <= 1 && iabs_(sz - iz) <= 1) continue;
+          double cs[3];
+          box_centre(T, l, sx, sy, sz, cs);
+          op_m2l(p, exp_at(T, T->M, l, box_lin(l, sx, sy, sz)), cs, ct, Lt);
+        }
+      }
+}
+
+/* Near field of particle i (in leaf (cx,cy,cz)): sum over the 27 neighbour
+ * leaves, j != i. */
+static int p2p_particle(const otree *T, const double *pos, const double *q, int64_t i,
+                        double *phi, double grad[3]) {
+  const int L = T->L, nb = 1 << L;
+  const int cx = T->cell[3 * i], cy = T->cell[3 * i + 1], cz = T->cell[3 * i + 2];
+  ksum f = {0, 0}, gx = {0, 0}, gy = {0, 0}, gz = {0, 0};
+  int status = ORACLE_OK;
+  for (int ax = cx - 1; ax <= cx + 1; ++ax)
+    for (int ay = cy - 1; ay <= cy + 1; ++ay)
+      for (int az = cz - 1; az <= cz + 1; ++az) {
+        if (ax < 0 || ay < 0 || az < 0 || ax >= nb || ay >= nb || az >= nb) continue;
+        const int64_t b = box_lin(L, ax, ay, az);
+        for (int64_t k = T->start[b]; k < T->start[b + 1]; ++k) {
+          const int64_t j = T->order[k];
+          if (j == i) continue;
+          const double dx = pos[3 * i] - pos[3 * j], dy = pos[3 * i + 1] - pos[3 * j + 1],
+                       dz = pos[3 * i + 2] - pos[3 * j + 2];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) {
+            status = ORACLE_E_COINCIDENT;
+            continue;
+          }
+          const double r = sqrt(r2), qr = q[j] / r, qr3 = qr / r2;
+          ksum_add(&f, qr);
+          ksum_add(&gx, -qr3 * dx);
+          ksum_add(&gy, -qr3 * dy);
+          ksum_add(&gz, -qr3 * dz);
+        }
+      }
+  *phi = ksum_val(&f);
+  grad[0] = ksum_val(&gx);
+  grad[1] = ksum_val(&gy);
+  grad[2] = ksum_val(&gz);
+  return status;
+}
+
+/* Full FMM (targets == NULL) or the FMM result at the listed targets only.
+ * In the second form the upward pass is done in full and the downward pass
+ * only along the ancestors of the targets' leaves; the values are the same as
+ * the full run's. */
+int oracle_fmm(int64_t n, const double *pos, const double *q, int depth, int p,
+               const double lo[3], double side, int64_t nt, const int64_t *targets, double *phi,
+               double *force, double *energy) {
+  if (n < 0 || !pos || !q || depth < 0 || depth > ORACLE_LMAX || p < 0 || p > ORACLE_PMAX)
+    return ORACLE_E_INVALID_ARG;
+  if (!targets) nt = n;
+  for (int64_t t = 0; t < nt; ++t)
+    if (targets && (targets[t] < 0 || targets[t] >= n)) return ORACLE_E_INVALID_ARG;
+  otree T;
+  int st = otree_build(&T, n, pos, depth, p, lo, side);
+  if (st) { otree_free(&T); return st; }
+  const int L = depth;
+
+  /* Which boxes need a local expansion: ancestors (levels 2..L) of a target's leaf. */
+  const int64_t nbox = T.lvl_off[L + 1];
+  unsigned char *need = calloc(nbox ? nbox : 1, 1);
+  if (!need) { otree_free(&T); return ORACLE_E_NOMEM; }
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t i = targets ? targets[t] : t;
+    for (int l = 2; l <= L; ++l) {
+      const int s = L - l;
+      need[T.lvl_off[l] + box_lin(l, T.cell[3 * i] >> s, T.cell[3 * i + 1] >> s,
+                                  T.cell[3 * i + 2] >> s)] = 1;
+    }
+  }
+
+  if (L >= 2) {
+    upward_pass(&T, pos, q);
+    /* M2L, every level 2..L */
+    for (int l = 2; l <= L; ++l) {
+      const int nl = 1 << l;
+#pragma omp parallel for schedule(dynamic, 4)
+      for (int64_t b = 0; b < (int64_t)nl * nl * nl; ++b) {
+        if (!need[T.lvl_off[l] + b]) continue;
+        m2l_box(&T, l, (int)(b / ((int64_t)nl * nl)), (int)((b / nl) % nl), (int)(b % nl));
+      }
+    }
+    /* L2L, level 2 down to L-1 into their children */
+    for (int l = 2; l < L; ++l) {
+      const int nl = 1 << (l + 1);
+#pragma omp parallel for schedule(dynamic, 16)
+      for (int64_t b = 0; b < (int64_t)nl * nl * nl; ++b) {
+        if (!need[T.lvl_off[l + 1] + b]) continue;
+        const int cx = (int)(b / ((int64_t)nl * nl)), cy = (int)((b / nl) % nl), cz = (int)(b % nl);
+        double cp[3], cc[3];
+        box_centre(&T, l, cx >> 1, cy >> 1, cz >> 1, cp);
+        box_centre(&T, l + 1, cx, cy, cz, cc);
+        op_l2l(p, exp_at(&T, T.Lc, l, box_lin(l, cx >> 1, cy >> 1, cz >> 1)), cp, cc,
+               exp_at(&T, T.Lc, l + 1, b));
+      }
+    }
+  }
+
+  int status = ORACLE_OK;
+  double *phi_all = phi;
+  double *phi_tmp = NULL;
+  if (!phi) {
+    phi_tmp = malloc(sizeof(double) * (nt ? nt : 1));
+    phi_all = phi_tmp;
+  }
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t i = targets ? targets[t] : t;
+    double fn, gn[3], ff = 0.0, gf[3] = {0.0, 0.0, 0.0};
+    int s = p2p_particle(&T, pos, q, i, &fn, gn);
+    if (s) {
+#pragma omp atomic write
+      status = s;
+    }
+    if (L >= 2) {
+      double c[3];
+      box_centre(&T, L, T.cell[3 * i], T.cell[3 * i + 1], T.cell[3 * i + 2], c);
+      op_l2p(p, exp_at(&T, T.Lc, L, box_lin(L, T.cell[3 * i], T.cell[3 * i + 1], T.cell[3 * i + 2])),
+             c, pos + 3 * i, &ff, gf);
+    }
+    phi_all[t] = fn + ff;
+    if (force)
+      for (int a = 0; a < 3; ++a) force[3 * t + a] = -q[i] * (gn[a] + gf[a]);
+  }
+  if (energy && !targets) {
+    ksum e = {0, 0};
+    for (int64_t i = 0; i < n; ++i) ksum_add(&e, q[i] * phi_all[i]);
+    *energy = 0.5 * ksum_val(&e);
+  }
+  free(phi_tmp);
+  free(need);
+  otree_free(&T);
+  return status;
+}
+
+/* Leaf cell (ix, iy, iz) of every particle, and the resolved cube. */
+int oracle_leaf_cells(int64_t n, const double *pos, int depth, const double lo_in[3],
+                      double side_in, int32_t *cells, double lo_out[3], double *side_out) {
+  if (n < 0 || !pos || depth < 0 || depth > ORACLE_LMAX) return ORACLE_E_INVALID_ARG;
+  double lo[3], side;
+  int st = resolve_cube(n, pos, lo_in, side_in, lo, &side);
+  if (st) return st;
+  for (int64_t i = 0; i < n; ++i)
+    for (int a = 0; a < 3; ++a) cells[3 * i + a] = leaf_cell_axis(pos[3 * i + a], lo[a], side, depth);
+  if (lo_out)
+    for (int a = 0; a < 3; ++a) lo_out[a] = lo[a];
+  if (side_out) *side_out = side;
+  return ORACLE_OK;
+}
+
+/* Operator chains for the single-operator pins.  Sources (ns points, charges
+ * q) are expanded about c1, then:
+ *   chain 0: M2P at x                          (P2M, M2P)
+ *   chain 1: M2M to c2, M2P at x               (P2M, M2M, M2P)
+ *   chain 2: M2L to c2, L2P at x               (P2M, M2L, L2P)
+ *   chain 3: M2L to c2, L2L to c3, L2P at x    (P2M, M2L, L2L, L2P)
+ * phi (nx) receives the potential, grad (nx x 3, may be NULL) the gradient
+ * (chains 2 and 3 only). */
+int oracle_chain(int chain, int p, int64_t ns, const double *src, const double *q,
+                 const double c1[3], const double c2[3], const double c3[3], int64_t nx,
+                 const double *x, double *phi, double *grad) {
+  if (p < 0 || p > ORACLE_PMAX || chain < 0 || chain > 3) return ORACLE_E_INVALID_ARG;
+  const int nh = nharm(p);
+  cplx *A = calloc(nh, sizeof(cplx)), *B = calloc(nh, sizeof(cplx)), *C = calloc(nh, sizeof(cplx));
+  if (!A || !B || !C) { free(A); free(B); free(C); return ORACLE_E_NOMEM; }
+  for (int64_t j = 0; j < ns; ++j) op_p2m(p, src + 3 * j, q[j], c1, A);
+  for (int64_t i = 0; i < nx; ++i) {
+    double g[3] = {0, 0, 0};
+    switch (chain) {
+      case 0: phi[i] = op_m2p(p, A, c1, x + 3 * i); break;
+      case 1:
+        if (i == 0) op_m2m(p, A, c1, c2, B);
+        phi[i] = op_m2p(p, B, c2, x + 3 * i);
+        break;
+      case 2:
+        if (i == 0) op_m2l(p, A, c1, c2, B);
+        op_l2p(p, B, c2, x + 3 * i, phi + i, g);
+        break;
+      case 3:
+        if (i == 0) {
+          op_m2l(p, A, c1, c2, B);
+          op_l2l(p, B, c2, c3, C);
+        }
+        op_l2p(p, C, c3, x + 3 * i, phi + i, g);
+        break;
+    }
+    if (grad)
+      for (int a = 0; a < 3; ++a) grad[3 * i + a] = g[a];
+  }
+  free(A);
+  free(B);
+  free(C);
+  return ORACLE_OK;
+}
