@@ -1,0 +1,188 @@
+/*
+ * fmm.h -- C ABI of libfmm.so, a fast multipole method (FMM) for the 3-D
+ * Coulomb / Laplace sum on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (the exact result the method approximates; open boundary, pure 1/r
+ * kernel with no Coulomb constant, i = j excluded, no softening):
+ *     phi_i = sum_{j != i} q_j / |x_i - x_j|
+ *     F_i   = -q_i grad phi_i = q_i sum_{j != i} q_j (x_i - x_j) / |x_i - x_j|^3
+ *     E     = 1/2 sum_i q_i phi_i
+ *
+ * Method: uniform octree of depth L (root = level 0) over a cube, boxes kept in
+ * Hilbert order; well-separatedness 1 (near list = 27 boxes at Chebyshev index
+ * distance <= 1; interaction list = children of the parent's near list that are
+ * not in the box's near list); multipole and local expansions of degree <= p
+ * about box centres with every (local degree <= p, multipole degree <= p) pair
+ * kept in the multipole-to-local (M2L) translation.  The passes are P2M, M2M
+ * (leaves up to level 2), M2L (levels 2..L), L2L (level 2 down to the leaves),
+ * L2P and the P2P near-field direct sum (Greengard, "The Rapid Evaluation of
+ * Potential Fields in Particle Systems", MIT Press 1988, ch. 3; Cheng, Greengard
+ * & Rokhlin, J. Comput. Phys. 155:468 (1999), sec. 2-3).
+ *
+ * Conventions shared by every call
+ *   - Memory: the caller owns every device buffer, the workspace included; the
+ *     library allocates no device memory.  It owns only the host-side plan
+ *     object, freed by fmm_destroy.  Input arrays are read-only.
+ *   - Layouts: positions are n x 3 row-major FP64 (x0 y0 z0 x1 ...); charges,
+ *     potentials n FP64; forces n x 3 row-major FP64; all in the caller's
+ *     ("user") particle order.  Pointers marked "device" must be device memory.
+ *   - Streams: every call that takes a hipStream_t only enqueues work on that
+ *     stream and returns; a plan must not be used from two streams at once.
+ *   - Determinism: every sum is taken in a fixed order (no floating-point
+ *     atomics), so repeated runs on the same inputs are bitwise identical.
+ *   - Errors: argument errors are detected on the host, returned at once and
+ *     leave every output untouched.  Errors found by kernels (a point outside a
+ *     given cube, a non-finite coordinate, two distinct particles at the same
+ *     point) raise a flag in the workspace; fmm_check waits for the stream and
+ *     reports it.  Outputs of a call whose flag is raised are unspecified (but
+ *     every kernel stays in bounds).  HIP runtime failures map to FMM_E_DEVICE.
+ *     No call aborts or throws.
+ */
+#ifndef FMM_H_
+#define FMM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FMM_ABI_VERSION 1
+#define FMM_P_MAX 12     /* largest expansion order */
+#define FMM_DEPTH_MAX 9  /* deepest uniform tree (8^9 leaves) */
+
+typedef struct ihipStream_t *fmm_stream_t; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  FMM_OK = 0,
+  FMM_E_INVALID_ARG = 1, /* a NULL pointer, size or config field out of range */
+  FMM_E_WORKSPACE = 2,   /* workspace NULL, misaligned (256 B) or too small */
+  FMM_E_OUT_OF_CUBE = 3, /* device: a position outside the given root cube */
+  FMM_E_NONFINITE = 4,   /* device: a non-finite coordinate */
+  FMM_E_COINCIDENT = 5,  /* device: two distinct particles at the same point */
+  FMM_E_UNSUPPORTED = 6, /* a valid request this build does not implement */
+  FMM_E_DEVICE = 7       /* a HIP runtime call failed */
+} fmm_status;
+
+typedef enum {
+  FMM_PREC_FP64 = 0,  /* every pass in FP64 */
+  FMM_PREC_MIXED = 1  /* P2M, M2L, L2P, P2P in FP32 (M2L on FP32 MFMA); M2M, L2L,
+                         the combination of results and the energy in FP64 */
+} fmm_precision;
+
+typedef enum {
+  FMM_M2L_AUTO = 0, /* FP64 MFMA for FMM_PREC_FP64, FP32 MFMA for FMM_PREC_MIXED */
+  FMM_M2L_F64 = 1,
+  FMM_M2L_F32 = 2
+} fmm_m2l_kind;
+
+typedef struct {
+  uint32_t abi_version; /* must equal FMM_ABI_VERSION */
+  int32_t p;            /* expansion order, 0..FMM_P_MAX */
+  int32_t depth;        /* leaf level L of the uniform tree, 0..FMM_DEPTH_MAX.
+                           L <= 1 has no well-separated pairs: the result is the
+                           direct sum. */
+  int32_t leaf_max;     /* reserved for adaptive trees; must be 0 */
+  int32_t ws;           /* well-separatedness; must be 1 */
+  int32_t precision;    /* fmm_precision */
+  int32_t m2l_kind;     /* fmm_m2l_kind; must agree with precision or be AUTO */
+  double root_lo[3];    /* root cube corner */
+  double root_side;     /* > 0: the cube [root_lo, root_lo + root_side]^3, which
+                           must contain every position (else FMM_E_OUT_OF_CUBE);
+                           <= 0: derived on the device as lo_a = min_i x_ia,
+                           side = max_a (max_i x_ia - lo_a), or 1 if that is 0 */
+} fmm_config;
+
+typedef struct fmm_plan_s fmm_plan_t; /* opaque */
+
+/* Fill *cfg with defaults: p = 8, depth = 3, ws = 1, FP64, unit cube at 0. */
+void fmm_config_default(fmm_config *cfg);
+
+/* Bytes of device workspace a plan for n particles under cfg needs.
+ * Pure host computation.  Errors: FMM_E_INVALID_ARG (cfg or bytes NULL, a field
+ * out of range, n < 1 or n > 2^31 - 1). */
+fmm_status fmm_workspace_size(const fmm_config *cfg, int64_t n, size_t *bytes);
+
+/* Build the tree for n particles at d_pos (device, n x 3 FP64, user order):
+ * quantise to leaf cells of the root cube, Hilbert keys, counting sort into
+ * Hilbert order (ties kept in user order), leaf ranges, per-level box maps,
+ * box-local coordinates, and the translation operators for order p.
+ * d_workspace (device, 256-byte aligned, >= fmm_workspace_size bytes) is owned
+ * by the caller and must stay valid and unused by others until fmm_destroy.
+ * On FMM_OK *out receives a new plan (host object); work is only enqueued.
+ * Errors: FMM_E_INVALID_ARG, FMM_E_WORKSPACE, FMM_E_DEVICE (nothing is
+ * enqueued and *out is left unchanged on any error). */
+fmm_status fmm_plan(const fmm_config *cfg, int64_t n, const double *d_pos, void *d_workspace,
+                    size_t workspace_bytes, fmm_stream_t stream, fmm_plan_t **out);
+
+/* Evaluate the FMM for charges d_q (device, n FP64, user order).  Any of
+ * d_phi (n), d_force (n x 3), d_energy (1 FP64) may be NULL; all are device
+ * pointers in user order.  The positions of the plan are those passed to
+ * fmm_plan.  Errors: FMM_E_INVALID_ARG (plan or d_q NULL), FMM_E_DEVICE. */
+fmm_status fmm_evaluate(fmm_plan_t *plan, const double *d_q, double *d_phi, double *d_force,
+                        double *d_energy, fmm_stream_t stream);
+
+/* Adjoint of the energy: given the upstream gradient d_grad_energy (device
+ * scalar g = dL/dE) and the charges of the last fmm_evaluate, write
+ * d_dE_dx = g dE/dx (n x 3) and d_dE_dq = g dE/dq (n), either may be NULL.
+ * Not implemented in this build: returns FMM_E_UNSUPPORTED. */
+fmm_status fmm_backward(fmm_plan_t *plan, const double *d_grad_energy, double *d_dE_dx,
+                        double *d_dE_dq, fmm_stream_t stream);
+
+/* Wait for the plan's last stream and report a device-detected error
+ * (FMM_E_OUT_OF_CUBE, FMM_E_NONFINITE, FMM_E_COINCIDENT) or FMM_OK. */
+fmm_status fmm_check(fmm_plan_t *plan);
+
+/* Free the host plan object (waits for its last stream first).  NULL is a no-op. */
+fmm_status fmm_destroy(fmm_plan_t *plan);
+
+/* Static text for a status code. */
+const char *fmm_status_string(fmm_status status);
+
+/* ---- introspection (tests and measurement) ------------------------------- */
+
+/* Leaf cell (ix, iy, iz) of every particle in user order (d_cells: device,
+ * n x 3 int32) and the Hilbert slot of its leaf (d_leaf: device, n uint32); either
+ * may be NULL.  Enqueued on stream.  Errors: FMM_E_INVALID_ARG, FMM_E_DEVICE. */
+fmm_status fmm_plan_leaves(fmm_plan_t *plan, int32_t *d_cells, uint32_t *d_leaf,
+                           fmm_stream_t stream);
+
+/* The resolved root cube (waits for the stream). */
+fmm_status fmm_plan_cube(fmm_plan_t *plan, double lo[3], double *side);
+
+/* 3-D Hilbert index (3 * bits bits) of cell (ix, iy, iz) on a 2^bits grid, the
+ * curve the library sorts by (Skilling, AIP Conf. Proc. 707:381 (2004)).  Host
+ * function; returns 0 for arguments out of range. */
+uint64_t fmm_hilbert_index(uint32_t ix, uint32_t iy, uint32_t iz, int32_t bits);
+
+/* Kernel-duration recording.  While enabled, the library records HIP events on
+ * the call's stream around each pass it launches.  fmm_profile_read waits for
+ * them, writes for each pass (FMM_PHASE_*) the summed duration in ms and the
+ * number of launches, and clears the record.  Capacity: 8192 launches between
+ * reads (later launches are not recorded). */
+enum {
+  FMM_PHASE_TREE = 0,   /* quantise, keys, count, scan, scatter, leaf sort, gather */
+  FMM_PHASE_OPERATORS,  /* translation-operator tables */
+  FMM_PHASE_P2M,
+  FMM_PHASE_M2M,
+  FMM_PHASE_M2L,
+  FMM_PHASE_L2L,
+  FMM_PHASE_L2P,
+  FMM_PHASE_P2P,        /* near field, combination, unpermute, energy partials */
+  FMM_PHASE_ENERGY,
+  FMM_PHASE_COUNT
+};
+fmm_status fmm_profile_enable(fmm_plan_t *plan, int enable);
+fmm_status fmm_profile_read(fmm_plan_t *plan, double ms[FMM_PHASE_COUNT],
+                            int32_t launches[FMM_PHASE_COUNT]);
+
+/* Algorithmic work of the plan's tree (after the stream has finished the
+ * plan): number of M2L (target, source) box pairs with both boxes non-empty,
+ * summed over levels 2..L, and number of ordered P2P particle pairs (i != j). */
+fmm_status fmm_plan_work(fmm_plan_t *plan, int64_t *m2l_pairs, int64_t *p2p_pairs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FMM_H_ */

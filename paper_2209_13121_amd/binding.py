@@ -1,0 +1,238 @@
+"""Python binding of libfmm.so (include/fmm.h): argument marshalling only.
+
+Every function here forwards to the C ABI function of the same name; device
+buffers are torch tensors on a HIP device, streams are torch streams.  No
+arithmetic of the method runs in Python, and there is no fallback: if the
+library is missing or fails to load, ``load()`` raises.
+
+``FMM`` is a small convenience owner of one workspace and one plan.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfmm.so")
+
+FMM_ABI_VERSION = 1
+FMM_P_MAX = 12
+FMM_DEPTH_MAX = 9
+FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
+FMM_M2L_AUTO, FMM_M2L_F64, FMM_M2L_F32 = 0, 1, 2
+STATUS_NAMES = {0: "FMM_OK", 1: "FMM_E_INVALID_ARG", 2: "FMM_E_WORKSPACE", 3: "FMM_E_OUT_OF_CUBE",
+                4: "FMM_E_NONFINITE", 5: "FMM_E_COINCIDENT", 6: "FMM_E_UNSUPPORTED",
+                7: "FMM_E_DEVICE"}
+PHASES = ["tree", "operators", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "energy"]
+
+# every symbol include/fmm.h declares
+EXPORTS = ["fmm_config_default", "fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_backward",
+           "fmm_check", "fmm_destroy", "fmm_status_string", "fmm_plan_leaves", "fmm_plan_cube",
+           "fmm_hilbert_index", "fmm_profile_enable", "fmm_profile_read", "fmm_plan_work"]
+
+
+class fmm_config(ctypes.Structure):
+    _fields_ = [("abi_version", ctypes.c_uint32), ("p", ctypes.c_int32), ("depth", ctypes.c_int32),
+                ("leaf_max", ctypes.c_int32), ("ws", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("m2l_kind", ctypes.c_int32),
+                ("root_lo", ctypes.c_double * 3), ("root_side", ctypes.c_double)]
+
+
+class FMMError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}")
+
+
+_LIB = None
+
+
+def load(path=LIB_PATH):
+    """Load libfmm.so (raises OSError when it is missing or unloadable).
+
+    torch is imported first so that the library binds to the HIP runtime torch
+    already mapped (torch ships its own libamdhip64 with the same soname);
+    loading the library first would map a second runtime, in which torch's
+    device pointers and streams are not valid."""
+    global _LIB
+    if _LIB is not None and path == LIB_PATH:
+        return _LIB
+    import torch  # noqa: F401  (see above)
+    if not os.path.exists(path):
+        raise OSError(f"{path} is not built; run paper_2209_13121_amd/build.py")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)
+    cfgp = ctypes.POINTER(fmm_config)
+    lib.fmm_config_default.argtypes = [cfgp]
+    lib.fmm_config_default.restype = None
+    lib.fmm_workspace_size.argtypes = [cfgp, i64, ctypes.POINTER(ctypes.c_size_t)]
+    lib.fmm_plan.argtypes = [cfgp, i64, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    lib.fmm_evaluate.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.fmm_backward.argtypes = [vp, vp, vp, vp, vp]
+    lib.fmm_check.argtypes = [vp]
+    lib.fmm_destroy.argtypes = [vp]
+    lib.fmm_status_string.argtypes = [ctypes.c_int]
+    lib.fmm_status_string.restype = ctypes.c_char_p
+    lib.fmm_plan_leaves.argtypes = [vp, vp, vp, vp]
+    lib.fmm_plan_cube.argtypes = [vp, dp, dp]
+    lib.fmm_hilbert_index.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, i32]
+    lib.fmm_hilbert_index.restype = ctypes.c_uint64
+    lib.fmm_profile_enable.argtypes = [vp, ctypes.c_int]
+    lib.fmm_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32)]
+    lib.fmm_plan_work.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    for name in EXPORTS:
+        f = getattr(lib, name)
+        if f.restype is ctypes.c_int or name in ("fmm_workspace_size", "fmm_plan", "fmm_evaluate",
+                                                 "fmm_backward", "fmm_check", "fmm_destroy",
+                                                 "fmm_plan_leaves", "fmm_plan_cube",
+                                                 "fmm_profile_enable", "fmm_profile_read",
+                                                 "fmm_plan_work"):
+            f.restype = ctypes.c_int
+    if path == LIB_PATH:
+        _LIB = lib
+    return lib
+
+
+def _check(st, what):
+    if st != 0:
+        raise FMMError(st, what)
+
+
+def make_config(p=8, depth=3, precision=FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
+                m2l_kind=FMM_M2L_AUTO):
+    cfg = fmm_config()
+    load().fmm_config_default(ctypes.byref(cfg))
+    cfg.p, cfg.depth, cfg.precision, cfg.m2l_kind = p, depth, precision, m2l_kind
+    for a in range(3):
+        cfg.root_lo[a] = float(lo[a])
+    cfg.root_side = float(side)
+    return cfg
+
+
+def fmm_workspace_size(cfg, n):
+    out = ctypes.c_size_t(0)
+    _check(load().fmm_workspace_size(ctypes.byref(cfg), int(n), ctypes.byref(out)),
+           "fmm_workspace_size")
+    return out.value
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _require(t, name, dtype, numel):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()
+            and t.numel() == numel):
+        raise ValueError(f"{name} must be a contiguous {dtype} device tensor with {numel} elements")
+
+
+def fmm_plan(cfg, n, pos, workspace, stream=None):
+    """pos: (n, 3) float64 device tensor; workspace: uint8 device tensor."""
+    import torch
+    _require(pos, "pos", torch.float64, 3 * n)
+    plan = ctypes.c_void_p()
+    _check(load().fmm_plan(ctypes.byref(cfg), int(n), _ptr(pos), _ptr(workspace),
+                           workspace.numel(), _stream_handle(stream), ctypes.byref(plan)),
+           "fmm_plan")
+    return plan
+
+
+def fmm_evaluate(plan, q, phi=None, force=None, energy=None, stream=None):
+    _check(load().fmm_evaluate(plan, _ptr(q), _ptr(phi), _ptr(force), _ptr(energy),
+                               _stream_handle(stream)), "fmm_evaluate")
+
+
+def fmm_backward(plan, grad_energy, dE_dx=None, dE_dq=None, stream=None):
+    _check(load().fmm_backward(plan, _ptr(grad_energy), _ptr(dE_dx), _ptr(dE_dq),
+                               _stream_handle(stream)), "fmm_backward")
+
+
+def fmm_check(plan):
+    return load().fmm_check(plan)
+
+
+def fmm_destroy(plan):
+    _check(load().fmm_destroy(plan), "fmm_destroy")
+
+
+def fmm_status_string(status):
+    return load().fmm_status_string(int(status)).decode()
+
+
+def fmm_plan_leaves(plan, cells=None, leaf=None, stream=None):
+    _check(load().fmm_plan_leaves(plan, _ptr(cells), _ptr(leaf), _stream_handle(stream)),
+           "fmm_plan_leaves")
+
+
+def fmm_plan_cube(plan):
+    lo = (ctypes.c_double * 3)()
+    side = ctypes.c_double()
+    _check(load().fmm_plan_cube(plan, lo, ctypes.byref(side)), "fmm_plan_cube")
+    return list(lo), side.value
+
+
+def fmm_hilbert_index(ix, iy, iz, bits):
+    return int(load().fmm_hilbert_index(ix, iy, iz, bits))
+
+
+def fmm_profile_enable(plan, on=True):
+    _check(load().fmm_profile_enable(plan, 1 if on else 0), "fmm_profile_enable")
+
+
+def fmm_profile_read(plan):
+    ms = (ctypes.c_double * len(PHASES))()
+    cnt = (ctypes.c_int32 * len(PHASES))()
+    _check(load().fmm_profile_read(plan, ms, cnt), "fmm_profile_read")
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(PHASES)}
+
+
+def fmm_plan_work(plan):
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().fmm_plan_work(plan, ctypes.byref(a), ctypes.byref(b)), "fmm_plan_work")
+    return a.value, b.value
+
+
+class FMM:
+    """Owns a workspace and a plan for one position set (torch device tensors)."""
+
+    def __init__(self, pos, p=8, depth=3, precision=FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
+                 stream=None, workspace=None):
+        import torch
+        self.n = pos.shape[0]
+        self.cfg = make_config(p, depth, precision, lo, side)
+        nbytes = fmm_workspace_size(self.cfg, self.n)
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=pos.device)
+        off = (-workspace.data_ptr()) % 256
+        self.workspace = workspace
+        self._ws = workspace[off:off + nbytes]
+        self.pos = pos
+        self.plan = fmm_plan(self.cfg, self.n, pos, self._ws, stream)
+
+    def evaluate(self, q, want_phi=True, want_force=True, want_energy=True, stream=None):
+        import torch
+        dev = q.device
+        phi = torch.empty(self.n, dtype=torch.float64, device=dev) if want_phi else None
+        force = torch.empty((self.n, 3), dtype=torch.float64, device=dev) if want_force else None
+        energy = torch.empty(1, dtype=torch.float64, device=dev) if want_energy else None
+        fmm_evaluate(self.plan, q, phi, force, energy, stream)
+        return phi, force, energy
+
+    def check(self):
+        return fmm_check(self.plan)
+
+    def close(self):
+        if self.plan is not None:
+            fmm_destroy(self.plan)
+            self.plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

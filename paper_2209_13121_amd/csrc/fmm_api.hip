@@ -1,0 +1,317 @@
+// fmm_api.hip -- the C ABI of libfmm.so: argument validation, workspace
+// layout, plan lifetime, pass sequencing and kernel-duration recording.
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
+  memset(lay, 0, sizeof(*lay));
+  const int L = cfg.depth, p = cfg.p, nc = ncoef(p);
+  const bool mixed = cfg.precision == FMM_PREC_MIXED;
+  lay->n = n;
+  lay->nleaf = (int64_t)1 << (3 * L);
+  int64_t off = 0;
+  for (int l = 0; l <= L; ++l) {
+    lay->lvl_off[l] = off;
+    off += (int64_t)1 << (3 * l);
+  }
+  lay->lvl_off[L + 1] = off;
+  lay->nbox = off;
+  lay->n_energy_part = (n + kBlock - 1) / kBlock;
+  // scan scratch: block sums of every level of the recursive scan
+  int64_t tmp = 0, m = lay->nleaf + 1;
+  while (m > 1) {
+    m = (m + 1023) / 1024;
+    tmp += m;
+  }
+  lay->scan_tmp_elems = tmp + 1;
+
+  size_t cur = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = cur;
+    cur = align256(cur + (bytes ? bytes : 1));
+    return at;
+  };
+  const size_t N = (size_t)n, NB = (size_t)lay->nbox, NL = (size_t)lay->nleaf;
+  lay->params = take(sizeof(DevParams));
+  lay->flags = take(sizeof(int32_t) * 4);
+  lay->energy_part = take(sizeof(double) * (size_t)lay->n_energy_part);
+  lay->bbox = take(sizeof(double) * 6 * 1024);
+  lay->keys = take(sizeof(uint32_t) * N);
+  lay->perm = take(sizeof(int32_t) * N);
+  lay->perm_tmp = take(sizeof(int32_t) * N);
+  lay->sorted_leaf = take(sizeof(uint32_t) * N);
+  lay->leaf_count = take(sizeof(uint32_t) * NL);
+  lay->leaf_start = take(sizeof(uint32_t) * (NL + 1));
+  lay->leaf_fill = take(sizeof(uint32_t) * NL);
+  lay->scan_tmp = take(sizeof(uint32_t) * (size_t)lay->scan_tmp_elems);
+  lay->coord2slot = take(sizeof(uint32_t) * NB);
+  lay->slot2coord = take(sizeof(uint32_t) * NB);
+  lay->loc64 = take(sizeof(double) * 3 * N);
+  lay->loc32 = mixed ? take(sizeof(float) * 3 * N) : 0;
+  lay->q64 = take(sizeof(double) * N);
+  lay->q32 = mixed ? take(sizeof(float) * N) : 0;
+  lay->far_phi = take(sizeof(double) * N);
+  lay->far_grad = take(sizeof(double) * 3 * N);
+  const size_t nce = (size_t)nc;
+  if (L >= 2) {
+    lay->mult64 = take(sizeof(double) * NB * nce);
+    lay->mult32 = mixed ? take(sizeof(float) * NB * nce) : 0;
+    lay->m2l_out = take((mixed ? sizeof(float) : sizeof(double)) * NB * nce);
+    lay->loc_exp64 = take(sizeof(double) * NB * nce);
+    lay->leaf_loc32 = mixed ? take(sizeof(float) * NL * nce) : 0;
+    lay->op_m2m = take(sizeof(double) * 8 * nce * nce);
+    lay->op_l2l = take(sizeof(double) * 8 * nce * nce);
+    const size_t opsz = (size_t)kNumM2LOps * m2l_k_pad(p) * m2l_rows_pad(p);
+    lay->op_m2l64 = mixed ? 0 : take(sizeof(double) * opsz);
+    lay->op_m2l32 = mixed ? take(sizeof(float) * opsz) : 0;
+  }
+  lay->work = take(sizeof(int64_t) * 2);
+  lay->total = cur;
+  return true;
+}
+
+static inline fmm_status from_hip(hipError_t e) { return e == hipSuccess ? FMM_OK : FMM_E_DEVICE; }
+
+void prof_begin(fmm_plan_s* P, int phase, hipStream_t s) {
+  if (!P->profile || P->nrec >= kMaxProfile) return;
+  ProfileRec& r = P->rec[P->nrec];
+  if (P->nrec >= P->nevents_created) {
+    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
+    P->nevents_created = P->nrec + 1;
+  }
+  r.phase = phase;
+  hipEventRecord(r.start, s);
+}
+
+void prof_end(fmm_plan_s* P, hipStream_t s) {
+  if (!P->profile || P->nrec >= kMaxProfile || P->nrec >= P->nevents_created) return;
+  hipEventRecord(P->rec[P->nrec].stop, s);
+  P->nrec++;
+}
+
+static fmm_status validate_config(const fmm_config* cfg) {
+  if (!cfg) return FMM_E_INVALID_ARG;
+  if (cfg->abi_version != FMM_ABI_VERSION) return FMM_E_INVALID_ARG;
+  if (cfg->p < 0 || cfg->p > FMM_P_MAX) return FMM_E_INVALID_ARG;
+  if (cfg->depth < 0 || cfg->depth > FMM_DEPTH_MAX) return FMM_E_INVALID_ARG;
+  if (cfg->ws != 1) return FMM_E_INVALID_ARG;
+  if (cfg->leaf_max != 0) return FMM_E_UNSUPPORTED;
+  if (cfg->precision != FMM_PREC_FP64 && cfg->precision != FMM_PREC_MIXED) return FMM_E_INVALID_ARG;
+  if (cfg->m2l_kind < FMM_M2L_AUTO || cfg->m2l_kind > FMM_M2L_F32) return FMM_E_INVALID_ARG;
+  if (cfg->m2l_kind == FMM_M2L_F64 && cfg->precision != FMM_PREC_FP64) return FMM_E_UNSUPPORTED;
+  if (cfg->m2l_kind == FMM_M2L_F32 && cfg->precision != FMM_PREC_MIXED) return FMM_E_UNSUPPORTED;
+  for (int a = 0; a < 3; ++a)
+    if (!(cfg->root_lo[a] == cfg->root_lo[a]) || cfg->root_lo[a] - cfg->root_lo[a] != 0.0)
+      return FMM_E_INVALID_ARG;  // NaN or infinite corner
+  if (!(cfg->root_side == cfg->root_side) || cfg->root_side - cfg->root_side != 0.0)
+    return FMM_E_INVALID_ARG;
+  return FMM_OK;
+}
+
+}  // namespace fmm
+
+using namespace fmm;
+
+extern "C" {
+
+void fmm_config_default(fmm_config* cfg) {
+  if (!cfg) return;
+  memset(cfg, 0, sizeof(*cfg));
+  cfg->abi_version = FMM_ABI_VERSION;
+  cfg->p = 8;
+  cfg->depth = 3;
+  cfg->ws = 1;
+  cfg->precision = FMM_PREC_FP64;
+  cfg->m2l_kind = FMM_M2L_AUTO;
+  cfg->root_side = 1.0;
+}
+
+fmm_status fmm_workspace_size(const fmm_config* cfg, int64_t n, size_t* bytes) {
+  if (!bytes) return FMM_E_INVALID_ARG;
+  fmm_status st = validate_config(cfg);
+  if (st != FMM_OK) return st;
+  if (n < 1 || n > INT32_MAX) return FMM_E_INVALID_ARG;
+  Layout lay;
+  make_layout(*cfg, n, &lay);
+  *bytes = lay.total;
+  return FMM_OK;
+}
+
+fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void* d_workspace,
+                    size_t workspace_bytes, fmm_stream_t stream, fmm_plan_t** out) {
+  fmm_status st = validate_config(cfg);
+  if (st != FMM_OK) return st;
+  if (!out || !d_pos || n < 1 || n > INT32_MAX) return FMM_E_INVALID_ARG;
+  if (!d_workspace || ((uintptr_t)d_workspace & 255u)) return FMM_E_WORKSPACE;
+  Layout lay;
+  make_layout(*cfg, n, &lay);
+  if (workspace_bytes < lay.total) return FMM_E_WORKSPACE;
+
+  fmm_plan_s* P = new (std::nothrow) fmm_plan_s;
+  if (!P) return FMM_E_DEVICE;
+  memset(P, 0, sizeof(*P));
+  P->cfg = *cfg;
+  P->lay = lay;
+  P->n = n;
+  P->L = cfg->depth;
+  P->p = cfg->p;
+  P->nc = ncoef(cfg->p);
+  P->mixed = cfg->precision == FMM_PREC_MIXED;
+  P->ws = static_cast<char*>(d_workspace);
+  P->last_stream = reinterpret_cast<hipStream_t>(stream);
+  P->rec = static_cast<ProfileRec*>(calloc(kMaxProfile, sizeof(ProfileRec)));
+  if (!P->rec) {
+    delete P;
+    return FMM_E_DEVICE;
+  }
+  hipStream_t s = P->last_stream;
+  hipError_t e = launch_tree(P, d_pos, s);
+  if (e == hipSuccess && P->L >= 2) e = launch_operators(P, s);
+  if (e != hipSuccess) {
+    free(P->rec);
+    delete P;
+    return FMM_E_DEVICE;
+  }
+  *out = P;
+  return FMM_OK;
+}
+
+fmm_status fmm_evaluate(fmm_plan_t* P, const double* d_q, double* d_phi, double* d_force,
+                        double* d_energy, fmm_stream_t stream) {
+  if (!P || !d_q) return FMM_E_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  P->last_stream = s;
+  hipError_t e = launch_upward(P, d_q, s);
+  if (e == hipSuccess && P->L >= 2) e = launch_m2l(P, s);
+  if (e == hipSuccess && P->L >= 2) e = launch_downward(P, s);
+  if (e == hipSuccess) e = launch_near_and_finish(P, d_phi, d_force, d_energy, s);
+  return from_hip(e);
+}
+
+fmm_status fmm_backward(fmm_plan_t* P, const double* d_grad_energy, double* d_dE_dx,
+                        double* d_dE_dq, fmm_stream_t stream) {
+  (void)d_grad_energy;
+  (void)d_dE_dx;
+  (void)d_dE_dq;
+  (void)stream;
+  if (!P) return FMM_E_INVALID_ARG;
+  return FMM_E_UNSUPPORTED;
+}
+
+fmm_status fmm_check(fmm_plan_t* P) {
+  if (!P) return FMM_E_INVALID_ARG;
+  if (hipStreamSynchronize(P->last_stream) != hipSuccess) return FMM_E_DEVICE;
+  int32_t flags = 0;
+  if (hipMemcpy(&flags, P->ws + P->lay.flags, sizeof(flags), hipMemcpyDeviceToHost) != hipSuccess)
+    return FMM_E_DEVICE;
+  if (flags & kFlagNonFinite) return FMM_E_NONFINITE;
+  if (flags & kFlagOutOfCube) return FMM_E_OUT_OF_CUBE;
+  if (flags & kFlagCoincident) return FMM_E_COINCIDENT;
+  return FMM_OK;
+}
+
+fmm_status fmm_destroy(fmm_plan_t* P) {
+  if (!P) return FMM_OK;
+  fmm_status st = FMM_OK;
+  if (hipStreamSynchronize(P->last_stream) != hipSuccess) st = FMM_E_DEVICE;
+  for (int i = 0; i < P->nevents_created; ++i) {
+    hipEventDestroy(P->rec[i].start);
+    hipEventDestroy(P->rec[i].stop);
+  }
+  free(P->rec);
+  delete P;
+  return st;
+}
+
+const char* fmm_status_string(fmm_status st) {
+  switch (st) {
+    case FMM_OK: return "ok";
+    case FMM_E_INVALID_ARG: return "invalid argument";
+    case FMM_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case FMM_E_OUT_OF_CUBE: return "a position lies outside the given root cube";
+    case FMM_E_NONFINITE: return "a coordinate is not finite";
+    case FMM_E_COINCIDENT: return "two distinct particles share a position";
+    case FMM_E_UNSUPPORTED: return "not supported by this build";
+    case FMM_E_DEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+fmm_status fmm_plan_leaves(fmm_plan_t* P, int32_t* d_cells, uint32_t* d_leaf, fmm_stream_t stream) {
+  if (!P) return FMM_E_INVALID_ARG;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  P->last_stream = s;
+  return from_hip(launch_leaves_out(P, d_cells, d_leaf, s));
+}
+
+fmm_status fmm_plan_cube(fmm_plan_t* P, double lo[3], double* side) {
+  if (!P || !lo || !side) return FMM_E_INVALID_ARG;
+  if (hipStreamSynchronize(P->last_stream) != hipSuccess) return FMM_E_DEVICE;
+  DevParams dp;
+  if (hipMemcpy(&dp, P->ws + P->lay.params, sizeof(dp), hipMemcpyDeviceToHost) != hipSuccess)
+    return FMM_E_DEVICE;
+  for (int a = 0; a < 3; ++a) lo[a] = dp.lo[a];
+  *side = dp.side;
+  return FMM_OK;
+}
+
+uint64_t fmm_hilbert_index(uint32_t ix, uint32_t iy, uint32_t iz, int32_t bits) {
+  if (bits < 0 || bits > 21) return 0;
+  if (bits < 32 && (ix >> bits || iy >> bits || iz >> bits)) return 0;
+  return hilbert_index(ix, iy, iz, bits);
+}
+
+fmm_status fmm_profile_enable(fmm_plan_t* P, int enable) {
+  if (!P) return FMM_E_INVALID_ARG;
+  P->profile = enable != 0;
+  return FMM_OK;
+}
+
+fmm_status fmm_profile_read(fmm_plan_t* P, double ms[FMM_PHASE_COUNT],
+                            int32_t launches[FMM_PHASE_COUNT]) {
+  if (!P || !ms || !launches) return FMM_E_INVALID_ARG;
+  for (int i = 0; i < FMM_PHASE_COUNT; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  fmm_status st = FMM_OK;
+  for (int i = 0; i < P->nrec; ++i) {
+    const ProfileRec& r = P->rec[i];
+    if (hipEventSynchronize(r.stop) != hipSuccess) {
+      st = FMM_E_DEVICE;
+      break;
+    }
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, r.start, r.stop) != hipSuccess) {
+      st = FMM_E_DEVICE;
+      break;
+    }
+    ms[r.phase] += t;
+    launches[r.phase] += 1;
+  }
+  P->nrec = 0;
+  return st;
+}
+
+fmm_status fmm_plan_work(fmm_plan_t* P, int64_t* m2l_pairs, int64_t* p2p_pairs) {
+  if (!P || !m2l_pairs || !p2p_pairs) return FMM_E_INVALID_ARG;
+  hipStream_t s = P->last_stream;
+  if (launch_work_count(P, s) != hipSuccess) return FMM_E_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return FMM_E_DEVICE;
+  int64_t w[2];
+  if (hipMemcpy(w, P->ws + P->lay.work, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess)
+    return FMM_E_DEVICE;
+  *m2l_pairs = w[0];
+  *p2p_pairs = w[1];
+  return FMM_OK;
+}
+
+}  // extern "C"

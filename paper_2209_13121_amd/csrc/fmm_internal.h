@@ -1,0 +1,240 @@
+// fmm_internal.h -- plan object, workspace layout and device helpers shared by
+// the library's HIP sources.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fmm.h"
+
+namespace fmm {
+
+constexpr int kBlock = 256;          // default work-group size (4 wave64)
+constexpr int kNumM2LOps = 316;      // offsets in [-3,3]^3 \ [-1,1]^3
+constexpr int kIL = 189;             // interaction-list offsets per parity class
+constexpr int kMaxProfile = 8192;    // recorded launches between profile reads
+
+// Error bits raised by kernels (atomicOr into Plan::d_flags).
+enum : int32_t { kFlagOutOfCube = 1, kFlagNonFinite = 2, kFlagCoincident = 4 };
+
+// Device-resident parameters of a plan (written by kernels, so that a derived
+// cube never needs a host round trip).
+struct DevParams {
+  double lo[3];
+  double side;
+};
+
+inline int ncoef(int p) { return (p + 1) * (p + 1); }
+// M2L operator tile sizes: rows padded to 16-row MFMA blocks, K to 4-deep steps.
+inline int m2l_rows_pad(int p) { return ((ncoef(p) + 15) / 16) * 16; }
+inline int m2l_k_pad(int p) { return ((ncoef(p) + 3) / 4) * 4; }
+
+struct Layout {  // byte offsets into the workspace, every one 256-aligned
+  size_t params, flags, energy_part, bbox;
+  size_t keys, perm, perm_tmp, sorted_leaf;
+  size_t leaf_count, leaf_start, leaf_fill, scan_tmp;
+  size_t coord2slot, slot2coord;
+  size_t loc64, loc32;     // box-unit local coordinates, SoA x | y | z
+  size_t q64, q32;         // sorted charges
+  size_t far_phi, far_grad;  // far-field results per sorted particle (FP64)
+  size_t mult64, mult32;   // multipole expansions, all levels
+  size_t m2l_out;          // M2L results, all levels (compute precision)
+  size_t loc_exp64;        // local expansions FP64, all levels
+  size_t leaf_loc32;       // leaf local expansions FP32 (mixed)
+  size_t op_m2m, op_l2l;   // 8 x ncoef x ncoef FP64 each
+  size_t op_m2l64, op_m2l32;
+  size_t work;             // 2 x int64 counters
+  size_t total;
+  int64_t n, nleaf, nbox, n_energy_part, scan_tmp_elems;
+  int64_t lvl_off[FMM_DEPTH_MAX + 2];
+};
+
+bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay);
+
+struct ProfileRec {
+  int phase;
+  hipEvent_t start, stop;
+};
+
+}  // namespace fmm
+
+struct fmm_plan_s {
+  fmm_config cfg;
+  fmm::Layout lay;
+  int64_t n;
+  int L, p, nc;
+  bool mixed;
+  char* ws;
+  hipStream_t last_stream;
+  // profiling
+  bool profile;
+  int nrec;
+  fmm::ProfileRec* rec;  // kMaxProfile entries, events created lazily
+  int nevents_created;
+};
+
+namespace fmm {
+
+template <typename T>
+inline T* wsp(fmm_plan_s* P, size_t off) {
+  return reinterpret_cast<T*>(P->ws + off);
+}
+
+// ---- launch helpers (defined in fmm_api.hip) -------------------------------
+void prof_begin(fmm_plan_s* P, int phase, hipStream_t s);
+void prof_end(fmm_plan_s* P, hipStream_t s);
+
+// ---- passes (each file defines its launchers) ------------------------------
+hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s);
+hipError_t launch_operators(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_upward(fmm_plan_s* P, const double* d_q, hipStream_t s);
+hipError_t launch_m2l(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_downward(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
+                                  double* d_energy, hipStream_t s);
+hipError_t launch_leaves_out(fmm_plan_s* P, int32_t* d_cells, uint32_t* d_leaf, hipStream_t s);
+hipError_t launch_work_count(fmm_plan_s* P, hipStream_t s);
+
+// ---- device helpers --------------------------------------------------------
+
+// 3-D Hilbert index of cell (x, y, z) on a 2^bits grid: Skilling's transpose
+// method (AIP Conf. Proc. 707:381, 2004) -- undo excess work from the top bit
+// down, Gray-encode, then interleave the transposed bits, most significant
+// first, in the order x, y, z.
+__host__ __device__ inline uint64_t hilbert_index(uint32_t x, uint32_t y, uint32_t z, int bits) {
+  if (bits <= 0) return 0;
+  uint32_t X[3] = {x, y, z};
+  const uint32_t top = 1u << (bits - 1);
+  for (uint32_t Q = top; Q > 1; Q >>= 1) {
+    const uint32_t Pm = Q - 1;
+    for (int i = 0; i < 3; ++i) {
+      if (X[i] & Q) {
+        X[0] ^= Pm;
+      } else {
+        const uint32_t t = (X[0] ^ X[i]) & Pm;
+        X[0] ^= t;
+        X[i] ^= t;
+      }
+    }
+  }
+  X[1] ^= X[0];
+  X[2] ^= X[1];
+  uint32_t t = 0;
+  for (uint32_t Q = top; Q > 1; Q >>= 1)
+    if (X[2] & Q) t ^= Q - 1;
+  X[0] ^= t;
+  X[1] ^= t;
+  X[2] ^= t;
+  uint64_t h = 0;
+  for (int b = bits - 1; b >= 0; --b)
+    for (int i = 0; i < 3; ++i) h = (h << 1) | ((X[i] >> b) & 1u);
+  return h;
+}
+
+__host__ __device__ inline uint32_t pack_coord(uint32_t x, uint32_t y, uint32_t z) {
+  return (x << 20) | (y << 10) | z;
+}
+__host__ __device__ inline void unpack_coord(uint32_t c, int& x, int& y, int& z) {
+  x = (int)(c >> 20);
+  y = (int)((c >> 10) & 1023u);
+  z = (int)(c & 1023u);
+}
+__host__ __device__ inline int64_t lex_index(int x, int y, int z, int l) {
+  return ((int64_t)x << (2 * l)) | ((int64_t)y << l) | (int64_t)z;
+}
+
+// Real packing of the coefficients of a real-valued expansion: degree n owns
+// entries n^2 .. n^2 + 2n as [Re c_n^0, Re c_n^1, Im c_n^1, ..., Re c_n^n, Im c_n^n];
+// negative orders follow from c_n^{-m} = (-1)^m conj(c_n^m).
+__host__ __device__ constexpr int cidx_re(int n, int m) { return m == 0 ? n * n : n * n + 2 * m - 1; }
+__host__ __device__ constexpr int cidx_im(int n, int m) { return n * n + 2 * m; }
+__host__ __device__ constexpr int tri(int n, int m) { return n * (n + 1) / 2 + m; }
+
+// Regular solid harmonics R_n^m(x) = r^n P_n^m(cos t) e^{i m f} / (n+m)!
+// (Condon-Shortley phase) for 0 <= m <= n <= P, by the three-term recurrences
+//   R_m^m = -(x + i y)/(2m) R_{m-1}^{m-1},  R_{m+1}^m = z R_m^m,
+//   (n-m)(n+m) R_n^m = (2n-1) z R_{n-1}^m - r^2 R_{n-2}^m.
+// Outputs are indexed by tri(n, m).
+template <int P, typename T>
+__device__ __forceinline__ void regular_harmonics(T x, T y, T z, T* re, T* im) {
+  const T r2 = x * x + y * y + z * z;
+  re[0] = T(1);
+  im[0] = T(0);
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    if (m > 0) {
+      const T s = T(-1.0 / (2.0 * m));
+      const T pr = re[tri(m - 1, m - 1)], pi = im[tri(m - 1, m - 1)];
+      re[tri(m, m)] = s * (x * pr - y * pi);
+      im[tri(m, m)] = s * (x * pi + y * pr);
+    }
+    if (m + 1 <= P) {
+      re[tri(m + 1, m)] = z * re[tri(m, m)];
+      im[tri(m + 1, m)] = z * im[tri(m, m)];
+    }
+#pragma unroll
+    for (int n = m + 2; n <= P; ++n) {
+      const T a = T((2.0 * n - 1.0) / ((double)(n - m) * (double)(n + m)));
+      const T b = T(1.0 / ((double)(n - m) * (double)(n + m)));
+      re[tri(n, m)] = a * z * re[tri(n - 1, m)] - b * r2 * re[tri(n - 2, m)];
+      im[tri(n, m)] = a * z * im[tri(n - 1, m)] - b * r2 * im[tri(n - 2, m)];
+    }
+  }
+}
+
+// M2L operators are numbered lexicographically over the offsets o in
+// [-3,3]^3 with max |o_a| >= 2 (the 316 possible target-minus-source offsets of
+// interaction-list boxes).
+__host__ __device__ inline void m2l_offset(int op, int o[3]) {
+  int idx = 0;
+  for (int a = -3; a <= 3; ++a)
+    for (int b = -3; b <= 3; ++b)
+      for (int c = -3; c <= 3; ++c) {
+        if (a >= -1 && a <= 1 && b >= -1 && b <= 1 && c >= -1 && c <= 1) continue;
+        if (idx == op) {
+          o[0] = a;
+          o[1] = b;
+          o[2] = c;
+        }
+        ++idx;
+      }
+}
+
+__host__ __device__ constexpr int clamp03(int v) { return v < 0 ? 0 : (v > 3 ? 3 : v); }
+
+// Inverse of m2l_offset: lexicographic position in [-3,3]^3 minus the number
+// of inner ([-1,1]^3) offsets that precede it.
+__host__ __device__ inline int m2l_op_index(int ox, int oy, int oz) {
+  const int a = ox + 3, b = oy + 3, c = oz + 3;
+  int before = 9 * clamp03(a - 2);
+  if (a >= 2 && a <= 4) {
+    before += 3 * clamp03(b - 2);
+    if (b >= 2 && b <= 4) before += clamp03(c - 2);
+  }
+  return a * 49 + b * 7 + c - before;
+}
+
+// Dispatch a templated functor on the expansion order p (0..FMM_P_MAX).
+template <template <int> class F, typename... Args>
+inline hipError_t dispatch_p(int p, Args&&... args) {
+  switch (p) {
+    case 0: return F<0>::run(args...);
+    case 1: return F<1>::run(args...);
+    case 2: return F<2>::run(args...);
+    case 3: return F<3>::run(args...);
+    case 4: return F<4>::run(args...);
+    case 5: return F<5>::run(args...);
+    case 6: return F<6>::run(args...);
+    case 7: return F<7>::run(args...);
+    case 8: return F<8>::run(args...);
+    case 9: return F<9>::run(args...);
+    case 10: return F<10>::run(args...);
+    case 11: return F<11>::run(args...);
+    case 12: return F<12>::run(args...);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+inline unsigned grid_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
+
+}  // namespace fmm

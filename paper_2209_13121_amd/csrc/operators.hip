@@ -1,0 +1,211 @@
+// operators.hip -- translation operators as dense real matrices.
+//
+// Expansions are kept in box-scaled form: at level l with box side h,
+//   multipole  M~_n^m = sum_j q_j conj(R_n^m((y_j - c)/h))
+//   local      phi(c + u) = sum L~_k^l R_k^l(u/h)
+// with the regular / irregular solid harmonics
+//   R_n^m = r^n P_n^m(cos t) e^{imf} / (n+m)!,   I_n^m = (n-m)! P_n^m(cos t) e^{imf} / r^{n+1}
+// (Epton & Dembart, SIAM J. Sci. Comput. 16:865 (1995)), whose addition
+// theorems give, after the scaling, translations that do not depend on the
+// level:
+//   M2M  M~p_n^m = sum_{k<=n,l} 2^{-k} M~c_k^l conj(R_{n-k}^{m-l}(w))
+//   L2L  L~c_j^i = sum_{k>=j,l} 2^{-j} L~p_k^l R_{k-j}^{l-i}(w)
+//   M2L  L~t_k^l = (1/h) (-1)^{k+l} sum_{n,m} M~s_n^m I_{n+k}^{m-l}(o)
+// where w = (c_child - c_parent)/h_parent = (+-1/4, +-1/4, +-1/4) and o is the
+// integer offset (c_t - c_s)/h.  Summing over m = -n..n with the real-charge
+// symmetry c^{-m} = (-1)^m conj(c^m) turns each translation into a real matrix
+// acting on the packed real coefficient vector (fmm_internal.h).  The 1/h of
+// M2L is applied when its result is promoted (L2L pass).
+//
+// Tables: M2M and L2L, 8 octants each, stored [octant][input k][output row]
+// (FP64); M2L, 316 offsets, stored [offset][input k (padded to KP)][output row
+// (padded to RP)], zero padded, in the M2L precision.
+#include "fmm_internal.h"
+
+namespace fmm {
+namespace {
+
+struct Cd {
+  double re, im;
+};
+
+// Entry of a real matrix from the two complex coefficients X1 (order m - l
+// partner) and X2 (the partner of the negative input order), given the packed
+// positions of input and output.
+__host__ __device__ inline double real_entry(int in_m, bool in_im, bool out_im, Cd X1, Cd X2) {
+  if (in_m == 0) return out_im ? X1.im : X1.re;
+  const double sg = (in_m & 1) ? -1.0 : 1.0;
+  if (!in_im) {
+    const Cd c = {X1.re + sg * X2.re, X1.im + sg * X2.im};
+    return out_im ? c.im : c.re;
+  }
+  const Cd d = {X1.re - sg * X2.re, X1.im - sg * X2.im};
+  return out_im ? d.re : -d.im;  // coefficient of i * b
+}
+
+__host__ __device__ inline void unpack_index(int c, int& n, int& m, bool& is_im) {
+  n = 0;
+  while ((n + 1) * (n + 1) <= c) ++n;
+  const int r = c - n * n;
+  m = (r + 1) / 2;
+  is_im = (r != 0) && ((r & 1) == 0);
+}
+
+// Harmonic table entry of order mm (any sign) from the m >= 0 table.
+__host__ __device__ inline Cd harm(const double* re, const double* im, int nmax, int n, int mm) {
+  if (n < 0 || n > nmax || mm > n || -mm > n) return {0.0, 0.0};
+  if (mm >= 0) return {re[tri(n, mm)], im[tri(n, mm)]};
+  const double sg = ((-mm) & 1) ? -1.0 : 1.0;
+  return {sg * re[tri(n, -mm)], -sg * im[tri(n, -mm)]};
+}
+
+// Regular harmonics in FP64, table of m >= 0 (runtime degree).
+__host__ __device__ void regular_table(double x, double y, double z, int p, double* re, double* im) {
+  const double r2 = x * x + y * y + z * z;
+  re[0] = 1.0;
+  im[0] = 0.0;
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) {
+      const double pr = re[tri(m - 1, m - 1)], pi = im[tri(m - 1, m - 1)];
+      re[tri(m, m)] = -(x * pr - y * pi) / (2.0 * m);
+      im[tri(m, m)] = -(x * pi + y * pr) / (2.0 * m);
+    }
+    if (m + 1 <= p) {
+      re[tri(m + 1, m)] = z * re[tri(m, m)];
+      im[tri(m + 1, m)] = z * im[tri(m, m)];
+    }
+    for (int n = m + 2; n <= p; ++n) {
+      const double d = (double)(n - m) * (double)(n + m);
+      re[tri(n, m)] = ((2.0 * n - 1.0) * z * re[tri(n - 1, m)] - r2 * re[tri(n - 2, m)]) / d;
+      im[tri(n, m)] = ((2.0 * n - 1.0) * z * im[tri(n - 1, m)] - r2 * im[tri(n - 2, m)]) / d;
+    }
+  }
+}
+
+// Irregular harmonics I_n^m, m >= 0, n <= p:
+//   I_0^0 = 1/r,  I_m^m = -(2m-1)(x + i y)/r^2 I_{m-1}^{m-1},
+//   I_{m+1}^m = (2m+1) z / r^2 I_m^m,
+//   r^2 I_n^m = (2n-1) z I_{n-1}^m - (n+m-1)(n-m-1) I_{n-2}^m.
+__host__ __device__ void irregular_table(double x, double y, double z, int p, double* re, double* im) {
+  const double r2 = x * x + y * y + z * z;
+  re[0] = 1.0 / sqrt(r2);
+  im[0] = 0.0;
+  for (int m = 0; m <= p; ++m) {
+    if (m > 0) {
+      const double pr = re[tri(m - 1, m - 1)], pi = im[tri(m - 1, m - 1)];
+      const double f = -(2.0 * m - 1.0) / r2;
+      re[tri(m, m)] = f * (x * pr - y * pi);
+      im[tri(m, m)] = f * (x * pi + y * pr);
+    }
+    if (m + 1 <= p) {
+      const double f = (2.0 * m + 1.0) * z / r2;
+      re[tri(m + 1, m)] = f * re[tri(m, m)];
+      im[tri(m + 1, m)] = f * im[tri(m, m)];
+    }
+    for (int n = m + 2; n <= p; ++n) {
+      const double c1 = (2.0 * n - 1.0) * z, c2 = (double)(n + m - 1) * (double)(n - m - 1);
+      re[tri(n, m)] = (c1 * re[tri(n - 1, m)] - c2 * re[tri(n - 2, m)]) / r2;
+      im[tri(n, m)] = (c1 * im[tri(n - 1, m)] - c2 * im[tri(n - 2, m)]) / r2;
+    }
+  }
+}
+
+constexpr int kTabMax = (2 * FMM_P_MAX + 1) * (2 * FMM_P_MAX + 2) / 2;
+
+__host__ __device__ inline void octant_vector(int oct, double w[3]) {
+  w[0] = (oct & 4) ? 0.25 : -0.25;
+  w[1] = (oct & 2) ? 0.25 : -0.25;
+  w[2] = (oct & 1) ? 0.25 : -0.25;
+}
+
+// Entry (row, col) of the M2M (is_l2l false) or L2L matrix of one octant,
+// from that octant's regular-harmonic table of w.
+__host__ __device__ inline double shift_entry(int p, bool is_l2l, int row, int col, const double* tre,
+                                              const double* tim) {
+  int n, m, k, l;
+  bool oim, iim;
+  unpack_index(row, n, m, oim);
+  unpack_index(col, k, l, iim);
+  if (!is_l2l) {
+    // output (n, m): multipole of the parent; input (k, l): multipole of the child
+    if (k > n) return 0.0;
+    Cd x1 = harm(tre, tim, p, n - k, m - l), x2 = harm(tre, tim, p, n - k, m + l);
+    x1.im = -x1.im;  // conjugates
+    x2.im = -x2.im;
+    return ldexp(real_entry(l, iim, oim, x1, x2), -k);
+  }
+  // output (n, m) = (j, i): local of the child; input (k, l): local of the parent
+  if (k < n) return 0.0;
+  const Cd x1 = harm(tre, tim, p, k - n, l - m), x2 = harm(tre, tim, p, k - n, -l - m);
+  return ldexp(real_entry(l, iim, oim, x1, x2), -n);
+}
+
+// Entry (row, col) of the unit-box M2L matrix from the irregular-harmonic
+// table (degrees <= 2p) of the offset (c_t - c_s)/h.
+__host__ __device__ inline double m2l_entry(int p, int row, int col, const double* tre,
+                                            const double* tim) {
+  int kd, l, n, m;
+  bool oim, iim;
+  unpack_index(row, kd, l, oim);
+  unpack_index(col, n, m, iim);
+  Cd x1 = harm(tre, tim, 2 * p, n + kd, m - l), x2 = harm(tre, tim, 2 * p, n + kd, -m - l);
+  if ((kd + l) & 1) {
+    x1.re = -x1.re, x1.im = -x1.im;
+    x2.re = -x2.re, x2.im = -x2.im;
+  }
+  return real_entry(m, iim, oim, x1, x2);
+}
+
+// M2M and L2L tables: block b < 8 builds M2M of octant b, block 8 + b L2L.
+__global__ void k_gen_shift(int p, double* __restrict__ m2m, double* __restrict__ l2l) {
+  __shared__ double tre[kTabMax], tim[kTabMax];
+  const int oct = blockIdx.x & 7;
+  const bool is_l2l = blockIdx.x >= 8;
+  if (threadIdx.x == 0) {
+    double w[3];
+    octant_vector(oct, w);
+    regular_table(w[0], w[1], w[2], p, tre, tim);
+  }
+  __syncthreads();
+  const int nc = (p + 1) * (p + 1);
+  double* out = (is_l2l ? l2l : m2m) + (size_t)oct * nc * nc;
+  for (int e = threadIdx.x; e < nc * nc; e += blockDim.x)
+    out[e] = shift_entry(p, is_l2l, e % nc, e / nc, tre, tim);
+}
+
+template <typename T>
+__global__ void k_gen_m2l(int p, int kp, int rp, T* __restrict__ ops) {
+  __shared__ double tre[kTabMax], tim[kTabMax];
+  const int op = blockIdx.x;
+  if (threadIdx.x == 0) {
+    int o[3];
+    m2l_offset(op, o);
+    // o is the target-minus-source offset (c_t - c_s)/h
+    irregular_table((double)o[0], (double)o[1], (double)o[2], 2 * p, tre, tim);
+  }
+  __syncthreads();
+  const int nc = (p + 1) * (p + 1);
+  T* out = ops + (size_t)op * kp * rp;
+  for (int e = threadIdx.x; e < kp * rp; e += blockDim.x) {
+    const int col = e / rp, row = e % rp;
+    const double v = (col < nc && row < nc) ? m2l_entry(p, row, col, tre, tim) : 0.0;
+    out[e] = (T)v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
+  const Layout& lay = P->lay;
+  prof_begin(P, FMM_PHASE_OPERATORS, s);
+  k_gen_shift<<<16, kBlock, 0, s>>>(P->p, wsp<double>(P, lay.op_m2m), wsp<double>(P, lay.op_l2l));
+  const int kp = m2l_k_pad(P->p), rp = m2l_rows_pad(P->p);
+  if (P->mixed)
+    k_gen_m2l<float><<<kNumM2LOps, kBlock, 0, s>>>(P->p, kp, rp, wsp<float>(P, lay.op_m2l32));
+  else
+    k_gen_m2l<double><<<kNumM2LOps, kBlock, 0, s>>>(P->p, kp, rp, wsp<double>(P, lay.op_m2l64));
+  prof_end(P, s);
+  return hipGetLastError();
+}
+
+}  // namespace fmm

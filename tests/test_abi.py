@@ -1,0 +1,121 @@
+"""Host-side checks of libfmm.so (no GPU): it loads, exports every symbol
+include/fmm.h declares, validates arguments before touching the device, and
+its Hilbert curve is an octree-consistent space-filling curve."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2209_13121_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2209_13121_amd import build
+    if build.is_stale():
+        build.build()
+    return B.load()
+
+
+def test_exports_match_header(lib):
+    hdr = open(os.path.join(ROOT, "include", "fmm.h")).read()
+    declared = set(re.findall(r"\b(fmm_[a-z_]+)\s*\(", hdr))
+    assert declared == set(B.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in range(8):
+        assert B.fmm_status_string(code) != "unknown status"
+    assert B.fmm_status_string(99) == "unknown status"
+
+
+def test_config_validation(lib):
+    n = 1000
+    for field, bad, code in [("p", -1, 1), ("p", 13, 1), ("depth", -1, 1), ("depth", 10, 1),
+                             ("ws", 2, 1), ("leaf_max", 64, 6), ("precision", 5, 1),
+                             ("m2l_kind", 9, 1), ("abi_version", 2, 1)]:
+        cfg = B.make_config()
+        setattr(cfg, field, bad)
+        with pytest.raises(B.FMMError) as ei:
+            B.fmm_workspace_size(cfg, n)
+        assert ei.value.status == code, (field, bad)
+    cfg = B.make_config(precision=B.FMM_PREC_MIXED, m2l_kind=B.FMM_M2L_F64)
+    with pytest.raises(B.FMMError) as ei:
+        B.fmm_workspace_size(cfg, n)
+    assert ei.value.status == 6
+    cfg = B.make_config(side=float("nan"))
+    with pytest.raises(B.FMMError):
+        B.fmm_workspace_size(cfg, n)
+    for bad_n in (0, -5, 2**31):
+        with pytest.raises(B.FMMError):
+            B.fmm_workspace_size(B.make_config(), bad_n)
+
+
+def test_workspace_size_monotone(lib):
+    a = B.fmm_workspace_size(B.make_config(depth=3, p=4), 4096)
+    b = B.fmm_workspace_size(B.make_config(depth=3, p=4), 8192)
+    c = B.fmm_workspace_size(B.make_config(depth=4, p=4), 4096)
+    d = B.fmm_workspace_size(B.make_config(depth=3, p=8), 4096)
+    assert a < b and a < c and a < d
+
+
+def test_plan_rejects_bad_arguments_without_device(lib):
+    cfg = B.make_config(depth=3, p=4)
+    plan = ctypes.c_void_p()
+    need = B.fmm_workspace_size(cfg, 100)
+    fake = ctypes.c_void_p(0x100000)  # never dereferenced: validation fails first
+    st = lib.fmm_plan(ctypes.byref(cfg), 100, None, fake, need, None, ctypes.byref(plan))
+    assert st == 1
+    st = lib.fmm_plan(ctypes.byref(cfg), 100, fake, None, need, None, ctypes.byref(plan))
+    assert st == 2
+    st = lib.fmm_plan(ctypes.byref(cfg), 100, fake, ctypes.c_void_p(0x100008), need, None,
+                      ctypes.byref(plan))
+    assert st == 2  # misaligned
+    st = lib.fmm_plan(ctypes.byref(cfg), 100, fake, fake, need - 1, None, ctypes.byref(plan))
+    assert st == 2  # too small
+    st = lib.fmm_plan(ctypes.byref(cfg), 0, fake, fake, need, None, ctypes.byref(plan))
+    assert st == 1
+    assert plan.value is None
+    assert lib.fmm_evaluate(None, fake, None, None, None, None) == 1
+    assert lib.fmm_check(None) == 1
+    assert lib.fmm_destroy(None) == 0
+
+
+@pytest.mark.parametrize("bits", [1, 2, 3, 4])
+def test_hilbert_is_a_face_adjacent_bijection(lib, bits):
+    nb = 1 << bits
+    idx = {}
+    for x in range(nb):
+        for y in range(nb):
+            for z in range(nb):
+                idx[B.fmm_hilbert_index(x, y, z, bits)] = (x, y, z)
+    assert sorted(idx) == list(range(nb**3))
+    for h in range(nb**3 - 1):
+        a, b = np.array(idx[h]), np.array(idx[h + 1])
+        assert np.abs(a - b).sum() == 1  # consecutive cells share a face
+
+
+@pytest.mark.parametrize("bits", [3, 4])
+def test_hilbert_prefix_is_the_ancestor_box(lib, bits):
+    nb = 1 << bits
+    for level in range(bits + 1):
+        sh = bits - level
+        slots = {}
+        for x in range(nb):
+            for y in range(nb):
+                for z in range(nb):
+                    box = (x >> sh, y >> sh, z >> sh)
+                    slot = B.fmm_hilbert_index(x, y, z, bits) >> (3 * sh)
+                    assert slots.setdefault(box, slot) == slot
+        assert sorted(slots.values()) == list(range(8**level))
+
+
+def test_hilbert_rejects_out_of_range(lib):
+    assert B.fmm_hilbert_index(8, 0, 0, 3) == 0
+    assert B.fmm_hilbert_index(0, 0, 0, -1) == 0

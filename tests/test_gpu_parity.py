@@ -1,0 +1,246 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Tolerances
+  * FP64 mode: normwise relative error of phi and F, and relative error of E,
+    <= 1e-12 against the oracle FMM with the same cube, depth and p.  Both
+    sides evaluate the same truncated expansion in FP64 in different bases and
+    summation orders, so only rounding separates them.
+  * Mixed mode: relative E <= 1e-6, normwise relative RMS force <= 1e-5 and
+    potential <= 1e-5 against the FP64 oracle FMM.
+  * Integer work (leaf cells, the resolved cube): bit-exact.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import B, half_sum_q_phi, log, rel, run_gpu, energy_rel
+from paper_2209_13121_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+# (name, n, charges, seed, depth, p)
+FP64_CASES = [
+    ("small-workload", W.SMALL.n, W.SMALL.charges, W.SMALL.seed, W.SMALL.depth, W.SMALL.p),
+    ("n2000-L2-p6", 2000, "gauss", 11, 2, 6),
+    ("n5000-L4-p5-empty-leaves", 5000, "gauss", 12, 4, 5),
+    ("n3000-L3-p8", 3000, "pm1", 13, 3, 8),
+    ("n1500-L3-p0", 1500, "gauss", 14, 3, 0),
+    ("n1500-L3-p1", 1500, "gauss", 15, 3, 1),
+    ("n1000-L3-p12", 1000, "gauss", 16, 3, 12),
+    ("n777-L1-direct", 777, "gauss", 17, 1, 3),
+    ("n513-L0-direct", 513, "pm1", 18, 0, 2),
+    ("n20011-L4-p6-ragged", 20011, "gauss", 19, 4, 6),
+]
+
+
+def make(n, charges, seed):
+    gen = W.uniform_pm1 if charges == "pm1" else W.uniform_gauss
+    return gen(n, seed)
+
+
+@pytest.mark.parametrize("case", FP64_CASES, ids=[c[0] for c in FP64_CASES])
+def test_fp64_matches_oracle(case):
+    name, n, charges, seed, depth, p = case
+    log(f"[fp64] {name}")
+    pos, q = make(n, charges, seed)
+    phi, force, e, _ = run_gpu(pos, q, depth, p)
+    phi_o, force_o, e_o = oracle.fmm(pos, q, depth, p)
+    assert rel(phi, phi_o) <= 1e-12
+    assert rel(force, force_o) <= 1e-12
+    assert energy_rel(e, e_o) <= 1e-12
+    assert energy_rel(e, half_sum_q_phi(q, phi)) <= 1e-13
+
+
+def test_fp64_nonunit_and_derived_cube():
+    log("[fp64] non-unit cube")
+    pos, q = W.uniform_gauss(3000, 21)
+    lo, side = np.array([-3.0, 1.5, 0.25]), 2.5
+    pos = lo + pos * side * 0.999
+    phi, force, e, _ = run_gpu(pos, q, 3, 6, lo=lo, side=side)
+    phi_o, force_o, e_o = oracle.fmm(pos, q, 3, 6, lo=lo, side=side)
+    assert rel(phi, phi_o) <= 1e-12 and rel(force, force_o) <= 1e-12
+    assert energy_rel(e, e_o) <= 1e-12
+    log("[fp64] derived cube")
+    phi, force, e, _ = run_gpu(pos, q, 3, 6, side=0.0)
+    phi_o, force_o, e_o = oracle.fmm(pos, q, 3, 6, side=0.0)
+    assert rel(phi, phi_o) <= 1e-12 and rel(force, force_o) <= 1e-12
+    assert energy_rel(e, e_o) <= 1e-12
+
+
+@pytest.mark.parametrize("depth,side", [(3, 1.0), (5, 1.0), (4, 0.0)])
+def test_leaf_cells_and_cube_bit_exact(depth, side):
+    import torch
+    log(f"[tree] depth {depth} side {side}")
+    pos, _ = W.uniform_gauss(10000, 31 + depth)
+    # points exactly on internal faces and on the top face
+    pos[:8] = np.array([[0.5, 0.25, 0.125], [1.0, 1.0, 1.0], [0.0, 0.0, 0.0],
+                        [0.75, 0.999999999999, 0.5], [0.125, 0.375, 0.625],
+                        [1 / 3, 2 / 3, 0.1], [0.3125, 0.6875, 0.0625], [0.5, 0.5, 0.5]])
+    dev = torch.device("cuda:0")
+    tp = torch.from_numpy(pos).to(dev)
+    f = B.FMM(tp, p=2, depth=depth, side=side)
+    cells = torch.empty((len(pos), 3), dtype=torch.int32, device=dev)
+    leaf = torch.empty(len(pos), dtype=torch.int32, device=dev)
+    B.fmm_plan_leaves(f.plan, cells, leaf)
+    lo_g, side_g = B.fmm_plan_cube(f.plan)
+    assert f.check() == 0
+    cells_o, lo_o, side_o = oracle.leaf_cells(pos, depth, side=side)
+    assert np.array_equal(cells.cpu().numpy(), cells_o)
+    assert lo_g == list(lo_o) and side_g == side_o
+    lv = leaf.cpu().numpy().astype(np.int64)
+    hk = np.array([B.fmm_hilbert_index(*map(int, c), depth) for c in cells_o[:500]])
+    assert np.array_equal(lv[:500], hk)
+    f.close()
+
+
+def test_headline_fp64_sampled():
+    """Full-size headline workload, FP64 mode, in the launch configuration the
+    benchmark uses; sampled targets against the oracle one by one."""
+    wl = W.HEADLINE
+    log(f"[fp64] {wl.name} (sampled)")
+    pos, q = wl.make()
+    phi, force, e, _ = run_gpu(pos, q, wl.depth, wl.p)
+    t = np.random.default_rng(5).choice(wl.n, 256, replace=False)
+    phi_o, force_o, _ = oracle.fmm(pos, q, wl.depth, wl.p, targets=t)
+    assert rel(phi[t], phi_o) <= 1e-12
+    assert rel(force[t], force_o) <= 1e-12
+    assert energy_rel(e, half_sum_q_phi(q, phi)) <= 1e-12
+    golden = os.path.join(HERE, "golden", "headline_oracle.json")
+    if os.path.exists(golden):
+        ref = json.load(open(golden))[wl.name]
+        assert energy_rel(e, ref["energy"]) <= 1e-12
+
+
+MIXED_CASES = [
+    ("small-workload", W.SMALL.n, W.SMALL.charges, W.SMALL.seed, W.SMALL.depth, W.SMALL.p),
+    ("n30000-L4-p8", 30000, "gauss", 41, 4, 8),
+    ("n8000-L3-p10", 8000, "pm1", 42, 3, 10),
+    ("n2000-L2-p6", 2000, "gauss", 43, 2, 6),
+]
+
+
+@pytest.mark.parametrize("case", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
+def test_mixed_within_gate(case):
+    name, n, charges, seed, depth, p = case
+    log(f"[mixed] {name}")
+    pos, q = make(n, charges, seed)
+    phi, force, e, _ = run_gpu(pos, q, depth, p, precision=B.FMM_PREC_MIXED)
+    phi_o, force_o, e_o = oracle.fmm(pos, q, depth, p)
+    log(f"  dE {energy_rel(e, e_o):.2e} dF {rel(force, force_o):.2e} dphi {rel(phi, phi_o):.2e}")
+    assert energy_rel(e, e_o) <= 1e-6
+    assert rel(force, force_o) <= 1e-5
+    assert rel(phi, phi_o) <= 1e-5
+    assert energy_rel(e, half_sum_q_phi(q, phi)) <= 1e-13
+
+
+def test_headline_mixed_sampled():
+    wl = W.HEADLINE
+    log(f"[mixed] {wl.name} (sampled)")
+    pos, q = wl.make()
+    phi, force, e, _ = run_gpu(pos, q, wl.depth, wl.p, precision=B.FMM_PREC_MIXED)
+    t = np.random.default_rng(6).choice(wl.n, 512, replace=False)
+    phi_o, force_o, _ = oracle.fmm(pos, q, wl.depth, wl.p, targets=t)
+    log(f"  sampled dF {rel(force[t], force_o):.2e} dphi {rel(phi[t], phi_o):.2e}")
+    assert rel(force[t], force_o) <= 1e-5
+    assert rel(phi[t], phi_o) <= 1e-5
+    assert energy_rel(e, half_sum_q_phi(q, phi)) <= 1e-12
+    golden = os.path.join(HERE, "golden", "headline_oracle.json")
+    if os.path.exists(golden):
+        ref = json.load(open(golden))[wl.name]
+        log(f"  dE {energy_rel(e, ref['energy']):.2e}")
+        assert energy_rel(e, ref["energy"]) <= 1e-6
+
+
+@pytest.mark.parametrize("precision", [B.FMM_PREC_FP64, B.FMM_PREC_MIXED])
+def test_deterministic(precision):
+    log(f"[determinism] precision {precision}")
+    pos, q = W.uniform_gauss(50000, 51)
+    a = run_gpu(pos, q, 4, 6, precision=precision)
+    b = run_gpu(pos, q, 4, 6, precision=precision)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
+def test_edge_cases():
+    log("[edge] n=1, n=2, one leaf, empty leaves")
+    phi, force, e, _ = run_gpu(np.array([[0.3, 0.4, 0.5]]), np.array([2.0]), 3, 4)
+    assert phi[0] == 0.0 and np.all(force == 0.0) and e == 0.0
+    pos = np.array([[0.1, 0.1, 0.1], [0.9, 0.8, 0.85]])
+    q = np.array([1.0, -2.0])
+    for depth in (0, 2, 3):
+        phi, force, e, _ = run_gpu(pos, q, depth, 6)
+        phi_o, force_o, e_o = oracle.fmm(pos, q, depth, 6)
+        assert rel(phi, phi_o) <= 1e-12 and energy_rel(e, e_o) <= 1e-12
+    # every particle in one leaf of a deep tree: only P2P contributes
+    rng = np.random.default_rng(3)
+    pos = 0.2 + 0.01 * rng.random((300, 3))
+    q = rng.normal(size=300)
+    phi, force, e, _ = run_gpu(pos, q, 4, 5)
+    phi_d, force_d, e_d = oracle.direct(pos, q)
+    assert rel(phi, phi_d) <= 1e-13 and rel(force, force_d) <= 1e-13
+
+
+def test_device_error_flags():
+    log("[errors] out of cube, non-finite, coincident")
+    pos, q = W.uniform_gauss(1000, 61)
+    bad = pos.copy()
+    bad[10] = [0.5, 1.5, 0.5]
+    assert run_gpu(bad, q, 3, 4, check=False)[3] == 3
+    bad = pos.copy()
+    bad[20, 1] = np.nan
+    assert run_gpu(bad, q, 3, 4, check=False)[3] == 4
+    bad = pos.copy()
+    bad[30] = bad[31]
+    for prec in (B.FMM_PREC_FP64, B.FMM_PREC_MIXED):
+        assert run_gpu(bad, q, 3, 4, precision=prec, check=False)[3] == 5
+
+
+def test_optional_outputs_and_reuse():
+    import torch
+    log("[api] optional outputs, plan reuse")
+    pos, q = W.uniform_gauss(4000, 71)
+    dev = torch.device("cuda:0")
+    f = B.FMM(torch.from_numpy(pos).to(dev), p=5, depth=3)
+    tq = torch.from_numpy(q).to(dev)
+    phi, force, e = f.evaluate(tq)
+    phi2, _, _ = f.evaluate(tq, want_force=False, want_energy=False)
+    _, force3, _ = f.evaluate(tq, want_phi=False, want_energy=False)
+    _, _, e4 = f.evaluate(-tq, want_phi=False, want_force=False)
+    assert torch.equal(phi, phi2) and torch.equal(force, force3) and torch.equal(e, e4)
+    assert f.check() == 0
+    with pytest.raises(B.FMMError) as ei:
+        B.fmm_backward(f.plan, e)
+    assert ei.value.status == 6
+    f.close()
+
+
+def test_work_counts():
+    import torch
+    log("[api] work counts")
+    pos, q = W.SMALL.make()
+    f = B.FMM(torch.from_numpy(pos).to("cuda:0"), p=4, depth=3)
+    m2l, p2p = B.fmm_plan_work(f.plan)
+    f.close()
+    cells, _, _ = oracle.leaf_cells(pos, 3)
+    # independent count from the leaf cells
+    occ = np.zeros((8, 8, 8), dtype=np.int64)
+    np.add.at(occ, tuple(cells.T), 1)
+    exp_p2p = 0
+    for x, y, z in zip(*np.nonzero(occ)):
+        sl = occ[max(x - 1, 0):x + 2, max(y - 1, 0):y + 2, max(z - 1, 0):z + 2].sum()
+        exp_p2p += occ[x, y, z] * (sl - 1)
+    assert p2p == exp_p2p
+    exp_m2l = 0
+    for level in (2, 3):
+        nb = 1 << level
+        o = occ.reshape(nb, 8 // nb, nb, 8 // nb, nb, 8 // nb).sum(axis=(1, 3, 5))
+        boxes = np.argwhere(o > 0)
+        for t in boxes:
+            d = np.abs(boxes - t).max(axis=1)
+            pd = np.abs(boxes // 2 - t // 2).max(axis=1)
+            exp_m2l += int(((d > 1) & (pd <= 1)).sum())
+    assert m2l == exp_m2l
