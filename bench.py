@@ -32,7 +32,24 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-boxes", type=int, default=1,
                     help="level-1 boxes (1/8 of the domain each) whose particles the oracle evaluates")
+    ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
+                    help="time one precision only (profiling runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (HBM counter calibration) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain device copy of known size: 5 launches, each reading and writing
+    mib MiB, to scale the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * 2**20 // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
 
 
 def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream):
@@ -91,6 +108,9 @@ def cpu_baseline(pos, q, wl, nboxes):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
               "this build has no multi-GPU path", file=sys.stderr)
@@ -110,6 +130,8 @@ def main():
 
     results = {}
     for name, prec in (("mixed", B.FMM_PREC_MIXED), ("fp64", B.FMM_PREC_FP64)):
+        if args.only and name != args.only:
+            continue
         cfg = B.make_config(p=wl.p, depth=wl.depth, precision=prec)
         nbytes = B.fmm_workspace_size(cfg, wl.n)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
@@ -122,6 +144,13 @@ def main():
         del ws
         torch.cuda.empty_cache()
 
+    if args.only:
+        r = results[args.only]
+        print(json.dumps({"only": args.only, "ms_per_step": r["ms"],
+                          "value": wl.n / (r["ms"] / 1e3), "status": r["status"],
+                          "phases_ms_per_step": {k: v[0] / args.steps for k, v in r["phases"].items()}}),
+              flush=True)
+        return
     golden_path = os.path.join(HERE, "tests", "golden", "headline_oracle.json")
     e_ref = json.load(open(golden_path))[wl.name]["energy"] if os.path.exists(golden_path) else None
     mx, f64 = results["mixed"], results["fp64"]

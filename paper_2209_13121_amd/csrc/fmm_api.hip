@@ -62,8 +62,9 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   lay->far_grad = take(sizeof(double) * 3 * N);
   const size_t nce = (size_t)nc;
   if (L >= 2) {
-    lay->mult64 = take(sizeof(double) * NB * nce);
-    lay->mult32 = mixed ? take(sizeof(float) * NB * nce) : 0;
+    const size_t ms = (size_t)mstride(p);
+    lay->mult64 = take(sizeof(double) * NB * ms);
+    lay->mult32 = mixed ? take(sizeof(float) * NB * ms) : 0;
     lay->m2l_out = take((mixed ? sizeof(float) : sizeof(double)) * NB * nce);
     lay->loc_exp64 = take(sizeof(double) * NB * nce);
     lay->leaf_loc32 = mixed ? take(sizeof(float) * NL * nce) : 0;

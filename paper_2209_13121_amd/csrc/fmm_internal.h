@@ -25,6 +25,10 @@ struct DevParams {
 };
 
 inline int ncoef(int p) { return (p + 1) * (p + 1); }
+// Row stride of the multipole arrays: ncoef rounded up to a multiple of 4
+// (zero padded), so that a box's coefficients start 16-byte aligned.
+__host__ __device__ constexpr int mstride_of(int nc) { return ((nc + 3) / 4) * 4; }
+inline int mstride(int p) { return mstride_of(ncoef(p)); }
 // M2L operator tile sizes: rows padded to 16-row MFMA blocks, K to 4-deep steps.
 inline int m2l_rows_pad(int p) { return ((ncoef(p) + 15) / 16) * 16; }
 inline int m2l_k_pad(int p) { return ((ncoef(p) + 3) / 4) * 4; }
@@ -37,7 +41,7 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t loc64, loc32;     // box-unit local coordinates, SoA x | y | z
   size_t q64, q32;         // sorted charges
   size_t far_phi, far_grad;  // far-field results per sorted particle (FP64)
-  size_t mult64, mult32;   // multipole expansions, all levels
+  size_t mult64, mult32;   // multipole expansions, all levels (row stride mstride)
   size_t m2l_out;          // M2L results, all levels (compute precision)
   size_t loc_exp64;        // local expansions FP64, all levels
   size_t leaf_loc32;       // leaf local expansions FP32 (mixed)

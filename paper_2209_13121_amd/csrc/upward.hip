@@ -26,6 +26,7 @@ __global__ __launch_bounds__(kBlock) void k_p2m(const uint32_t* __restrict__ sta
                                                 const T* __restrict__ loc, const T* __restrict__ q,
                                                 int64_t n, int64_t nleaf, T* __restrict__ mult) {
   constexpr int NC = (P + 1) * (P + 1);
+  constexpr int MS = mstride_of(NC);
   constexpr int NT = (P + 1) * (P + 2) / 2;
   const int64_t leaf = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (leaf >= nleaf) return;
@@ -47,14 +48,17 @@ __global__ __launch_bounds__(kBlock) void k_p2m(const uint32_t* __restrict__ sta
       }
     }
   }
-  T* out = mult + leaf * NC;
+  T* out = mult + leaf * MS;
 #pragma unroll
   for (int c = 0; c < NC; ++c) out[c] = acc[c];
+#pragma unroll
+  for (int c = NC; c < MS; ++c) out[c] = T(0);
 }
 
-// One block per parent box of level l; thread = output coefficient.
+// One block per parent box of level l; thread = output coefficient.  Child
+// and parent rows have stride ms (zero padding written for rows nc..ms-1).
 template <typename TC>
-__global__ void k_m2m(int nc, int l, int64_t nparent, const uint32_t* __restrict__ s2c_child,
+__global__ void k_m2m(int nc, int ms, int64_t nparent, const uint32_t* __restrict__ s2c_child,
                       const TC* __restrict__ child, const double* __restrict__ A,
                       double* __restrict__ parent64, float* __restrict__ parent32) {
   extern __shared__ double sm[];  // 8 * nc child coefficients
@@ -66,18 +70,25 @@ __global__ void k_m2m(int nc, int l, int64_t nparent, const uint32_t* __restrict
     unpack_coord(s2c_child[8 * ps + c], x, y, z);
     oct[c] = ((x & 1) << 2) | ((y & 1) << 1) | (z & 1);
   }
-  for (int e = threadIdx.x; e < 8 * nc; e += blockDim.x) sm[e] = (double)child[8 * ps * nc + e];
+  for (int e = threadIdx.x; e < 8 * nc; e += blockDim.x)
+    sm[e] = (double)child[(8 * ps + e / nc) * ms + e % nc];
   __syncthreads();
   const int row = threadIdx.x;
-  if (row >= nc) return;
+  if (row >= nc) {
+    if (row < ms) {
+      parent64[ps * ms + row] = 0.0;
+      if (parent32) parent32[ps * ms + row] = 0.0f;
+    }
+    return;
+  }
   double acc = 0.0;
   for (int c = 0; c < 8; ++c) {
     const double* Ac = A + (size_t)oct[c] * nc * nc;
     const double* Mc = sm + c * nc;
     for (int k = 0; k < nc; ++k) acc += Ac[(size_t)k * nc + row] * Mc[k];
   }
-  parent64[ps * nc + row] = acc;
-  if (parent32) parent32[ps * nc + row] = (float)acc;
+  parent64[ps * ms + row] = acc;
+  if (parent32) parent32[ps * ms + row] = (float)acc;
 }
 
 template <int P>
@@ -93,9 +104,9 @@ struct P2MRun {
     const Layout& lay = Pl->lay;
     if (Pl->mixed)
       return go<float>(Pl, wsp<float>(Pl, lay.loc32), wsp<float>(Pl, lay.q32),
-                       wsp<float>(Pl, lay.mult32) + lay.lvl_off[Pl->L] * Pl->nc, s);
+                       wsp<float>(Pl, lay.mult32) + lay.lvl_off[Pl->L] * mstride(Pl->p), s);
     return go<double>(Pl, wsp<double>(Pl, lay.loc64), wsp<double>(Pl, lay.q64),
-                      wsp<double>(Pl, lay.mult64) + lay.lvl_off[Pl->L] * Pl->nc, s);
+                      wsp<double>(Pl, lay.mult64) + lay.lvl_off[Pl->L] * mstride(Pl->p), s);
   }
 };
 
@@ -112,8 +123,8 @@ hipError_t launch_upward(fmm_plan_s* P, const double* d_q, hipStream_t s) {
   hipError_t e = dispatch_p<P2MRun>(P->p, P, s);
   prof_end(P, s);
   if (e != hipSuccess) return e;
-  const int nc = P->nc;
-  const int threads = ((nc + 63) / 64) * 64;
+  const int nc = P->nc, ms = mstride(P->p);
+  const int threads = ((ms + 63) / 64) * 64;
   const size_t shm = sizeof(double) * 8 * nc;
   const uint32_t* s2c = wsp<uint32_t>(P, lay.slot2coord);
   double* m64 = wsp<double>(P, lay.mult64);
@@ -123,14 +134,14 @@ hipError_t launch_upward(fmm_plan_s* P, const double* d_q, hipStream_t s) {
   for (int l = P->L - 1; l >= 2; --l) {
     const int64_t np = (int64_t)1 << (3 * l);
     const uint32_t* s2c_child = s2c + lay.lvl_off[l + 1];
-    double* p64 = m64 + lay.lvl_off[l] * nc;
-    float* p32 = m32 ? m32 + lay.lvl_off[l] * nc : nullptr;
+    double* p64 = m64 + lay.lvl_off[l] * ms;
+    float* p32 = m32 ? m32 + lay.lvl_off[l] * ms : nullptr;
     if (l + 1 == P->L && P->mixed)
-      k_m2m<float><<<(unsigned)np, threads, shm, s>>>(nc, l, np, s2c_child,
-                                                      m32 + lay.lvl_off[l + 1] * nc, A, p64, p32);
+      k_m2m<float><<<(unsigned)np, threads, shm, s>>>(nc, ms, np, s2c_child,
+                                                      m32 + lay.lvl_off[l + 1] * ms, A, p64, p32);
     else
-      k_m2m<double><<<(unsigned)np, threads, shm, s>>>(nc, l, np, s2c_child,
-                                                       m64 + lay.lvl_off[l + 1] * nc, A, p64, p32);
+      k_m2m<double><<<(unsigned)np, threads, shm, s>>>(nc, ms, np, s2c_child,
+                                                       m64 + lay.lvl_off[l + 1] * ms, A, p64, p32);
   }
   prof_end(P, s);
   return hipGetLastError();
