@@ -21,6 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 METRIC = "particles/s per FMM evaluation at 1e-6 rel. energy err, mixed vs FP64"
+M2L_SOURCES = ["paper_2209_13121_amd/csrc/m2l.hip", "paper_2209_13121_amd/csrc/fmm_internal.h"]
+TRAFFIC_SUMMARY = "profiles/k_m2l_mixed_uniform-gauss-n1048576-depth6-p8_hbm_counters.txt"
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}  # MI355X dense matrix peaks
 
 
@@ -50,6 +52,30 @@ def copy_calibration(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
+
+
+def m2l_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in M2L_SOURCES:
+        h.update(open(os.path.join(HERE, f), "rb").read())
+    return h.hexdigest()
+
+
+def m2l_traffic():
+    """HBM bytes per k_m2l launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or
+    None when the summary is missing or was taken on different kernel source."""
+    path = os.path.join(HERE, TRAFFIC_SUMMARY)
+    if not os.path.exists(path):
+        return None
+    src_hash, traffic = None, None
+    for line in open(path):
+        if line.startswith("source sha256:"):
+            src_hash = line.split()[-1]
+        if line.startswith("traffic_bytes_per_launch"):
+            traffic = float(line.split()[-1])
+    return traffic if src_hash == m2l_source_hash() else None
 
 
 def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream):
@@ -180,7 +206,7 @@ def main():
     t64, n64 = f64["phases"]["m2l"]
     roofline = {"bound": "mfma", "kernel": "k_m2l<8,float>", "achieved": achieved,
                 "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
-                "traffic": None, "flops_per_launch": m2l_flops, "m2l_pairs": m2l_pairs,
+                "traffic": m2l_traffic(), "flops_per_launch": m2l_flops, "m2l_pairs": m2l_pairs,
                 "avg_launch_ms": t_m2l / n_m2l,
                 "fp64_kernel_achieved": m2l_flops / (t64 / n64 / 1e3) / 1e12,
                 "fp64_kernel_frac": m2l_flops / (t64 / n64 / 1e3) / 1e12 / PEAK_TFLOPS["f64"]}

@@ -123,10 +123,17 @@ fmm_status fmm_plan(const fmm_config *cfg, int64_t n, const double *d_pos, void 
 fmm_status fmm_evaluate(fmm_plan_t *plan, const double *d_q, double *d_phi, double *d_force,
                         double *d_energy, fmm_stream_t stream);
 
-/* Adjoint of the energy: given the upstream gradient d_grad_energy (device
- * scalar g = dL/dE) and the charges of the last fmm_evaluate, write
- * d_dE_dx = g dE/dx (n x 3) and d_dE_dq = g dE/dq (n), either may be NULL.
- * Not implemented in this build: returns FMM_E_UNSUPPORTED. */
+/* Adjoint of the energy E = 1/2 q^T K q of the last fmm_evaluate on this plan.
+ * Given the upstream gradient d_grad_energy (device, one FP64 g = dL/dE),
+ * writes d_dE_dq = g dE/dq = g phi (n) and d_dE_dx = g dE/dx = g q_i grad phi_i
+ * = -g F_i (n x 3), both device, user order, either may be NULL.  Every pass
+ * is recomputed from the stored charges (nothing of the forward call is
+ * kept).  The FMM energy is exactly symmetric in the charges (every (local <=
+ * p, multipole <= p) pair is kept), and differentiable in x_i wherever no
+ * particle crosses a box face (Greengard 1988, ch. 3; the expansions are
+ * polynomials in the box-local offsets).  Same precision mode as the plan.
+ * Errors: FMM_E_INVALID_ARG (plan or d_grad_energy NULL, or no fmm_evaluate
+ * on the plan yet), FMM_E_DEVICE. */
 fmm_status fmm_backward(fmm_plan_t *plan, const double *d_grad_energy, double *d_dE_dx,
                         double *d_dE_dq, fmm_stream_t stream);
 

@@ -236,3 +236,45 @@ class FMM:
             self.close()
         except Exception:
             pass
+
+
+def _autograd_function():
+    import torch
+
+    class FMMEnergy(torch.autograd.Function):
+        """E = 1/2 sum q_i phi_i of the FMM, differentiable in positions and
+        charges through fmm_backward (dE/dq = phi, dE/dx = q grad phi, valid
+        while no particle crosses a box face)."""
+
+        @staticmethod
+        def forward(ctx, pos, q, p, depth, precision, lo, side):
+            f = FMM(pos.detach().contiguous(), p=p, depth=depth, precision=precision, lo=lo,
+                    side=side)
+            _, _, e = f.evaluate(q.detach().contiguous(), want_phi=False, want_force=False)
+            ctx.fmm = f
+            return e.reshape(())
+
+        @staticmethod
+        def backward(ctx, grad_e):
+            f = ctx.fmm
+            g = grad_e.detach().reshape(1).to(torch.float64).contiguous()
+            dx = torch.empty((f.n, 3), dtype=torch.float64, device=g.device) \
+                if ctx.needs_input_grad[0] else None
+            dq = torch.empty(f.n, dtype=torch.float64, device=g.device) \
+                if ctx.needs_input_grad[1] else None
+            if dx is not None or dq is not None:
+                fmm_backward(f.plan, g, dx, dq)
+            return dx, dq, None, None, None, None, None
+
+    return FMMEnergy
+
+
+_FMMENERGY = None
+
+
+def fmm_energy(pos, q, p=8, depth=3, precision=FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0):
+    """Differentiable FMM energy (torch.autograd) of charges q at positions pos."""
+    global _FMMENERGY
+    if _FMMENERGY is None:
+        _FMMENERGY = _autograd_function()
+    return _FMMENERGY.apply(pos, q, p, depth, precision, tuple(lo), side)

@@ -44,6 +44,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   lay->flags = take(sizeof(int32_t) * 4);
   lay->energy_part = take(sizeof(double) * (size_t)lay->n_energy_part);
   lay->bbox = take(sizeof(double) * 6 * 1024);
+  lay->zero_row = take(sizeof(double) * (size_t)mstride(p));
   lay->keys = take(sizeof(uint32_t) * N);
   lay->perm = take(sizeof(int32_t) * N);
   lay->perm_tmp = take(sizeof(int32_t) * N);
@@ -54,10 +55,8 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   lay->scan_tmp = take(sizeof(uint32_t) * (size_t)lay->scan_tmp_elems);
   lay->coord2slot = take(sizeof(uint32_t) * NB);
   lay->slot2coord = take(sizeof(uint32_t) * NB);
-  lay->loc64 = take(sizeof(double) * 3 * N);
-  lay->loc32 = mixed ? take(sizeof(float) * 3 * N) : 0;
+  lay->src = take((mixed ? sizeof(Rec<float>) : sizeof(Rec<double>)) * N);
   lay->q64 = take(sizeof(double) * N);
-  lay->q32 = mixed ? take(sizeof(float) * N) : 0;
   lay->far_phi = take(sizeof(double) * N);
   lay->far_grad = take(sizeof(double) * 3 * N);
   const size_t nce = (size_t)nc;
@@ -66,11 +65,13 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     lay->mult64 = take(sizeof(double) * NB * ms);
     lay->mult32 = mixed ? take(sizeof(float) * NB * ms) : 0;
     lay->m2l_out = take((mixed ? sizeof(float) : sizeof(double)) * NB * nce);
-    lay->loc_exp64 = take(sizeof(double) * NB * nce);
-    lay->leaf_loc32 = mixed ? take(sizeof(float) * NL * nce) : 0;
-    lay->op_m2m = take(sizeof(double) * 8 * nce * nce);
-    lay->op_l2l = take(sizeof(double) * 8 * nce * nce);
-    const size_t opsz = (size_t)kNumM2LOps * m2l_k_pad(p) * m2l_rows_pad(p);
+    lay->loc_exp64 = take(sizeof(double) * NB * ms);
+    lay->leaf_loc32 = mixed ? take(sizeof(float) * NL * ms) : 0;
+    const size_t tile = (size_t)m2l_k_pad(p) * m2l_rows_pad(p);
+    lay->op_m2m = take(sizeof(double) * 8 * tile);
+    lay->op_l2l = take(sizeof(double) * 8 * tile);
+    const size_t el = mixed ? sizeof(float) : sizeof(double);
+    const size_t opsz = (size_t)kNumM2LOps * m2l_rows_pad(p) * m2l_kstride_of(nc, (int)el);
     lay->op_m2l64 = mixed ? 0 : take(sizeof(double) * opsz);
     lay->op_m2l32 = mixed ? take(sizeof(float) * opsz) : 0;
   }
@@ -193,18 +194,27 @@ fmm_status fmm_evaluate(fmm_plan_t* P, const double* d_q, double* d_phi, double*
   hipError_t e = launch_upward(P, d_q, s);
   if (e == hipSuccess && P->L >= 2) e = launch_m2l(P, s);
   if (e == hipSuccess && P->L >= 2) e = launch_downward(P, s);
-  if (e == hipSuccess) e = launch_near_and_finish(P, d_phi, d_force, d_energy, s);
+  if (e == hipSuccess)
+    e = launch_near_and_finish(P, d_phi, d_force, d_energy, nullptr, nullptr, nullptr, s);
+  if (e == hipSuccess) P->has_charges = true;
   return from_hip(e);
 }
 
 fmm_status fmm_backward(fmm_plan_t* P, const double* d_grad_energy, double* d_dE_dx,
                         double* d_dE_dq, fmm_stream_t stream) {
-  (void)d_grad_energy;
-  (void)d_dE_dx;
-  (void)d_dE_dq;
-  (void)stream;
-  if (!P) return FMM_E_INVALID_ARG;
-  return FMM_E_UNSUPPORTED;
+  if (!P || !d_grad_energy) return FMM_E_INVALID_ARG;
+  if (!P->has_charges) return FMM_E_INVALID_ARG;  // no fmm_evaluate on this plan yet
+  if (!d_dE_dx && !d_dE_dq) return FMM_OK;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  P->last_stream = s;
+  // Recompute every pass from the stored sorted charges (no expansion of the
+  // forward call is reused), then write the scaled gradients.
+  hipError_t e = launch_upward(P, nullptr, s);
+  if (e == hipSuccess && P->L >= 2) e = launch_m2l(P, s);
+  if (e == hipSuccess && P->L >= 2) e = launch_downward(P, s);
+  if (e == hipSuccess)
+    e = launch_near_and_finish(P, nullptr, nullptr, nullptr, d_grad_energy, d_dE_dq, d_dE_dx, s);
+  return from_hip(e);
 }
 
 fmm_status fmm_check(fmm_plan_t* P) {

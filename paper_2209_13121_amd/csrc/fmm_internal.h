@@ -29,23 +29,30 @@ inline int ncoef(int p) { return (p + 1) * (p + 1); }
 // (zero padded), so that a box's coefficients start 16-byte aligned.
 __host__ __device__ constexpr int mstride_of(int nc) { return ((nc + 3) / 4) * 4; }
 inline int mstride(int p) { return mstride_of(ncoef(p)); }
-// M2L operator tile sizes: rows padded to 16-row MFMA blocks, K to 4-deep steps.
+// Operator tile sizes: rows padded to 16-row MFMA blocks, K to 4-deep steps.
 inline int m2l_rows_pad(int p) { return ((ncoef(p) + 15) / 16) * 16; }
 inline int m2l_k_pad(int p) { return ((ncoef(p) + 3) / 4) * 4; }
+// M2L operators are stored [row][k] with k-stride V (4 V nq + 1) elements, V
+// the elements per 16-byte vector and nq = ceil(ncoef / 4V): every 16-byte
+// k-quad a lane reads is inside the row (zero padded), and the odd quad stride
+// keeps 16 consecutive rows in distinct LDS bank groups.
+__host__ __device__ constexpr int m2l_kstride_of(int nc, int elem) {
+  return (16 / elem) * (4 * ((nc + 4 * (16 / elem) - 1) / (4 * (16 / elem))) + 1);
+}
 
 struct Layout {  // byte offsets into the workspace, every one 256-aligned
-  size_t params, flags, energy_part, bbox;
+  size_t params, flags, energy_part, bbox, zero_row;
   size_t keys, perm, perm_tmp, sorted_leaf;
   size_t leaf_count, leaf_start, leaf_fill, scan_tmp;
   size_t coord2slot, slot2coord;
-  size_t loc64, loc32;     // box-unit local coordinates, SoA x | y | z
-  size_t q64, q32;         // sorted charges
+  size_t src;              // particle records {u_x, u_y, u_z, q} in the compute precision
+  size_t q64;              // sorted charges (FP64)
   size_t far_phi, far_grad;  // far-field results per sorted particle (FP64)
   size_t mult64, mult32;   // multipole expansions, all levels (row stride mstride)
   size_t m2l_out;          // M2L results, all levels (compute precision)
-  size_t loc_exp64;        // local expansions FP64, all levels
-  size_t leaf_loc32;       // leaf local expansions FP32 (mixed)
-  size_t op_m2m, op_l2l;   // 8 x ncoef x ncoef FP64 each
+  size_t loc_exp64;        // local expansions FP64, all levels (row stride mstride)
+  size_t leaf_loc32;       // leaf local expansions FP32 (mixed; row stride mstride)
+  size_t op_m2m, op_l2l;   // 8 padded operators each, FP64
   size_t op_m2l64, op_m2l32;
   size_t work;             // 2 x int64 counters
   size_t total;
@@ -70,6 +77,7 @@ struct fmm_plan_s {
   bool mixed;
   char* ws;
   hipStream_t last_stream;
+  bool has_charges;  // fmm_evaluate has run: sorted charges are in the workspace
   // profiling
   bool profile;
   int nrec;
@@ -93,9 +101,12 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s);
 hipError_t launch_operators(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_upward(fmm_plan_s* P, const double* d_q, hipStream_t s);
 hipError_t launch_m2l(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_m2m(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_l2l(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_downward(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
-                                  double* d_energy, hipStream_t s);
+                                  double* d_energy, const double* adj_g, double* dEdq,
+                                  double* dEdx, hipStream_t s);
 hipError_t launch_leaves_out(fmm_plan_s* P, int32_t* d_cells, uint32_t* d_leaf, hipStream_t s);
 hipError_t launch_work_count(fmm_plan_s* P, hipStream_t s);
 
@@ -146,6 +157,13 @@ __host__ __device__ inline void unpack_coord(uint32_t c, int& x, int& y, int& z)
 __host__ __device__ inline int64_t lex_index(int x, int y, int z, int l) {
   return ((int64_t)x << (2 * l)) | ((int64_t)y << l) | (int64_t)z;
 }
+
+// Per sorted particle: its box-unit offset from its leaf centre and its
+// charge, one 16-byte (FP32) or 32-byte (FP64) record.
+template <typename T>
+struct alignas(4 * sizeof(T)) Rec {
+  T x, y, z, q;
+};
 
 // Real packing of the coefficients of a real-valued expansion: degree n owns
 // entries n^2 .. n^2 + 2n as [Re c_n^0, Re c_n^1, Im c_n^1, ..., Re c_n^n, Im c_n^n];

@@ -13,24 +13,28 @@
 // Mapping.  One work-group owns 128 targets of one parity class at one level
 // (the parity-pi children of 128 consecutive parent slots in Hilbert order);
 // each of its 8 waves owns 16 of them and keeps their NC-row local expansions
-// in MFMA accumulators for the whole offset loop.
-//  * A operand (operator rows): T_d is staged in LDS, in chunks of k-rows,
-//    double-buffered so the next chunk's global loads are in flight while the
-//    current one feeds the MFMAs; all 128 targets share each staged operator.
-//  * B operand (source coefficients): each lane loads its source's
-//    coefficients as 16-byte vectors.  The K order of the MFMA steps is
-//    permuted so that lane group g at sub-step s of vector chunk q uses
-//    k = 4V q + V g + s (V elements per vector); the A read from LDS follows
-//    the same order.  A whole offset's B vectors are prefetched into registers
-//    while the previous offset's MFMAs run.
-//  * Each offset's product is a fresh MFMA chain; chains are summed across
-//    offsets with Kahan compensation in FP32 (plainly in FP64).  One FP32
-//    chain over all 189 x NC/4 steps loses about 4x more accuracy.
-// FP64 MFMA in the FP64 mode, FP32 MFMA in the mixed mode.  Sources outside
-// the domain contribute zero; offsets with no valid source for any of a wave's
-// 16 targets are skipped.  Work-groups are assigned to XCDs in contiguous
-// ranges so that neighbouring tiles (which share operators and sources) share
-// an L2.
+// in MFMA accumulators (16x16x4) for the whole offset loop.
+//  * K order: lane group g at sub-step s of k-quad chunk q works on
+//    k = 4V q + V g + s (V elements per 16-byte vector), so each lane's A and B
+//    values for a chunk are one 16-byte vector each.
+//  * A operand (operator rows): T_d is stored [row][k] with an odd stride in
+//    16-byte quads and staged in LDS (double-buffered across offsets: the next
+//    operator's global loads are in flight while the current one feeds the
+//    MFMAs); one ds_read_b128 gives a lane its V values of a 16-row block, and
+//    the reads of chunk q+1 are issued before the MFMAs of chunk q.  All 128
+//    targets share each staged operator.
+//  * B operand (source coefficients): 16-byte vectors from global memory; a
+//    whole offset's vectors are prefetched while the previous offset's MFMAs
+//    run (two register sets used alternately) where the registers allow.
+//    Sources outside the domain read a zero row.  All loads are unconditional
+//    (clamped addresses) so the waits on them are exact.
+//  * FP32: each offset's product is a fresh MFMA chain and the chains are
+//    summed across offsets with Kahan compensation (one FP32 chain over all
+//    189 x NC/4 steps loses about 4x more accuracy).  FP64: one chain.
+// FP64 MFMA in the FP64 mode, FP32 MFMA in the mixed mode.  Offsets with no
+// source inside the domain for any of a wave's 16 targets skip their MFMAs.
+// Work-groups are assigned to XCDs in contiguous ranges so that neighbouring
+// tiles (which share operators and sources) share an L2.
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -48,8 +52,9 @@ struct Mfma;
 template <>
 struct Mfma<float> {
   typedef f32x4 acc_t;
-  typedef f32x4 vec_t;  // one 16-byte B vector
+  typedef f32x4 vec_t;  // one 16-byte vector
   static constexpr int V = 4;
+  static constexpr bool kChain = true;  // per-offset chains, compensated sum
   static __device__ __forceinline__ int row(int kg, int i) { return 4 * kg + i; }
   static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
@@ -66,6 +71,7 @@ struct Mfma<double> {
   typedef f64x4 acc_t;
   typedef f64x2 vec_t;
   static constexpr int V = 2;
+  static constexpr bool kChain = false;  // one FP64 chain over all offsets
   static __device__ __forceinline__ int row(int kg, int i) { return kg + 4 * i; }
   static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -76,6 +82,7 @@ struct Mfma<double> {
 constexpr int kWaves = 8;  // waves per work-group
 constexpr int kThreads = kWaves * 64;
 constexpr int kTargetsPerGroup = kWaves * 16;
+constexpr int kLdsBudget = 150 * 1024;  // two operator buffers
 
 struct M2LArgs {
   int L;
@@ -90,37 +97,42 @@ struct M2LArgs {
 template <int P, typename T>
 struct Shape {
   static constexpr int NC = (P + 1) * (P + 1);
-  static constexpr int RB = (NC + 15) / 16;      // 16-row blocks
+  static constexpr int RB = (NC + 15) / 16;    // 16-row blocks
   static constexpr int RP = RB * 16;
-  static constexpr int KP = ((NC + 3) / 4) * 4;  // operator k-rows (padded)
-  static constexpr int MS = mstride_of(NC);      // multipole row stride
-  static constexpr int V = Mfma<T>::V;           // elements per B vector
-  static constexpr int G = 4 * V;                // k per vector chunk
-  static constexpr int NQ = (NC + G - 1) / G;    // vector chunks
+  static constexpr int MS = mstride_of(NC);    // multipole row stride
+  static constexpr int V = Mfma<T>::V;         // elements per vector
+  static constexpr int G = 4 * V;              // k per quad chunk
+  static constexpr int NQ = (NC + G - 1) / G;  // quad chunks
   static constexpr int S_LAST = NC - G * (NQ - 1) < V ? NC - G * (NQ - 1) : V;
-  // LDS row stride: >= RP, 16 or 48 mod 64 words, so that the four k-rows one
-  // A-fragment read touches fall in distinct bank groups.
-  static constexpr int SLD = (RP % 64 == 16 || RP % 64 == 48) ? RP : RP + 16;
-  // k-rows staged at a time: all of them if two buffers fit in ~80 KB of LDS,
-  // else a multiple of G that does.
-  static constexpr int FIT = (80 * 1024) / (2 * SLD * (int)sizeof(T)) / G * G;
-  static constexpr int KC = FIT >= KP ? KP : FIT;
-  static constexpr int NCH = (KP + KC - 1) / KC;
-  static constexpr int PER_THREAD = (KC * RP / V + kThreads - 1) / kThreads;
-  static_assert(MS == KP, "multipole stride must equal the operator k padding");
-  static_assert(NCH == 1 || KC % G == 0, "operator chunks must hold whole vector chunks");
+  static constexpr int KS = m2l_kstride_of(NC, (int)sizeof(T));  // global row stride
+  // quad chunks per staged operator chunk: as many as fit two LDS buffers
+  static constexpr int fit_nqc(int n) {
+    return n <= 1 ? 1 : (2 * RP * V * (4 * n + 1) * (int)sizeof(T) <= kLdsBudget ? n : fit_nqc(n - 1));
+  }
+  static constexpr int NQC = fit_nqc(NQ);
+  static constexpr int NCH = (NQ + NQC - 1) / NQC;  // operator chunks
+  static constexpr int KC = G * NQC;                // k per operator chunk
+  static constexpr int KCS = V * (4 * NQC + 1);     // LDS row stride (odd quads)
+  static constexpr int VPR = KC / V;                // vectors per row per chunk
+  static constexpr int NV = RP * VPR;               // vectors per chunk
+  static constexpr int PER_THREAD = (NV + kThreads - 1) / kThreads;
+  // Prefetch the next offset's B vectors (a second register set) only where
+  // the registers allow it without spills.
+  static constexpr bool PREFETCH_B = sizeof(T) == 4 ? P <= 10 : P <= 7;
+  static_assert(MS % V == 0, "multipole rows must hold whole vectors");
 };
 
 template <int P, typename T>
 __global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict__ mult,
+                                                  const T* __restrict__ zero_row,
                                                   const T* __restrict__ ops,
                                                   T* __restrict__ out) {
   typedef Shape<P, T> S;
-  constexpr int NC = S::NC, RB = S::RB, RP = S::RP, KP = S::KP, MS = S::MS, SLD = S::SLD;
-  constexpr int V = S::V, G = S::G, NQ = S::NQ, KC = S::KC, NCH = S::NCH;
+  constexpr int NC = S::NC, RB = S::RB, RP = S::RP, MS = S::MS, V = S::V, G = S::G;
+  constexpr int NQ = S::NQ, NQC = S::NQC, NCH = S::NCH, KC = S::KC, KCS = S::KCS, KS = S::KS;
   typedef typename Mfma<T>::acc_t acc_t;
   typedef typename Mfma<T>::vec_t vec_t;
-  __shared__ __attribute__((aligned(16))) T sT[2][KC * SLD];
+  __shared__ __attribute__((aligned(16))) T sT[2][RP * KCS];
 
   // XCD-aware order: hardware group b runs on XCD b % 8; each XCD gets a
   // contiguous range of logical groups.
@@ -171,117 +183,139 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict
     while (j < 216 && !offset_of(j, dx, dy, dz)) ++j;
     return j;
   };
-  // Operator chunk ch: global k-rows [ch*KC, min(KP, (ch+1)*KC)).
-  auto chunk_vecs = [&](int ch) { return ((ch + 1) * KC <= KP ? KC : KP - ch * KC) * RP / V; };
+  // Operator chunk ch of operator op into registers / into an LDS buffer.
+  // Vector e of a chunk is row e / VPR, k-vector e % VPR; loads are clamped
+  // so that every lane issues the same loads.
   auto stage_load = [&](int op, int ch, vec_t* reg) {
-    const vec_t* src =
-        reinterpret_cast<const vec_t*>(ops + (size_t)op * KP * RP + (size_t)ch * KC * RP);
-    const int nvec = chunk_vecs(ch);
+    const T* base = ops + (size_t)op * RP * KS + ch * KC;
 #pragma unroll
     for (int i = 0; i < S::PER_THREAD; ++i) {
-      const int e = tid + i * kThreads;
-      if (e < nvec) reg[i] = src[e];
+      int e = tid + i * kThreads;
+      e = e < S::NV ? e : S::NV - 1;
+      const int row = e / S::VPR, kv = e % S::VPR;
+      const int k = ch * KC + kv * V;
+      // vectors past the operator's stored width (last chunk) read its last vector
+      const int kk = k + V <= KS ? kv * V : KS - V - ch * KC;
+      reg[i] = *reinterpret_cast<const vec_t*>(base + (size_t)row * KS + kk);
     }
   };
-  auto stage_store = [&](int ch, T* buf, const vec_t* reg) {
-    const int nvec = chunk_vecs(ch);
+  auto stage_store = [&](T* buf, const vec_t* reg) {
 #pragma unroll
     for (int i = 0; i < S::PER_THREAD; ++i) {
       const int e = tid + i * kThreads;
-      if (e < nvec) {
-        const int k = (e * V) / RP, row = (e * V) % RP;
-        *reinterpret_cast<vec_t*>(buf + k * SLD + row) = reg[i];
+      if (e < S::NV) {
+        const int row = e / S::VPR, kv = e % S::VPR;
+        *reinterpret_cast<vec_t*>(buf + row * KCS + kv * V) = reg[i];
       }
     }
   };
-  // This lane's source box for offset (dx, dy, dz) (nullptr outside the
-  // domain) and its B vectors.
-  auto source_of = [&](int dx, int dy, int dz) -> const T* {
+  // This lane's source row for offset (dx, dy, dz): the zero row outside the domain.
+  auto source_of = [&](int dx, int dy, int dz, bool& ok) -> const T* {
     const int sx = tx - dx, sy = ty - dy, sz = tz - dz;
-    const bool ok = col_ok && sx >= 0 && sy >= 0 && sz >= 0 && sx < nb && sy < nb && sz < nb;
-    return ok ? mlev + (int64_t)c2s[lex_index(sx, sy, sz, l)] * MS : nullptr;
+    ok = col_ok && sx >= 0 && sy >= 0 && sz >= 0 && sx < nb && sy < nb && sz < nb;
+    return ok ? mlev + (int64_t)c2s[lex_index(sx, sy, sz, l)] * MS : zero_row;
   };
+  // B vectors of a source row; k-quads past the row read its last vector
+  // (they meet zero operator columns).
   auto load_b = [&](const T* ms, vec_t* b) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
-      const int k0 = G * q + V * kg;
-      b[q] = vec_t{};
-      if (ms && k0 < MS) b[q] = *reinterpret_cast<const vec_t*>(ms + k0);
+      int k0 = G * q + V * kg;
+      k0 = k0 + V <= MS ? k0 : MS - V;
+      b[q] = *reinterpret_cast<const vec_t*>(ms + k0);
+    }
+  };
+  // MFMAs of operator chunk ch (staged in buf) against B vectors b.
+  auto compute_chunk = [&](const T* buf, int ch, const vec_t* b) {
+    acc_t* dst = Mfma<T>::kChain ? acc : sum;
+    const T* sa = buf + col * KCS + V * kg;
+    vec_t av[2][RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) av[0][r] = *reinterpret_cast<const vec_t*>(sa + 16 * r * KCS);
+#pragma unroll
+    for (int qc = 0; qc < NQC; ++qc) {
+      const int q = ch * NQC + qc;
+      if (q >= NQ) break;
+      if (qc + 1 < NQC && q + 1 < NQ) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+          av[(qc + 1) & 1][r] = *reinterpret_cast<const vec_t*>(sa + 16 * r * KCS + G * (qc + 1));
+      }
+      const int ns = (q == NQ - 1) ? S::S_LAST : V;
+#pragma unroll
+      for (int s = 0; s < V; ++s) {
+        if (s >= ns) break;
+        const T bv = b[q][s];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) dst[r] = Mfma<T>::step(av[qc & 1][r][s], bv, dst[r]);
+      }
     }
   };
 
+  constexpr bool PB = S::PREFETCH_B;
   vec_t reg[S::PER_THREAD];
-  vec_t bcur[NQ], bnext[NQ];
+  vec_t b0[NQ], b1[PB ? NQ : 1];
   int dx, dy, dz;
   int j = next_offset(-1, dx, dy, dz);
-  const T* ms_cur = source_of(dx, dy, dz);
-  load_b(ms_cur, bcur);
+  bool wave_any = false;
+  if (PB) {
+    bool ok_cur;
+    load_b(source_of(dx, dy, dz, ok_cur), b0);
+    wave_any = __any(ok_cur);
+  }
   stage_load(m2l_op_index(dx, dy, dz), 0, reg);
-  stage_store(0, sT[0], reg);
+  stage_store(sT[0], reg);
   __syncthreads();
-  int cur = 0, ch = 0;
-  bool wave_any = __any(ms_cur != nullptr);
-  bool ok_next = false;
-  while (true) {
-    // the stage after (j, ch); its operator chunk is loaded while this one computes
-    int jn = j, chn = ch + 1, ndx = dx, ndy = dy, ndz = dz;
-    if (chn == NCH) {
-      chn = 0;
-      jn = next_offset(j, ndx, ndy, ndz);
-    }
-    const bool more = jn < 216;
-    if (more) stage_load(m2l_op_index(ndx, ndy, ndz), chn, reg);
-    if (ch == 0) {  // prefetch the next offset's sources
-      int fx = dx, fy = dy, fz = dz;
-      const int jf = next_offset(j, fx, fy, fz);
-      ok_next = false;
-      if (jf < 216) {
-        const T* ms_next = source_of(fx, fy, fz);
-        ok_next = ms_next != nullptr;
-        load_b(ms_next, bnext);
-      }
-    }
+  int cur = 0;
 
-    if (wave_any) {
-      const T* sTc = sT[cur] + col;
-      const int kbase = ch * KC;
+  // One offset: its NCH operator chunks; stages the next chunk (of this or the
+  // next offset) and, at the first chunk, prefetches the next offset's B
+  // vectors into bn (or, without prefetch, loads this offset's into bc).
+  // Returns false after the last offset.
+  auto do_offset = [&](vec_t* bc, vec_t* bn) -> bool {
+    int ndx = dx, ndy = dy, ndz = dz;
+    const int jn = next_offset(j, ndx, ndy, ndz);
+    const bool more = jn < 216;
+    bool ok_next = false;
+    if (!PB) {
+      bool ok_cur;
+      load_b(source_of(dx, dy, dz, ok_cur), bc);
+      wave_any = __any(ok_cur);
+    }
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        if (NCH > 1 && (G * q < kbase || G * q >= kbase + KC)) continue;
-        const int ns = (q == NQ - 1) ? S::S_LAST : V;
-#pragma unroll
-        for (int s = 0; s < V; ++s) {
-          if (s >= ns) break;
-          int k = G * q + V * kg + s;
-          k = k < KP ? k : KP - 1;  // rows past KP meet zero B values; keep the read in range
-          const T bv = bcur[q][s];
-#pragma unroll
-          for (int r = 0; r < RB; ++r)
-            acc[r] = Mfma<T>::step(sTc[(k - kbase) * SLD + 16 * r], bv, acc[r]);
-        }
-      }
-      if (ch == NCH - 1) {
+    for (int ch = 0; ch < NCH; ++ch) {
+      const bool last_chunk = ch == NCH - 1;
+      if (!last_chunk)
+        stage_load(m2l_op_index(dx, dy, dz), ch + 1, reg);
+      else if (more)
+        stage_load(m2l_op_index(ndx, ndy, ndz), 0, reg);
+      if (PB && ch == 0 && more) load_b(source_of(ndx, ndy, ndz, ok_next), bn);
+      if (wave_any) compute_chunk(sT[cur], ch, bc);
+      if (Mfma<T>::kChain && last_chunk && wave_any) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           Mfma<T>::add(sum[r], comp[r], acc[r]);
           acc[r] = acc_t{0, 0, 0, 0};
         }
       }
-    }
-    if (!more) break;
-    stage_store(chn, sT[cur ^ 1], reg);
-    __syncthreads();
-    cur ^= 1;
-    if (chn == 0) {  // moving to the next offset, whose sources are in bnext
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) bcur[q] = bnext[q];
-      wave_any = __any(ok_next);
+      if (last_chunk && !more) return false;
+      stage_store(sT[cur ^ 1], reg);
+      __syncthreads();
+      cur ^= 1;
     }
     j = jn;
-    ch = chn;
     dx = ndx;
     dy = ndy;
     dz = ndz;
+    if (PB) wave_any = __any(ok_next);
+    return true;
+  };
+  if (PB) {
+    while (do_offset(b0, b1) && do_offset(b1, b0)) {
+    }
+  } else {
+    while (do_offset(b0, b0)) {
+    }
   }
 
   if (!col_ok) return;
@@ -316,10 +350,12 @@ struct M2LRun {
     const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
     if (Pl->mixed)
       k_m2l<P, float><<<grid, kThreads, 0, s>>>(a, wsp<float>(Pl, lay.mult32),
+                                               wsp<float>(Pl, lay.zero_row),
                                                wsp<float>(Pl, lay.op_m2l32),
                                                wsp<float>(Pl, lay.m2l_out));
     else
       k_m2l<P, double><<<grid, kThreads, 0, s>>>(a, wsp<double>(Pl, lay.mult64),
+                                                wsp<double>(Pl, lay.zero_row),
                                                 wsp<double>(Pl, lay.op_m2l64),
                                                 wsp<double>(Pl, lay.m2l_out));
     return hipGetLastError();

@@ -6,7 +6,11 @@
 // box-local coordinates, x_i - x_j = h ((u_i - u_j) - o) with o the integer
 // leaf offset, so FP32 keeps the full relative accuracy of the local offsets.
 // Then phi_i = phi_near + phi_far, F_i = -q_i grad phi_i (FP64), written at the
-// particle's user index.  E = 1/2 sum q_i phi_i is reduced in FP64 in a fixed
+// particle's user index.  In the adjoint form the same pass writes
+// g dE/dq_i = g phi_i and g dE/dx_i = g q_i grad phi_i: with every
+// (local <= p, multipole <= p) pair kept, the FMM energy is a symmetric
+// quadratic form in q, and while no particle crosses a box face its gradient
+// in x_i is q_i grad phi_i.  E = 1/2 sum q_i phi_i is reduced in FP64 in a fixed
 // tree order: per-block partials, then one block over the partials.
 #include <math.h>
 
@@ -22,10 +26,11 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_near(
     int64_t n, int L, const DevParams* __restrict__ dp, const uint32_t* __restrict__ sorted_leaf,
     const uint32_t* __restrict__ start, const uint32_t* __restrict__ c2s,
-    const uint32_t* __restrict__ s2c, const T* __restrict__ loc, const T* __restrict__ qs,
+    const uint32_t* __restrict__ s2c, const Rec<T>* __restrict__ src,
     const double* __restrict__ q64, const int32_t* __restrict__ perm, int has_far,
     const double* __restrict__ far_phi, const double* __restrict__ far_grad,
     double* __restrict__ phi_out, double* __restrict__ force_out, double* __restrict__ epart,
+    const double* __restrict__ adj_g, double* __restrict__ dEdq, double* __restrict__ dEdx,
     int32_t* __restrict__ flags) {
   __shared__ double red[kBlock];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -34,7 +39,8 @@ __global__ __launch_bounds__(kBlock) void k_near(
     const uint32_t leaf = sorted_leaf[i];
     int cx, cy, cz;
     unpack_coord(s2c[leaf], cx, cy, cz);
-    const T xi = loc[i], yi = loc[n + i], zi = loc[2 * n + i];
+    const Rec<T> ri = src[i];
+    const T xi = ri.x, yi = ri.y, zi = ri.z;
     T f = T(0), gx = T(0), gy = T(0), gz = T(0);
     bool coincident = false;
     const int nb = 1 << L;
@@ -52,14 +58,15 @@ __global__ __launch_bounds__(kBlock) void k_near(
           const T ox = xi - T(dx), oy = yi - T(dy), oz = zi - T(dz);
           for (uint32_t j = b; j < e; ++j) {
             if ((int64_t)j == i) continue;
-            const T rx = ox - loc[j], ry = oy - loc[n + j], rz = oz - loc[2 * n + j];
+            const Rec<T> rj = src[j];
+            const T rx = ox - rj.x, ry = oy - rj.y, rz = oz - rj.z;
             const T r2 = rx * rx + ry * ry + rz * rz;
             if (r2 == T(0)) {
               coincident = true;
               continue;
             }
             const T rinv = inv_sqrt(r2);
-            const T qr = qs[j] * rinv;
+            const T qr = rj.q * rinv;
             const T qr3 = qr * rinv * rinv;
             f += qr;
             gx -= qr3 * rx;
@@ -83,6 +90,12 @@ __global__ __launch_bounds__(kBlock) void k_near(
     if (phi_out) phi_out[u] = phi;
     if (force_out)
       for (int a = 0; a < 3; ++a) force_out[3 * u + a] = -qi * g[a];
+    if (adj_g) {  // adjoint: dE/dq_i = phi_i, dE/dx_i = q_i grad phi_i, times g
+      const double gs = adj_g[0];
+      if (dEdq) dEdq[u] = gs * phi;
+      if (dEdx)
+        for (int a = 0; a < 3; ++a) dEdx[3 * u + a] = gs * (qi * g[a]);
+    }
     e_i = qi * phi;
   }
   if (!epart) return;
@@ -111,7 +124,8 @@ __global__ void k_energy(const double* __restrict__ part, int64_t nparts, double
 }  // namespace
 
 hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
-                                  double* d_energy, hipStream_t s) {
+                                  double* d_energy, const double* adj_g, double* dEdq,
+                                  double* dEdx, hipStream_t s) {
   const Layout& lay = P->lay;
   const int64_t n = P->n;
   const int L = P->L;
@@ -122,17 +136,17 @@ hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
   if (P->mixed)
     k_near<float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
         n, L, wsp<DevParams>(P, lay.params), wsp<uint32_t>(P, lay.sorted_leaf),
-        wsp<uint32_t>(P, lay.leaf_start), c2s, s2c, wsp<float>(P, lay.loc32),
-        wsp<float>(P, lay.q32), wsp<double>(P, lay.q64), wsp<int32_t>(P, lay.perm), L >= 2,
-        wsp<double>(P, lay.far_phi), wsp<double>(P, lay.far_grad), d_phi, d_force, epart,
-        wsp<int32_t>(P, lay.flags));
+        wsp<uint32_t>(P, lay.leaf_start), c2s, s2c, wsp<Rec<float>>(P, lay.src),
+        wsp<double>(P, lay.q64), wsp<int32_t>(P, lay.perm), L >= 2,
+        wsp<double>(P, lay.far_phi), wsp<double>(P, lay.far_grad), d_phi, d_force, epart, adj_g,
+        dEdq, dEdx, wsp<int32_t>(P, lay.flags));
   else
     k_near<double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
         n, L, wsp<DevParams>(P, lay.params), wsp<uint32_t>(P, lay.sorted_leaf),
-        wsp<uint32_t>(P, lay.leaf_start), c2s, s2c, wsp<double>(P, lay.loc64),
-        wsp<double>(P, lay.q64), wsp<double>(P, lay.q64), wsp<int32_t>(P, lay.perm), L >= 2,
-        wsp<double>(P, lay.far_phi), wsp<double>(P, lay.far_grad), d_phi, d_force, epart,
-        wsp<int32_t>(P, lay.flags));
+        wsp<uint32_t>(P, lay.leaf_start), c2s, s2c, wsp<Rec<double>>(P, lay.src),
+        wsp<double>(P, lay.q64), wsp<int32_t>(P, lay.perm), L >= 2,
+        wsp<double>(P, lay.far_phi), wsp<double>(P, lay.far_grad), d_phi, d_force, epart, adj_g,
+        dEdq, dEdx, wsp<int32_t>(P, lay.flags));
   prof_end(P, s);
   if (d_energy) {
     prof_begin(P, FMM_PHASE_ENERGY, s);

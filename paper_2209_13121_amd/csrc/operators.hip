@@ -17,9 +17,10 @@
 // acting on the packed real coefficient vector (fmm_internal.h).  The 1/h of
 // M2L is applied when its result is promoted (L2L pass).
 //
-// Tables: M2M and L2L, 8 octants each, stored [octant][input k][output row]
-// (FP64); M2L, 316 offsets, stored [offset][input k (padded to KP)][output row
-// (padded to RP)], zero padded, in the M2L precision.
+// Tables, zero padded: M2M and L2L, 8 octants each, FP64, stored
+// [octant][input k (padded to KP)][output row (padded to RP)]; M2L, 316
+// offsets in the M2L precision, stored [offset][output row (padded to RP)]
+// [input k (stride m2l_kstride_of)].
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -112,6 +113,33 @@ __host__ __device__ void irregular_table(double x, double y, double z, int p, do
 
 constexpr int kTabMax = (2 * FMM_P_MAX + 1) * (2 * FMM_P_MAX + 2) / 2;
 
+// Column m (all degrees n = m..p) of the irregular table, by the same
+// recurrences, with the diagonal entry in closed form
+// I_m^m = (-1)^m (2m-1)!! (x + i y)^m / r^{2m+1}; one thread per order m.
+__host__ __device__ void irregular_column(double x, double y, double z, int p, int m, double* re,
+                                 double* im) {
+  const double r2 = x * x + y * y + z * z;
+  double dr = 1.0 / sqrt(r2), di = 0.0;  // I_0^0
+  for (int k = 1; k <= m; ++k) {
+    const double f = -(2.0 * k - 1.0) / r2;
+    const double nr = f * (x * dr - y * di), ni = f * (x * di + y * dr);
+    dr = nr;
+    di = ni;
+  }
+  re[tri(m, m)] = dr;
+  im[tri(m, m)] = di;
+  if (m + 1 <= p) {
+    const double f = (2.0 * m + 1.0) * z / r2;
+    re[tri(m + 1, m)] = f * dr;
+    im[tri(m + 1, m)] = f * di;
+  }
+  for (int n = m + 2; n <= p; ++n) {
+    const double c1 = (2.0 * n - 1.0) * z, c2 = (double)(n + m - 1) * (double)(n - m - 1);
+    re[tri(n, m)] = (c1 * re[tri(n - 1, m)] - c2 * re[tri(n - 2, m)]) / r2;
+    im[tri(n, m)] = (c1 * im[tri(n - 1, m)] - c2 * im[tri(n - 2, m)]) / r2;
+  }
+}
+
 __host__ __device__ inline void octant_vector(int oct, double w[3]) {
   w[0] = (oct & 4) ? 0.25 : -0.25;
   w[1] = (oct & 2) ? 0.25 : -0.25;
@@ -156,8 +184,10 @@ __host__ __device__ inline double m2l_entry(int p, int row, int col, const doubl
   return real_entry(m, iim, oim, x1, x2);
 }
 
-// M2M and L2L tables: block b < 8 builds M2M of octant b, block 8 + b L2L.
-__global__ void k_gen_shift(int p, double* __restrict__ m2m, double* __restrict__ l2l) {
+// M2M and L2L tables: block b < 8 builds M2M of octant b, block 8 + b L2L,
+// stored [octant][k (padded to kp)][row (padded to rp)], zero padded.
+__global__ void k_gen_shift(int p, int kp, int rp, double* __restrict__ m2m,
+                            double* __restrict__ l2l) {
   __shared__ double tre[kTabMax], tim[kTabMax];
   const int oct = blockIdx.x & 7;
   const bool is_l2l = blockIdx.x >= 8;
@@ -168,26 +198,28 @@ __global__ void k_gen_shift(int p, double* __restrict__ m2m, double* __restrict_
   }
   __syncthreads();
   const int nc = (p + 1) * (p + 1);
-  double* out = (is_l2l ? l2l : m2m) + (size_t)oct * nc * nc;
-  for (int e = threadIdx.x; e < nc * nc; e += blockDim.x)
-    out[e] = shift_entry(p, is_l2l, e % nc, e / nc, tre, tim);
+  double* out = (is_l2l ? l2l : m2m) + (size_t)oct * kp * rp;
+  for (int e = threadIdx.x; e < kp * rp; e += blockDim.x) {
+    const int col = e / rp, row = e % rp;
+    out[e] = (col < nc && row < nc) ? shift_entry(p, is_l2l, row, col, tre, tim) : 0.0;
+  }
 }
 
 template <typename T>
-__global__ void k_gen_m2l(int p, int kp, int rp, T* __restrict__ ops) {
+__global__ void k_gen_m2l(int p, int rp, int ks, T* __restrict__ ops) {
   __shared__ double tre[kTabMax], tim[kTabMax];
   const int op = blockIdx.x;
-  if (threadIdx.x == 0) {
+  if ((int)threadIdx.x <= 2 * p) {
     int o[3];
     m2l_offset(op, o);
     // o is the target-minus-source offset (c_t - c_s)/h
-    irregular_table((double)o[0], (double)o[1], (double)o[2], 2 * p, tre, tim);
+    irregular_column((double)o[0], (double)o[1], (double)o[2], 2 * p, threadIdx.x, tre, tim);
   }
   __syncthreads();
   const int nc = (p + 1) * (p + 1);
-  T* out = ops + (size_t)op * kp * rp;
-  for (int e = threadIdx.x; e < kp * rp; e += blockDim.x) {
-    const int col = e / rp, row = e % rp;
+  T* out = ops + (size_t)op * rp * ks;
+  for (int e = threadIdx.x; e < rp * ks; e += blockDim.x) {
+    const int row = e / ks, col = e % ks;
     const double v = (col < nc && row < nc) ? m2l_entry(p, row, col, tre, tim) : 0.0;
     out[e] = (T)v;
   }
@@ -198,12 +230,15 @@ __global__ void k_gen_m2l(int p, int kp, int rp, T* __restrict__ ops) {
 hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
   const Layout& lay = P->lay;
   prof_begin(P, FMM_PHASE_OPERATORS, s);
-  k_gen_shift<<<16, kBlock, 0, s>>>(P->p, wsp<double>(P, lay.op_m2m), wsp<double>(P, lay.op_l2l));
   const int kp = m2l_k_pad(P->p), rp = m2l_rows_pad(P->p);
+  k_gen_shift<<<16, kBlock, 0, s>>>(P->p, kp, rp, wsp<double>(P, lay.op_m2m),
+                                    wsp<double>(P, lay.op_l2l));
   if (P->mixed)
-    k_gen_m2l<float><<<kNumM2LOps, kBlock, 0, s>>>(P->p, kp, rp, wsp<float>(P, lay.op_m2l32));
+    k_gen_m2l<float><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, m2l_kstride_of(P->nc, 4),
+                                                   wsp<float>(P, lay.op_m2l32));
   else
-    k_gen_m2l<double><<<kNumM2LOps, kBlock, 0, s>>>(P->p, kp, rp, wsp<double>(P, lay.op_m2l64));
+    k_gen_m2l<double><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, m2l_kstride_of(P->nc, 8),
+                                                    wsp<double>(P, lay.op_m2l64));
   prof_end(P, s);
   return hipGetLastError();
 }

@@ -201,11 +201,11 @@ __global__ void k_luts(int L, int64_t nbox, Layout lay,
   s2c[lay.lvl_off[l] + slot] = pack_coord(x, y, z);
 }
 
+template <typename T>
 __global__ void k_gather(const double* __restrict__ pos, const int32_t* __restrict__ perm,
                          const uint32_t* __restrict__ keys, int64_t n, int L,
                          const DevParams* __restrict__ dp, const uint32_t* __restrict__ s2c_leaf,
-                         uint32_t* __restrict__ sorted_leaf, double* __restrict__ loc64,
-                         float* __restrict__ loc32) {
+                         uint32_t* __restrict__ sorted_leaf, Rec<T>* __restrict__ src) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int32_t i = perm[s];
@@ -214,14 +214,19 @@ __global__ void k_gather(const double* __restrict__ pos, const int32_t* __restri
   int c[3];
   unpack_coord(s2c_leaf[leaf], c[0], c[1], c[2]);
   const double h = dp->side / (double)(1 << L);
+  double u[3];
   for (int a = 0; a < 3; ++a) {
     double x = pos[3 * (int64_t)i + a];
     if (!isfinite(x)) x = dp->lo[a];
     const double centre = dp->lo[a] + ((double)c[a] + 0.5) * h;
-    const double u = (x - centre) / h;
-    loc64[a * n + s] = u;
-    if (loc32) loc32[a * n + s] = (float)u;
+    u[a] = (x - centre) / h;
   }
+  Rec<T> r;
+  r.x = (T)u[0];
+  r.y = (T)u[1];
+  r.z = (T)u[2];
+  r.q = T(0);  // filled by each evaluation
+  src[s] = r;
 }
 
 __global__ void k_leaves_out(const uint32_t* __restrict__ keys, int64_t n,
@@ -319,6 +324,10 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
     k_bbox_final<<<1, 64, 0, s>>>(part, nparts, dp, flags);
   }
   k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(count, lay.nleaf, 0u);
+  {  // the zero row M2L reads for sources outside the domain
+    const int64_t words = 2 * (int64_t)mstride(P->p);
+    k_fill_u32<<<grid_for(words, kBlock), kBlock, 0, s>>>(wsp<uint32_t>(P, lay.zero_row), words, 0u);
+  }
   k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(fill, lay.nleaf, 0u);
   k_luts<<<grid_for(lay.nbox, kBlock), kBlock, 0, s>>>(L, lay.nbox, lay, c2s, s2c);
   k_keys<<<grid_for(n, kBlock), kBlock, 0, s>>>(d_pos, n, L, given ? 1 : 0, dp, keys, count, flags);
@@ -329,9 +338,14 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
   int32_t* perm = wsp<int32_t>(P, lay.perm);
   k_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(keys, n, start, fill, perm_tmp);
   k_rank<<<grid_for(n, kBlock), kBlock, 0, s>>>(perm_tmp, keys, n, start, count, perm);
-  k_gather<<<grid_for(n, kBlock), kBlock, 0, s>>>(
-      d_pos, perm, keys, n, L, dp, s2c + lay.lvl_off[L], wsp<uint32_t>(P, lay.sorted_leaf),
-      wsp<double>(P, lay.loc64), P->mixed ? wsp<float>(P, lay.loc32) : nullptr);
+  if (P->mixed)
+    k_gather<float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
+        d_pos, perm, keys, n, L, dp, s2c + lay.lvl_off[L], wsp<uint32_t>(P, lay.sorted_leaf),
+        wsp<Rec<float>>(P, lay.src));
+  else
+    k_gather<double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
+        d_pos, perm, keys, n, L, dp, s2c + lay.lvl_off[L], wsp<uint32_t>(P, lay.sorted_leaf),
+        wsp<Rec<double>>(P, lay.src));
   prof_end(P, s);
   return hipGetLastError();
 }
