@@ -226,7 +226,7 @@ __host__ __device__ constexpr int clamp03(int v) { return v < 0 ? 0 : (v > 3 ? 3
 
 // Inverse of m2l_offset: lexicographic position in [-3,3]^3 minus the number
 // of inner ([-1,1]^3) offsets that precede it.
-__host__ __device__ inline int m2l_op_index(int ox, int oy, int oz) {
+__host__ __device__ constexpr int m2l_op_index(int ox, int oy, int oz) {
   const int a = ox + 3, b = oy + 3, c = oz + 3;
   int before = 9 * clamp03(a - 2);
   if (a >= 2 && a <= 4) {

@@ -35,10 +35,13 @@
 // source inside the domain for any of a wave's 16 targets skip their MFMAs.
 // Work-groups are assigned to XCDs in contiguous ranges so that neighbouring
 // tiles (which share operators and sources) share an L2.
-#include "fmm_internal.h"
+#include "m2l_common.h"
 
 namespace fmm {
 namespace {
+
+using m2l::kThreads;
+using m2l::kWaves;
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
@@ -65,6 +68,12 @@ struct Mfma<float> {
     comp = (t - sum) - y;
     sum = t;
   }
+  static __device__ __forceinline__ void add1(float& sum, float& comp, float v) {
+    const float y = v - comp;
+    const float t = sum + y;
+    comp = (t - sum) - y;
+    sum = t;
+  }
 };
 template <>
 struct Mfma<double> {
@@ -77,21 +86,11 @@ struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ void add(acc_t& sum, acc_t&, acc_t v) { sum += v; }
+  static __device__ __forceinline__ void add1(double& sum, double&, double v) { sum += v; }
 };
 
-constexpr int kWaves = 8;  // waves per work-group
-constexpr int kThreads = kWaves * 64;
-constexpr int kTargetsPerGroup = kWaves * 16;
-constexpr int kLdsBudget = 150 * 1024;  // two operator buffers
+constexpr int kLdsBudget = 140 * 1024;  // two operator buffers (plus the slot halo)
 
-struct M2LArgs {
-  int L;
-  int64_t lvl_off[FMM_DEPTH_MAX + 2];    // box offsets per level
-  int64_t group_off[FMM_DEPTH_MAX + 2];  // first work-group of each level (levels 2..L)
-  int64_t ngroups;
-  const uint32_t* c2s;
-  const uint32_t* s2c;
-};
 
 // Static shape of the kernel for order P and type T.
 template <int P, typename T>
@@ -99,6 +98,11 @@ struct Shape {
   static constexpr int NC = (P + 1) * (P + 1);
   static constexpr int RB = (NC + 15) / 16;    // 16-row blocks
   static constexpr int RP = RB * 16;
+  // NC = 16 RBM + 1 (p = 6, 8): the last row is a per-lane dot product on the
+  // vector ALU instead of a 16-row MFMA block holding one real row.
+  static constexpr bool TAIL = NC % 16 == 1 && NC > 16;
+  static constexpr int RBM = TAIL ? RB - 1 : RB;  // MFMA row blocks
+  static constexpr int ROWS = TAIL ? NC : RP;     // operator rows staged in LDS
   static constexpr int MS = mstride_of(NC);    // multipole row stride
   static constexpr int V = Mfma<T>::V;         // elements per vector
   static constexpr int G = 4 * V;              // k per quad chunk
@@ -107,14 +111,14 @@ struct Shape {
   static constexpr int KS = m2l_kstride_of(NC, (int)sizeof(T));  // global row stride
   // quad chunks per staged operator chunk: as many as fit two LDS buffers
   static constexpr int fit_nqc(int n) {
-    return n <= 1 ? 1 : (2 * RP * V * (4 * n + 1) * (int)sizeof(T) <= kLdsBudget ? n : fit_nqc(n - 1));
+    return n <= 1 ? 1 : (2 * ROWS * V * (4 * n + 1) * (int)sizeof(T) <= kLdsBudget ? n : fit_nqc(n - 1));
   }
   static constexpr int NQC = fit_nqc(NQ);
   static constexpr int NCH = (NQ + NQC - 1) / NQC;  // operator chunks
   static constexpr int KC = G * NQC;                // k per operator chunk
   static constexpr int KCS = V * (4 * NQC + 1);     // LDS row stride (odd quads)
   static constexpr int VPR = KC / V;                // vectors per row per chunk
-  static constexpr int NV = RP * VPR;               // vectors per chunk
+  static constexpr int NV = ROWS * VPR;             // vectors per chunk
   static constexpr int PER_THREAD = (NV + kThreads - 1) / kThreads;
   // Prefetch the next offset's B vectors (a second register set) only where
   // the registers allow it without spills.
@@ -123,65 +127,37 @@ struct Shape {
 };
 
 template <int P, typename T>
-__global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict__ mult,
+__global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restrict__ mult,
                                                   const T* __restrict__ zero_row,
                                                   const T* __restrict__ ops,
                                                   T* __restrict__ out) {
   typedef Shape<P, T> S;
   constexpr int NC = S::NC, RB = S::RB, RP = S::RP, MS = S::MS, V = S::V, G = S::G;
   constexpr int NQ = S::NQ, NQC = S::NQC, NCH = S::NCH, KC = S::KC, KCS = S::KCS, KS = S::KS;
+  constexpr int RBM = S::RBM;
+  constexpr bool TAIL = S::TAIL;
   typedef typename Mfma<T>::acc_t acc_t;
   typedef typename Mfma<T>::vec_t vec_t;
-  __shared__ __attribute__((aligned(16))) T sT[2][RP * KCS];
-
-  // XCD-aware order: hardware group b runs on XCD b % 8; each XCD gets a
-  // contiguous range of logical groups.
-  const int64_t per_xcd = (a.ngroups + 7) / 8;
-  const int64_t lg = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-  if (lg >= a.ngroups) return;  // uniform over the work-group
-
-  int l = 2;
-  while (l < a.L && lg >= a.group_off[l + 1]) ++l;
-  const int64_t np = (int64_t)1 << (3 * (l - 1));  // parents at level l-1
-  const int64_t ntile = (np + kTargetsPerGroup - 1) / kTargetsPerGroup;
-  const int64_t idx = lg - a.group_off[l];
-  const int pi = (int)(idx / ntile);
-  const int64_t tile = idx % ntile;
-  const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
-
+  __shared__ __attribute__((aligned(16))) T sT[2][S::ROWS * KCS];
+  __shared__ uint32_t sSlot[m2l::kHalo];
+  __shared__ int sBox[6];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  const int nb = 1 << l;
-  const uint32_t* c2s = a.c2s + a.lvl_off[l];
-  const T* mlev = mult + a.lvl_off[l] * MS;
+  m2l::Tile tl;
+  if (!tl.setup(a, wave, col, sSlot, sBox)) return;  // uniform over the work-group
+  const int pi = tl.pi;
+  const bool col_ok = tl.col_ok;
+  const T* mlev = mult + tl.lvl_off * MS;
 
-  const int64_t ps = tile * kTargetsPerGroup + wave * 16 + col;
-  const bool col_ok = ps < np;
-  int tx = 0, ty = 0, tz = 0;
-  if (col_ok) {
-    unpack_coord(a.s2c[a.lvl_off[l - 1] + ps], tx, ty, tz);
-    tx = 2 * tx + px;
-    ty = 2 * ty + py;
-    tz = 2 * tz + pz;
-  }
-
-  acc_t sum[RB], comp[RB], acc[RB];
+  acc_t sum[RBM], comp[RBM], acc[RBM];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) sum[r] = comp[r] = acc[r] = acc_t{0, 0, 0, 0};
+  for (int r = 0; r < RBM; ++r) sum[r] = comp[r] = acc[r] = acc_t{0, 0, 0, 0};
+  // Tail row (TAIL): this lane's partial sum over its k values.
+  T tsum = T(0), tcomp = T(0), tacc = T(0);
 
-  // Offsets of the class in a fixed order: d_a in [pi_a - 3, pi_a + 2] with
-  // max |d_a| >= 2 (216 candidates, 27 skipped).
-  auto offset_of = [&](int j, int& dx, int& dy, int& dz) {
-    dx = px - 3 + j / 36;
-    dy = py - 3 + (j / 6) % 6;
-    dz = pz - 3 + j % 6;
-    return !(dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1);
-  };
-  auto next_offset = [&](int j, int& dx, int& dy, int& dz) {
-    ++j;
-    while (j < 216 && !offset_of(j, dx, dy, dz)) ++j;
-    return j;
+  auto offset_of = [&](int i, int& dx, int& dy, int& dz) {
+    return m2l::il_offset(pi, i, dx, dy, dz);
   };
   // Operator chunk ch of operator op into registers / into an LDS buffer.
   // Vector e of a chunk is row e / VPR, k-vector e % VPR; loads are clamped
@@ -209,11 +185,11 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict
       }
     }
   };
-  // This lane's source row for offset (dx, dy, dz): the zero row outside the domain.
-  auto source_of = [&](int dx, int dy, int dz, bool& ok) -> const T* {
-    const int sx = tx - dx, sy = ty - dy, sz = tz - dz;
-    ok = col_ok && sx >= 0 && sy >= 0 && sz >= 0 && sx < nb && sy < nb && sz < nb;
-    return ok ? mlev + (int64_t)c2s[lex_index(sx, sy, sz, l)] * MS : zero_row;
+  typedef m2l::Src Src;
+  auto lookup = [&](int dx, int dy, int dz) -> Src { return tl.lookup(sSlot, dx, dy, dz); };
+  // Source row of a lookup: the zero row outside the domain.
+  auto row_of = [&](Src src) -> const T* {
+    return src.ok ? mlev + (int64_t)src.slot * MS : zero_row;
   };
   // B vectors of a source row; k-quads past the row read its last vector
   // (they meet zero operator columns).
@@ -228,18 +204,22 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict
   // MFMAs of operator chunk ch (staged in buf) against B vectors b.
   auto compute_chunk = [&](const T* buf, int ch, const vec_t* b) {
     acc_t* dst = Mfma<T>::kChain ? acc : sum;
+    T& tdst = Mfma<T>::kChain ? tacc : tsum;
     const T* sa = buf + col * KCS + V * kg;
-    vec_t av[2][RB];
+    const T* st = buf + (NC - 1) * KCS + V * kg;  // tail row (same for all 16 columns)
+    vec_t av[2][RBM], at[2];
 #pragma unroll
-    for (int r = 0; r < RB; ++r) av[0][r] = *reinterpret_cast<const vec_t*>(sa + 16 * r * KCS);
+    for (int r = 0; r < RBM; ++r) av[0][r] = *reinterpret_cast<const vec_t*>(sa + 16 * r * KCS);
+    if (TAIL) at[0] = *reinterpret_cast<const vec_t*>(st);
 #pragma unroll
     for (int qc = 0; qc < NQC; ++qc) {
       const int q = ch * NQC + qc;
       if (q >= NQ) break;
       if (qc + 1 < NQC && q + 1 < NQ) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r)
+        for (int r = 0; r < RBM; ++r)
           av[(qc + 1) & 1][r] = *reinterpret_cast<const vec_t*>(sa + 16 * r * KCS + G * (qc + 1));
+        if (TAIL) at[(qc + 1) & 1] = *reinterpret_cast<const vec_t*>(st + G * (qc + 1));
       }
       const int ns = (q == NQ - 1) ? S::S_LAST : V;
 #pragma unroll
@@ -247,7 +227,8 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict
         if (s >= ns) break;
         const T bv = b[q][s];
 #pragma unroll
-        for (int r = 0; r < RB; ++r) dst[r] = Mfma<T>::step(av[qc & 1][r][s], bv, dst[r]);
+        for (int r = 0; r < RBM; ++r) dst[r] = Mfma<T>::step(av[qc & 1][r][s], bv, dst[r]);
+        if (TAIL) tdst = fma(at[qc & 1][s], bv, tdst);
       }
     }
   };
@@ -255,15 +236,20 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict
   constexpr bool PB = S::PREFETCH_B;
   vec_t reg[S::PER_THREAD];
   vec_t b0[NQ], b1[PB ? NQ : 1];
-  int dx, dy, dz;
-  int j = next_offset(-1, dx, dy, dz);
+  // Pipeline over the class's offsets: offset i is computed while the
+  // operator of the next stage and the B vectors of offset i + 1 are loaded
+  // and the source slot of offset i + 2 is looked up.
+  int i = 0, dx, dy, dz, ndx, ndy, ndz;
+  int op = offset_of(0, dx, dy, dz);
+  int nop = offset_of(1, ndx, ndy, ndz);
+  Src s_cur = lookup(dx, dy, dz);
+  Src s_next = lookup(ndx, ndy, ndz);
   bool wave_any = false;
   if (PB) {
-    bool ok_cur;
-    load_b(source_of(dx, dy, dz, ok_cur), b0);
-    wave_any = __any(ok_cur);
+    load_b(row_of(s_cur), b0);
+    wave_any = __any(s_cur.ok);
   }
-  stage_load(m2l_op_index(dx, dy, dz), 0, reg);
+  stage_load(op, 0, reg);
   stage_store(sT[0], reg);
   __syncthreads();
   int cur = 0;
@@ -273,29 +259,29 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict
   // vectors into bn (or, without prefetch, loads this offset's into bc).
   // Returns false after the last offset.
   auto do_offset = [&](vec_t* bc, vec_t* bn) -> bool {
-    int ndx = dx, ndy = dy, ndz = dz;
-    const int jn = next_offset(j, ndx, ndy, ndz);
-    const bool more = jn < 216;
-    bool ok_next = false;
+    const bool more = i + 1 < kIL;
+    int fdx, fdy, fdz;
+    const int fop = offset_of(i + 2 < kIL ? i + 2 : kIL - 1, fdx, fdy, fdz);
+    const Src s_far = lookup(fdx, fdy, fdz);  // offset i + 2 (clamped at the end)
     if (!PB) {
-      bool ok_cur;
-      load_b(source_of(dx, dy, dz, ok_cur), bc);
-      wave_any = __any(ok_cur);
+      load_b(row_of(s_cur), bc);
+      wave_any = __any(s_cur.ok);
     }
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const bool last_chunk = ch == NCH - 1;
-      if (!last_chunk)
-        stage_load(m2l_op_index(dx, dy, dz), ch + 1, reg);
-      else if (more)
-        stage_load(m2l_op_index(ndx, ndy, ndz), 0, reg);
-      if (PB && ch == 0 && more) load_b(source_of(ndx, ndy, ndz, ok_next), bn);
+      stage_load(last_chunk ? (more ? nop : op) : op, last_chunk ? 0 : ch + 1, reg);
+      if (PB && ch == 0) load_b(row_of(s_next), bn);
       if (wave_any) compute_chunk(sT[cur], ch, bc);
       if (Mfma<T>::kChain && last_chunk && wave_any) {
 #pragma unroll
-        for (int r = 0; r < RB; ++r) {
+        for (int r = 0; r < RBM; ++r) {
           Mfma<T>::add(sum[r], comp[r], acc[r]);
           acc[r] = acc_t{0, 0, 0, 0};
+        }
+        if (TAIL) {
+          Mfma<T>::add1(tsum, tcomp, tacc);
+          tacc = T(0);
         }
       }
       if (last_chunk && !more) return false;
@@ -303,11 +289,18 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict
       __syncthreads();
       cur ^= 1;
     }
-    j = jn;
+    ++i;
+    op = nop;
     dx = ndx;
     dy = ndy;
     dz = ndz;
-    if (PB) wave_any = __any(ok_next);
+    nop = fop;
+    ndx = fdx;
+    ndy = fdy;
+    ndz = fdz;
+    if (PB) wave_any = __any(s_next.ok);
+    s_cur = s_next;
+    s_next = s_far;
     return true;
   };
   if (PB) {
@@ -318,36 +311,32 @@ __global__ __launch_bounds__(kThreads) void k_m2l(M2LArgs a, const T* __restrict
     }
   }
 
+  // Tail row: combine the four lane groups' partials (fixed order; all lanes
+  // take part in the shuffles).
+  T tail = T(0);
+  if (TAIL) {
+    tail = tsum - tcomp;
+    tail += __shfl_xor(tail, 16);
+    tail += __shfl_xor(tail, 32);
+  }
   if (!col_ok) return;
-  const int64_t ts = c2s[lex_index(tx, ty, tz, l)];
-  T* o = out + (a.lvl_off[l] + ts) * NC;
+  T* o = out + (tl.lvl_off + tl.target_slot(a)) * NC;
 #pragma unroll
-  for (int r = 0; r < RB; ++r)
+  for (int r = 0; r < RBM; ++r)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = 16 * r + Mfma<T>::row(kg, i);
       if (row < NC) o[row] = sum[r][i];
     }
+  if (TAIL && kg == 0) o[NC - 1] = tail;
 }
 
 template <int P>
 struct M2LRun {
   static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
     const Layout& lay = Pl->lay;
-    M2LArgs a;
-    a.L = Pl->L;
-    for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) a.lvl_off[l] = lay.lvl_off[l];
-    int64_t g = 0;
-    for (int l = 2; l <= Pl->L; ++l) {
-      a.group_off[l] = g;
-      const int64_t np = (int64_t)1 << (3 * (l - 1));
-      g += 8 * ((np + kTargetsPerGroup - 1) / kTargetsPerGroup);
-    }
-    a.group_off[Pl->L + 1] = g;
-    a.ngroups = g;
-    a.c2s = wsp<uint32_t>(Pl, lay.coord2slot);
-    a.s2c = wsp<uint32_t>(Pl, lay.slot2coord);
-    const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
+    const m2l::Args a = m2l::make_args(Pl);
+    const unsigned grid = m2l::grid_of(a);
     if (Pl->mixed)
       k_m2l<P, float><<<grid, kThreads, 0, s>>>(a, wsp<float>(Pl, lay.mult32),
                                                wsp<float>(Pl, lay.zero_row),

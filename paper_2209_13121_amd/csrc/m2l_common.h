@@ -1,0 +1,185 @@
+// m2l_common.h -- work decomposition shared by the M2L kernels (FP32/FP64
+// MFMA in m2l.hip, split-BF16 MFMA in m2l_bf16.hip).
+//
+// For a target box t at level l >= 2 the interaction list is every box s of
+// level l whose parent is adjacent to t's parent but which is not adjacent to
+// t (well-separatedness 1; Greengard 1988, ch. 3; Cheng, Greengard & Rokhlin
+// 1999, sec. 3).  With d = t - s the list depends only on the parity pi of t's
+// coordinates: d_a ranges over [pi_a - 3, pi_a + 2] with max |d_a| >= 2, 189
+// offsets per class, one unit-box operator per offset (316 in all).
+//
+// One work-group owns 128 targets of one parity class at one level: the
+// parity-pi children of 128 consecutive, aligned parent slots in Hilbert
+// order.  Each of its 8 waves owns 16 of them (one MFMA column block).
+#ifndef FMM_M2L_COMMON_H_
+#define FMM_M2L_COMMON_H_
+
+#include "fmm_internal.h"
+
+namespace fmm {
+namespace m2l {
+
+constexpr int kWaves = 8;  // waves per work-group
+constexpr int kThreads = kWaves * 64;
+constexpr int kTargetsPerGroup = kWaves * 16;
+
+// Interaction-list offsets of each parity class pi in a fixed order, with
+// their operator numbers: code = op | (dx + 4) << 9 | (dy + 4) << 13 | (dz + 4) << 17.
+struct ILTable {
+  uint32_t v[8][kIL];
+};
+constexpr ILTable make_il_table() {
+  ILTable t{};
+  for (int pi = 0; pi < 8; ++pi) {
+    const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
+    int i = 0;
+    for (int a = 0; a < 6; ++a)
+      for (int b = 0; b < 6; ++b)
+        for (int c = 0; c < 6; ++c) {
+          const int dx = px - 3 + a, dy = py - 3 + b, dz = pz - 3 + c;
+          if (dx >= -1 && dx <= 1 && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1) continue;
+          t.v[pi][i++] = (uint32_t)m2l_op_index(dx, dy, dz) | (uint32_t)(dx + 4) << 9 |
+                         (uint32_t)(dy + 4) << 13 | (uint32_t)(dz + 4) << 17;
+        }
+  }
+  return t;
+}
+static __constant__ ILTable kILTable = make_il_table();
+
+// Offset i of class pi and its operator number.
+__device__ __forceinline__ int il_offset(int pi, int i, int& dx, int& dy, int& dz) {
+  const uint32_t c = kILTable.v[pi][i];
+  dx = (int)((c >> 9) & 15u) - 4;
+  dy = (int)((c >> 13) & 15u) - 4;
+  dz = (int)((c >> 17) & 15u) - 4;
+  return (int)(c & 511u);
+}
+
+struct Args {
+  int L;
+  int64_t lvl_off[FMM_DEPTH_MAX + 2];    // box offsets per level
+  int64_t group_off[FMM_DEPTH_MAX + 2];  // first work-group of each level (levels 2..L)
+  int64_t ngroups;
+  const uint32_t* c2s;
+  const uint32_t* s2c;
+};
+
+inline Args make_args(fmm_plan_s* Pl) {
+  const Layout& lay = Pl->lay;
+  Args a;
+  a.L = Pl->L;
+  for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) a.lvl_off[l] = lay.lvl_off[l];
+  int64_t g = 0;
+  for (int l = 2; l <= Pl->L; ++l) {
+    a.group_off[l] = g;
+    const int64_t np = (int64_t)1 << (3 * (l - 1));
+    g += 8 * ((np + kTargetsPerGroup - 1) / kTargetsPerGroup);
+  }
+  a.group_off[Pl->L + 1] = g;
+  a.ngroups = g;
+  a.c2s = wsp<uint32_t>(Pl, lay.coord2slot);
+  a.s2c = wsp<uint32_t>(Pl, lay.slot2coord);
+  return a;
+}
+inline unsigned grid_of(const Args& a) { return (unsigned)(((a.ngroups + 7) / 8) * 8); }
+
+// Slots of every source box a work-group can touch: 128 consecutive aligned
+// Hilbert slots of the parent level are two face-adjacent 4^3 blocks, so the
+// targets span at most 15 x 7 x 7 boxes and their sources (targets - d,
+// d in [pi - 3, pi + 2]) at most 20 x 12 x 12.
+constexpr int kHalo = 20 * 12 * 12;
+
+struct Src {
+  uint32_t slot;
+  bool ok;  // inside the domain (else the source is a zero row)
+};
+
+// A lane's view of its work-group's tile.
+struct Tile {
+  int l, pi, nb;
+  int tx, ty, tz;  // this lane's target box (meaningful when col_ok)
+  bool col_ok;
+  int hx0, hy0, hz0, hx1, hy1, hz1, hey, hez;  // halo box (clamped to the level)
+  int64_t lvl_off;                             // first box of level l
+
+  // Decode the group, find this lane's target (column `col` of wave `wave`)
+  // and stage the halo's slots in sSlot.  Returns false, uniformly over the
+  // work-group, for a group past the end.  Contains barriers.
+  __device__ bool setup(const Args& a, int wave, int col, uint32_t* sSlot, int* sBox) {
+    // XCD-aware order: hardware group b runs on XCD b % 8; each XCD gets a
+    // contiguous range of logical groups.
+    const int64_t per_xcd = (a.ngroups + 7) / 8;
+    const int64_t lg = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (lg >= a.ngroups) return false;
+    l = 2;
+    while (l < a.L && lg >= a.group_off[l + 1]) ++l;
+    const int64_t np = (int64_t)1 << (3 * (l - 1));  // parents at level l-1
+    // The 8 parity classes of a tile are consecutive groups, so they run close
+    // together on one XCD and share its L2 for the tile's sources.
+    const int64_t idx = lg - a.group_off[l];
+    pi = (int)(idx % 8);
+    const int64_t tile = idx / 8;
+    const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
+    nb = 1 << l;
+    lvl_off = a.lvl_off[l];
+    const int64_t ps = tile * kTargetsPerGroup + wave * 16 + col;
+    col_ok = ps < np;
+    tx = ty = tz = 0;
+    if (col_ok) {
+      unpack_coord(a.s2c[a.lvl_off[l - 1] + ps], tx, ty, tz);
+      tx = 2 * tx + px;
+      ty = 2 * ty + py;
+      tz = 2 * tz + pz;
+    }
+    const int tid = threadIdx.x;
+    if (tid < 6) sBox[tid] = tid < 3 ? nb : -1;
+    __syncthreads();
+    if (col_ok) {
+      atomicMin(&sBox[0], tx - px - 2);
+      atomicMin(&sBox[1], ty - py - 2);
+      atomicMin(&sBox[2], tz - pz - 2);
+      atomicMax(&sBox[3], tx - px + 3);
+      atomicMax(&sBox[4], ty - py + 3);
+      atomicMax(&sBox[5], tz - pz + 3);
+    }
+    __syncthreads();
+    hx0 = sBox[0] < 0 ? 0 : sBox[0];
+    hy0 = sBox[1] < 0 ? 0 : sBox[1];
+    hz0 = sBox[2] < 0 ? 0 : sBox[2];
+    hx1 = sBox[3] >= nb ? nb - 1 : sBox[3];
+    hy1 = sBox[4] >= nb ? nb - 1 : sBox[4];
+    hz1 = sBox[5] >= nb ? nb - 1 : sBox[5];
+    hey = hy1 - hy0 + 1;
+    hez = hz1 - hz0 + 1;
+    const int hn = (hx1 - hx0 + 1) * hey * hez;  // <= kHalo by the bound above
+    const uint32_t* c2s = a.c2s + lvl_off;
+    for (int e = tid; e < hn && e < kHalo; e += (int)blockDim.x) {
+      const int x = hx0 + e / (hey * hez), y = hy0 + (e / hez) % hey, z = hz0 + e % hez;
+      sSlot[e] = c2s[lex_index(x, y, z, l)];
+    }
+    __syncthreads();
+    return true;
+  }
+
+  // This lane's source for offset (dx, dy, dz): its slot, read from the
+  // staged halo at coordinates clamped into it (so the read is
+  // unconditional), and whether it lies in the domain.
+  __device__ __forceinline__ Src lookup(const uint32_t* sSlot, int dx, int dy, int dz) const {
+    int sx = tx - dx, sy = ty - dy, sz = tz - dz;
+    const bool ok = col_ok && sx >= 0 && sy >= 0 && sz >= 0 && sx < nb && sy < nb && sz < nb;
+    sx = sx < hx0 ? hx0 : (sx > hx1 ? hx1 : sx);
+    sy = sy < hy0 ? hy0 : (sy > hy1 ? hy1 : sy);
+    sz = sz < hz0 ? hz0 : (sz > hz1 ? hz1 : sz);
+    return Src{sSlot[((sx - hx0) * hey + (sy - hy0)) * hez + (sz - hz0)], ok};
+  }
+
+  // Slot of this lane's target (col_ok only).
+  __device__ __forceinline__ int64_t target_slot(const Args& a) const {
+    return a.c2s[lvl_off + lex_index(tx, ty, tz, l)];
+  }
+};
+
+}  // namespace m2l
+}  // namespace fmm
+
+#endif  // FMM_M2L_COMMON_H_
