@@ -3,9 +3,10 @@
 Workload: 2^20 charges uniform in the unit cube, Gaussian charges shifted to
 net zero (seed 1002), uniform octree of depth 6, expansion order p = 8.  One
 step = fmm_plan (tree build for the positions) + fmm_evaluate (all passes,
-potentials, forces and energy) on device-resident inputs.  The headline value
-is the mixed-precision path; the FP64 path is timed the same way and reported
-beside it, with both energies compared to the stored FP64 oracle energy.
+potentials, forces and energy) on device-resident inputs.  Three variants are
+timed the same way: mixed precision with the split-BF16 M2L (the library's
+default mixed form, the headline value), mixed precision with the FP32 M2L,
+and FP64; every energy is compared to the stored FP64 oracle energy.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build runs on
 one GPU.
@@ -21,9 +22,29 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 METRIC = "particles/s per FMM evaluation at 1e-6 rel. energy err, mixed vs FP64"
-M2L_SOURCES = ["paper_2209_13121_amd/csrc/m2l.hip", "paper_2209_13121_amd/csrc/fmm_internal.h"]
-TRAFFIC_SUMMARY = "profiles/k_m2l_mixed_uniform-gauss-n1048576-depth6-p8_hbm_counters.txt"
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}  # MI355X dense matrix peaks
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}  # MI355X dense matrix peaks
+
+# Timed variants: name -> (precision, m2l_kind, M2L kernel, its sources, dtype
+# of the matrix-core work, piece products per FP32 product).
+VARIANTS = {
+    "mixed_bf16x3": ("MIXED", "BF16X3", "k_m2l_bf<8,3>",
+                     ["paper_2209_13121_amd/csrc/m2l_bf16.hip", "paper_2209_13121_amd/csrc/m2l_common.h",
+                      "paper_2209_13121_amd/csrc/bf16_split.h", "paper_2209_13121_amd/csrc/fmm_internal.h"],
+                     "bf16", 6),
+    "mixed_f32": ("MIXED", "F32", "k_m2l<8,float>",
+                  ["paper_2209_13121_amd/csrc/m2l.hip", "paper_2209_13121_amd/csrc/m2l_common.h",
+                   "paper_2209_13121_amd/csrc/fmm_internal.h"],
+                  "f32", 1),
+    "fp64": ("FP64", "AUTO", "k_m2l<8,double>",
+             ["paper_2209_13121_amd/csrc/m2l.hip", "paper_2209_13121_amd/csrc/m2l_common.h",
+              "paper_2209_13121_amd/csrc/fmm_internal.h"],
+             "f64", 1),
+}
+HEADLINE = "mixed_bf16x3"  # the mixed form the library picks for FMM_M2L_AUTO
+
+
+def traffic_summary(variant):
+    return f"profiles/k_m2l_{variant}_uniform-gauss-n1048576-depth6-p8_hbm_counters.txt"
 
 
 def parse():
@@ -34,8 +55,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-boxes", type=int, default=1,
                     help="level-1 boxes (1/8 of the domain each) whose particles the oracle evaluates")
-    ap.add_argument("--only", choices=["mixed", "fp64"], default=None,
-                    help="time one precision only (profiling runs)")
+    ap.add_argument("--only", choices=sorted(VARIANTS), default=None,
+                    help="time one variant only (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -54,19 +75,20 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
 
 
-def m2l_source_hash():
+def m2l_source_hash(variant):
     import hashlib
     h = hashlib.sha256()
-    for f in M2L_SOURCES:
+    for f in VARIANTS[variant][3]:
         h.update(open(os.path.join(HERE, f), "rb").read())
     return h.hexdigest()
 
 
-def m2l_traffic():
-    """HBM bytes per k_m2l launch from the committed rocprofv3 counter summary
-    (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's reading), or
-    None when the summary is missing or was taken on different kernel source."""
-    path = os.path.join(HERE, TRAFFIC_SUMMARY)
+def m2l_traffic(variant):
+    """HBM bytes per M2L kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by a plain copy's
+    reading), or None when the summary is missing or was taken on different
+    kernel source."""
+    path = os.path.join(HERE, traffic_summary(variant))
     if not os.path.exists(path):
         return None
     src_hash, traffic = None, None
@@ -75,7 +97,7 @@ def m2l_traffic():
             src_hash = line.split()[-1]
         if line.startswith("traffic_bytes_per_launch"):
             traffic = float(line.split()[-1])
-    return traffic if src_hash == m2l_source_hash() else None
+    return traffic if src_hash == m2l_source_hash(variant) else None
 
 
 def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream):
@@ -155,10 +177,11 @@ def main():
     B.load()
 
     results = {}
-    for name, prec in (("mixed", B.FMM_PREC_MIXED), ("fp64", B.FMM_PREC_FP64)):
+    for name, (prec, kind, *_rest) in VARIANTS.items():
         if args.only and name != args.only:
             continue
-        cfg = B.make_config(p=wl.p, depth=wl.depth, precision=prec)
+        cfg = B.make_config(p=wl.p, depth=wl.depth, precision=getattr(B, "FMM_PREC_" + prec),
+                            m2l_kind=getattr(B, "FMM_M2L_" + kind))
         nbytes = B.fmm_workspace_size(cfg, wl.n)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         print(f"[bench] {name}: workspace {nbytes / 2**20:.0f} MiB", file=sys.stderr, flush=True)
@@ -179,57 +202,72 @@ def main():
         return
     golden_path = os.path.join(HERE, "tests", "golden", "headline_oracle.json")
     e_ref = json.load(open(golden_path))[wl.name]["energy"] if os.path.exists(golden_path) else None
-    mx, f64 = results["mixed"], results["fp64"]
+    f64 = results["fp64"]
 
     def erel(e):
         return abs(e - e_ref) / abs(e_ref) if e_ref is not None else None
 
-    acc = {
-        "oracle_energy": e_ref,
-        "mixed_rel_energy_err_vs_oracle": erel(mx["energy"]),
-        "fp64_rel_energy_err_vs_oracle": erel(f64["energy"]),
-        "mixed_rel_rms_force_err_vs_fp64_gpu": float(
-            np.linalg.norm(mx["force"] - f64["force"]) / np.linalg.norm(f64["force"])),
-        "mixed_rel_phi_err_vs_fp64_gpu": float(
-            np.linalg.norm(mx["phi"] - f64["phi"]) / np.linalg.norm(f64["phi"])),
-    }
-    gate = acc["mixed_rel_energy_err_vs_oracle"] is not None and \
-        acc["mixed_rel_energy_err_vs_oracle"] <= 1e-6
-    acc["gate_1e-6_met"] = bool(gate)
-
     nc = (wl.p + 1) ** 2
-    m2l_pairs, p2p_pairs = mx["work"]
+    m2l_pairs, p2p_pairs = f64["work"]
     m2l_flops = 2.0 * nc * nc * m2l_pairs  # algorithmic, non-empty box pairs
-    t_m2l, n_m2l = mx["phases"]["m2l"]
-    avg_m2l_s = t_m2l / n_m2l / 1e3
-    achieved = m2l_flops / avg_m2l_s / 1e12
-    t64, n64 = f64["phases"]["m2l"]
-    roofline = {"bound": "mfma", "kernel": "k_m2l<8,float>", "achieved": achieved,
-                "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["f32"],
-                "traffic": m2l_traffic(), "flops_per_launch": m2l_flops, "m2l_pairs": m2l_pairs,
-                "avg_launch_ms": t_m2l / n_m2l,
-                "fp64_kernel_achieved": m2l_flops / (t64 / n64 / 1e3) / 1e12,
-                "fp64_kernel_frac": m2l_flops / (t64 / n64 / 1e3) / 1e12 / PEAK_TFLOPS["f64"]}
+
+    def m2l_rate(name):
+        """Average M2L launch (ms) and the kernel's achieved rate: its
+        matrix-core flops per launch (piece products for the split forms) over
+        that duration, against the dense peak of its own dtype."""
+        _, _, kernel, _, dtype, nprod = VARIANTS[name]
+        t, c = results[name]["phases"]["m2l"]
+        avg_ms = t / c
+        flops = nprod * m2l_flops
+        ach = flops / (avg_ms / 1e3) / 1e12
+        return {"kernel": kernel, "avg_launch_ms": avg_ms, "flops_per_launch": flops,
+                "achieved": ach, "peak": PEAK_TFLOPS[dtype], "frac": ach / PEAK_TFLOPS[dtype],
+                "fp32_equivalent_tflops": m2l_flops / (avg_ms / 1e3) / 1e12}
+
+    variants = {}
+    for name, r in results.items():
+        variants[name] = {
+            "value": wl.n / (r["ms"] / 1e3), "ms_per_step": r["ms"], "status": r["status"],
+            "rel_energy_err_vs_oracle": erel(r["energy"]),
+            "rel_rms_force_err_vs_fp64_gpu": float(
+                np.linalg.norm(r["force"] - f64["force"]) / np.linalg.norm(f64["force"])),
+            "rel_phi_err_vs_fp64_gpu": float(
+                np.linalg.norm(r["phi"] - f64["phi"]) / np.linalg.norm(f64["phi"])),
+            "phases_ms_per_step": {k: v[0] / args.steps for k, v in r["phases"].items()},
+            "m2l": m2l_rate(name),
+        }
+    hl = variants[HEADLINE]
+    gate = hl["rel_energy_err_vs_oracle"] is not None and hl["rel_energy_err_vs_oracle"] <= 1e-6
+    rate = hl["m2l"]
+    roofline = {"bound": "mfma", "kernel": rate["kernel"], "achieved": rate["achieved"],
+                "peak": rate["peak"], "unit": "TFLOP/s", "frac": rate["frac"],
+                "traffic": m2l_traffic(HEADLINE), "flops_per_launch": rate["flops_per_launch"],
+                "m2l_pairs": m2l_pairs, "avg_launch_ms": rate["avg_launch_ms"],
+                "fp32_equivalent_tflops": rate["fp32_equivalent_tflops"]}
 
     out = {
         "metric": METRIC,
-        "value": wl.n / (mx["ms"] / 1e3),
+        "value": hl["value"],
         "unit": "particles/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": mx["ms"],
+        "ms_per_step": hl["ms_per_step"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": VARIANTS[HEADLINE][4] + "/f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "n": wl.n, "depth": wl.depth, "p": wl.p, "seed": wl.seed,
-                   "precision": "mixed (FP32 P2M/M2L-MFMA/L2P/P2P, FP64 M2M/L2L/energy)",
+                   "variant": HEADLINE,
+                   "precision": "mixed (FP32 P2M/L2P/P2P, M2L on " +
+                                ("split-BF16 MFMA, 3 pieces" if VARIANTS[HEADLINE][4] == "bf16"
+                                 else "FP32 MFMA") + ", FP64 M2M/L2L/energy)",
                    "step": "fmm_plan + fmm_evaluate"},
-        "fp64": {"value": wl.n / (f64["ms"] / 1e3), "ms_per_step": f64["ms"]},
-        "accuracy": acc,
-        "phases_ms_per_step": {k: v[0] / args.steps for k, v in mx["phases"].items()},
-        "fp64_phases_ms_per_step": {k: v[0] / args.steps for k, v in f64["phases"].items()},
+        "accuracy": {"oracle_energy": e_ref,
+                     "rel_energy_err_vs_oracle": hl["rel_energy_err_vs_oracle"],
+                     "rel_rms_force_err_vs_fp64_gpu": hl["rel_rms_force_err_vs_fp64_gpu"],
+                     "rel_phi_err_vs_fp64_gpu": hl["rel_phi_err_vs_fp64_gpu"],
+                     "gate_1e-6_met": bool(gate)},
+        "variants": variants,
         "p2p_pairs": p2p_pairs,
         "roofline": roofline,
-        "status": {"mixed": mx["status"], "fp64": f64["status"]},
     }
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

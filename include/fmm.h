@@ -67,14 +67,21 @@ typedef enum {
 
 typedef enum {
   FMM_PREC_FP64 = 0,  /* every pass in FP64 */
-  FMM_PREC_MIXED = 1  /* P2M, M2L, L2P, P2P in FP32 (M2L on FP32 MFMA); M2M, L2L,
-                         the combination of results and the energy in FP64 */
+  FMM_PREC_MIXED = 1  /* P2M, L2P, P2P in FP32, M2L on the FP32 or split-BF16 matrix
+                         cores with FP32 accumulation (fmm_m2l_kind); M2M, L2L, the
+                         combination of results and the energy in FP64 */
 } fmm_precision;
 
 typedef enum {
-  FMM_M2L_AUTO = 0, /* FP64 MFMA for FMM_PREC_FP64, FP32 MFMA for FMM_PREC_MIXED */
-  FMM_M2L_F64 = 1,
-  FMM_M2L_F32 = 2
+  FMM_M2L_AUTO = 0,   /* FMM_M2L_F64 for FMM_PREC_FP64, FMM_M2L_BF16X3 for FMM_PREC_MIXED */
+  FMM_M2L_F64 = 1,    /* FP64 matrix cores (FMM_PREC_FP64 only) */
+  FMM_M2L_F32 = 2,    /* FP32 matrix cores (FMM_PREC_MIXED only) */
+  FMM_M2L_BF16X2 = 3, /* BF16 matrix cores, operands split into 2 BF16 pieces, 3 piece
+                         products, FP32 accumulation (FMM_PREC_MIXED only; about
+                         16 significant bits per product, below the FP32 modes) */
+  FMM_M2L_BF16X3 = 4  /* BF16 matrix cores, operands split into 3 BF16 pieces (exact for
+                         FP32 values), the 6 piece products of total order <= 2, FP32
+                         accumulation (FMM_PREC_MIXED only; FP32-level products) */
 } fmm_m2l_kind;
 
 typedef struct {
@@ -86,7 +93,8 @@ typedef struct {
   int32_t leaf_max;     /* reserved for adaptive trees; must be 0 */
   int32_t ws;           /* well-separatedness; must be 1 */
   int32_t precision;    /* fmm_precision */
-  int32_t m2l_kind;     /* fmm_m2l_kind; must agree with precision or be AUTO */
+  int32_t m2l_kind;     /* fmm_m2l_kind; must agree with precision or be AUTO
+                           (else FMM_E_UNSUPPORTED) */
   double root_lo[3];    /* root cube corner */
   double root_side;     /* > 0: the cube [root_lo, root_lo + root_side]^3, which
                            must contain every position (else FMM_E_OUT_OF_CUBE);

@@ -17,7 +17,7 @@ FMM_ABI_VERSION = 1
 FMM_P_MAX = 12
 FMM_DEPTH_MAX = 9
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
-FMM_M2L_AUTO, FMM_M2L_F64, FMM_M2L_F32 = 0, 1, 2
+FMM_M2L_AUTO, FMM_M2L_F64, FMM_M2L_F32, FMM_M2L_BF16X2, FMM_M2L_BF16X3 = 0, 1, 2, 3, 4
 STATUS_NAMES = {0: "FMM_OK", 1: "FMM_E_INVALID_ARG", 2: "FMM_E_WORKSPACE", 3: "FMM_E_OUT_OF_CUBE",
                 4: "FMM_E_NONFINITE", 5: "FMM_E_COINCIDENT", 6: "FMM_E_UNSUPPORTED",
                 7: "FMM_E_DEVICE"}
@@ -201,10 +201,10 @@ class FMM:
     """Owns a workspace and a plan for one position set (torch device tensors)."""
 
     def __init__(self, pos, p=8, depth=3, precision=FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
-                 stream=None, workspace=None):
+                 stream=None, workspace=None, m2l_kind=FMM_M2L_AUTO):
         import torch
         self.n = pos.shape[0]
-        self.cfg = make_config(p, depth, precision, lo, side)
+        self.cfg = make_config(p, depth, precision, lo, side, m2l_kind)
         nbytes = fmm_workspace_size(self.cfg, self.n)
         if workspace is None or workspace.numel() < nbytes:
             workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=pos.device)

@@ -11,6 +11,13 @@ namespace fmm {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+int m2l_pieces(const fmm_config& cfg) {
+  if (cfg.precision != FMM_PREC_MIXED) return 0;
+  if (cfg.m2l_kind == FMM_M2L_BF16X2) return 2;
+  if (cfg.m2l_kind == FMM_M2L_BF16X3 || cfg.m2l_kind == FMM_M2L_AUTO) return 3;
+  return 0;
+}
+
 bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   memset(lay, 0, sizeof(*lay));
   const int L = cfg.depth, p = cfg.p, nc = ncoef(p);
@@ -44,7 +51,8 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   lay->flags = take(sizeof(int32_t) * 4);
   lay->energy_part = take(sizeof(double) * (size_t)lay->n_energy_part);
   lay->bbox = take(sizeof(double) * 6 * 1024);
-  lay->zero_row = take(sizeof(double) * (size_t)mstride(p));
+  const int np = m2l_pieces(cfg);
+  lay->zero_row = take(zero_row_bytes(p, np));
   lay->keys = take(sizeof(uint32_t) * N);
   lay->perm = take(sizeof(int32_t) * N);
   lay->perm_tmp = take(sizeof(int32_t) * N);
@@ -73,7 +81,12 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     const size_t el = mixed ? sizeof(float) : sizeof(double);
     const size_t opsz = (size_t)kNumM2LOps * m2l_rows_pad(p) * m2l_kstride_of(nc, (int)el);
     lay->op_m2l64 = mixed ? 0 : take(sizeof(double) * opsz);
-    lay->op_m2l32 = mixed ? take(sizeof(float) * opsz) : 0;
+    lay->op_m2l32 = (mixed && !np) ? take(sizeof(float) * opsz) : 0;
+    if (np) {
+      const size_t rq = (size_t)m2lb_row_quads(nc, np);
+      lay->multb = take(16 * NB * rq);
+      lay->op_m2lb = take(16 * (size_t)kNumM2LOps * m2l_rows_pad(p) * (rq + 1));
+    }
   }
   lay->work = take(sizeof(int64_t) * 2);
   lay->total = cur;
@@ -107,9 +120,9 @@ static fmm_status validate_config(const fmm_config* cfg) {
   if (cfg->ws != 1) return FMM_E_INVALID_ARG;
   if (cfg->leaf_max != 0) return FMM_E_UNSUPPORTED;
   if (cfg->precision != FMM_PREC_FP64 && cfg->precision != FMM_PREC_MIXED) return FMM_E_INVALID_ARG;
-  if (cfg->m2l_kind < FMM_M2L_AUTO || cfg->m2l_kind > FMM_M2L_F32) return FMM_E_INVALID_ARG;
+  if (cfg->m2l_kind < FMM_M2L_AUTO || cfg->m2l_kind > FMM_M2L_BF16X3) return FMM_E_INVALID_ARG;
   if (cfg->m2l_kind == FMM_M2L_F64 && cfg->precision != FMM_PREC_FP64) return FMM_E_UNSUPPORTED;
-  if (cfg->m2l_kind == FMM_M2L_F32 && cfg->precision != FMM_PREC_MIXED) return FMM_E_UNSUPPORTED;
+  if (cfg->m2l_kind >= FMM_M2L_F32 && cfg->precision != FMM_PREC_MIXED) return FMM_E_UNSUPPORTED;
   for (int a = 0; a < 3; ++a)
     if (!(cfg->root_lo[a] == cfg->root_lo[a]) || cfg->root_lo[a] - cfg->root_lo[a] != 0.0)
       return FMM_E_INVALID_ARG;  // NaN or infinite corner
@@ -167,6 +180,7 @@ fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void*
   P->p = cfg->p;
   P->nc = ncoef(cfg->p);
   P->mixed = cfg->precision == FMM_PREC_MIXED;
+  P->m2l_np = m2l_pieces(*cfg);
   P->ws = static_cast<char*>(d_workspace);
   P->last_stream = reinterpret_cast<hipStream_t>(stream);
   P->rec = static_cast<ProfileRec*>(calloc(kMaxProfile, sizeof(ProfileRec)));

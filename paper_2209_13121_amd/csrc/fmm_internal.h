@@ -40,6 +40,21 @@ __host__ __device__ constexpr int m2l_kstride_of(int nc, int elem) {
   return (16 / elem) * (4 * ((nc + 4 * (16 / elem) - 1) / (4 * (16 / elem))) + 1);
 }
 
+// Split-BF16 M2L: k runs in steps of 32 (16x16x32 BF16 MFMA), each split into
+// 4 lane groups of 8; a row of an operator or a source box holds, for every
+// k step and piece, 4 16-byte quads: quad (ks * np + piece) * 4 + g covers
+// k = 32 ks + 8 g + j, j = 0..7 (zero past ncoef).
+__host__ __device__ constexpr int m2lb_ksteps(int nc) { return (nc + 31) / 32; }
+__host__ __device__ constexpr int m2lb_row_quads(int nc, int np) { return m2lb_ksteps(nc) * np * 4; }
+
+// Bytes of the all-zero source row that M2L reads outside the domain (large
+// enough for the FP64, FP32 and split-BF16 row forms).
+inline size_t zero_row_bytes(int p, int np) {
+  const size_t zb = sizeof(double) * (size_t)mstride(p);
+  const size_t zq = (size_t)16 * m2lb_row_quads(ncoef(p), np ? np : 1);
+  return zb > zq ? zb : zq;
+}
+
 struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t params, flags, energy_part, bbox, zero_row;
   size_t keys, perm, perm_tmp, sorted_leaf;
@@ -54,6 +69,8 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t leaf_loc32;       // leaf local expansions FP32 (mixed; row stride mstride)
   size_t op_m2m, op_l2l;   // 8 padded operators each, FP64
   size_t op_m2l64, op_m2l32;
+  size_t multb;            // split-BF16 M2L: multipoles as BF16 pieces, all boxes
+  size_t op_m2lb;          // split-BF16 M2L: operators as BF16 pieces
   size_t work;             // 2 x int64 counters
   size_t total;
   int64_t n, nleaf, nbox, n_energy_part, scan_tmp_elems;
@@ -61,6 +78,8 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
 };
 
 bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay);
+// BF16 pieces per operand of the M2L (2 or 3), or 0 for FP32/FP64 MFMA.
+int m2l_pieces(const fmm_config& cfg);
 
 struct ProfileRec {
   int phase;
@@ -75,6 +94,7 @@ struct fmm_plan_s {
   int64_t n;
   int L, p, nc;
   bool mixed;
+  int m2l_np;  // m2l_pieces(cfg)
   char* ws;
   hipStream_t last_stream;
   bool has_charges;  // fmm_evaluate has run: sorted charges are in the workspace
@@ -101,6 +121,7 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s);
 hipError_t launch_operators(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_upward(fmm_plan_s* P, const double* d_q, hipStream_t s);
 hipError_t launch_m2l(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_m2l_bf16(fmm_plan_s* P, hipStream_t s);  // split-BF16 form (P->m2l_np > 0)
 hipError_t launch_m2m(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_l2l(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_downward(fmm_plan_s* P, hipStream_t s);

@@ -355,7 +355,7 @@ struct M2LRun {
 
 hipError_t launch_m2l(fmm_plan_s* P, hipStream_t s) {
   prof_begin(P, FMM_PHASE_M2L, s);
-  hipError_t e = dispatch_p<M2LRun>(P->p, P, s);
+  hipError_t e = P->m2l_np ? launch_m2l_bf16(P, s) : dispatch_p<M2LRun>(P->p, P, s);
   prof_end(P, s);
   return e;
 }

@@ -1,0 +1,300 @@
+// m2l_bf16.hip -- multipole-to-local translation on the BF16 matrix cores
+// with split operands (mixed precision).
+//
+// Same operation and work decomposition as m2l.hip (m2l_common.h): per
+// parity class and offset d a dense product L~[:, targets] += T_d M~[:, targets - d].
+// Every operand x is carried as np BF16 pieces, x = x0 + x1 (+ x2):
+// x0 = bf16(x), x1 = bf16(x - x0), x2 = bf16(x - x0 - x1), each rounded to
+// nearest even.  For an FP32 value three pieces are exact (8 + 8 + 8
+// significant bits).  A product a b is taken as the sum of the piece products
+// a_i b_j with i + j < np (6 of 9 for np = 3: the dropped ones are below
+// 2^-24 relative; 3 of 4 for np = 2: about 2^-16).  Each piece product of a
+// 16 x 32 operator block and a 32 x 16 source block is one
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation; the matrix cores run BF16
+// at 16 times the FP32 rate, so np = 3 needs 6 / 16 of the FP32 issue time.
+//
+//  * Operand layout (16-byte quads of 8 BF16): a row of an operator or a
+//    source box holds quad (ks * np + piece) * 4 + g = k values 32 ks + 8 g ..
+//    + 7 of that piece, zero past ncoef; lane (col, g) of the MFMA reads
+//    exactly one quad per (k step, piece) for A and for B.
+//  * Operators: [op][row (16-row blocks)][quads + 1] (the extra zero quad
+//    makes the stride odd), generated once per plan from FP64 entries and
+//    staged in LDS per offset in k-step chunks, double-buffered.
+//  * Sources: the FP32 multipoles of every level, split once per evaluation
+//    into BF16 pieces (k_split_mult) so the M2L loop only loads quads.
+//  * Accumulation: each offset's product is a fresh FP32 chain (smallest
+//    piece products first); the chains are summed across offsets with Kahan
+//    compensation, as in the FP32 form.
+#include "bf16_split.h"
+#include "m2l_common.h"
+
+namespace fmm {
+namespace {
+
+using m2l::kThreads;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLdsBudget = 140 * 1024;  // two operator buffers (plus the slot halo)
+
+// Piece products (a piece, b piece) with i + j < NP, smallest first.
+template <int NP>
+struct Prod;
+template <>
+struct Prod<3> {
+  static constexpr int N = 6;
+  static constexpr int a[6] = {1, 0, 2, 0, 1, 0};
+  static constexpr int b[6] = {1, 2, 0, 1, 0, 0};
+};
+template <>
+struct Prod<2> {
+  static constexpr int N = 3;
+  static constexpr int a[3] = {0, 1, 0};
+  static constexpr int b[3] = {1, 0, 0};
+};
+
+// Split every box's FP32 multipole row (stride ms) of levels 2..L into pieces:
+// one thread per (box, k step, lane group g) writes the NP quads of its 8 k values.
+template <int NP>
+__global__ void k_split_mult(const float* __restrict__ m32, int ms, int nc, int kst, int64_t nbox,
+                             u32x4* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nbox * kst * 4) return;
+  const int64_t box = t / (kst * 4);
+  const int ks = (int)(t / 4 % kst), g = (int)(t % 4);
+  const float* row = m32 + box * ms;
+  uint32_t pc[8][NP];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = 32 * ks + 8 * g + j;
+    split_f32<NP>(k < nc ? row[k] : 0.0f, pc[j]);
+  }
+  u32x4 q[NP];
+  pack_quads<NP>(pc, q);
+  u32x4* o = out + box * (kst * NP * 4);
+#pragma unroll
+  for (int i = 0; i < NP; ++i) o[(ks * NP + i) * 4 + g] = q[i];
+}
+
+// Shape of the kernel for order P and NP pieces.
+template <int P, int NP>
+struct Shape {
+  static constexpr int NC = (P + 1) * (P + 1);
+  static constexpr int RB = (NC + 15) / 16;  // 16-row blocks
+  static constexpr int RP = RB * 16;
+  static constexpr int KST = m2lb_ksteps(NC);       // 32-wide k steps
+  static constexpr int QR = m2lb_row_quads(NC, NP);  // quads per row (= per source box)
+  static constexpr int QRS = QR + 1;                 // global operator row stride
+  // k steps per staged chunk: as many as fit two LDS buffers
+  static constexpr int fit_kc(int n) {
+    return n <= 1 ? 1 : (2 * RP * (n * NP * 4 + 1) * 16 <= kLdsBudget ? n : fit_kc(n - 1));
+  }
+  static constexpr int KC = fit_kc(KST);
+  static constexpr int NCH = (KST + KC - 1) / KC;  // chunks per operator
+  static constexpr int QC = KC * NP * 4;           // quads per row per chunk
+  static constexpr int QCS = QC + 1;               // LDS row stride (odd)
+  static constexpr int NV = RP * QC;               // quads per chunk
+  static constexpr int PER_THREAD = (NV + kThreads - 1) / kThreads;
+  static constexpr int RG = RB < 3 ? RB : 3;       // row blocks interleaved per A load
+  // Prefetch the next offset's B quads (a second register set) where the
+  // registers allow it.
+  static constexpr bool PREFETCH_B = KST * NP <= 9;
+};
+
+template <int P, int NP>
+__global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* __restrict__ multq,
+                                                     const u32x4* __restrict__ zero_q,
+                                                     const u32x4* __restrict__ ops,
+                                                     float* __restrict__ out) {
+  typedef Shape<P, NP> S;
+  typedef Prod<NP> PR;
+  constexpr int NC = S::NC, RB = S::RB, RP = S::RP, KST = S::KST, QR = S::QR, QRS = S::QRS;
+  constexpr int KC = S::KC, NCH = S::NCH, QC = S::QC, QCS = S::QCS, RG = S::RG;
+  __shared__ u32x4 sT[2][RP * QCS];
+  __shared__ uint32_t sSlot[m2l::kHalo];
+  __shared__ int sBox[6];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kg = lane >> 4;
+  m2l::Tile tl;
+  if (!tl.setup(a, wave, col, sSlot, sBox)) return;  // uniform over the work-group
+  const int pi = tl.pi;
+  const u32x4* mlev = multq + tl.lvl_off * QR;
+
+  f32x4 sum[RB], comp[RB], acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) sum[r] = comp[r] = acc[r] = f32x4{0, 0, 0, 0};
+
+  // Operator chunk ch of operator op into registers / into an LDS buffer.
+  // Quad e of a chunk is row e / QC, quad e % QC; quads past the stored row
+  // (a partial last chunk) read the row's zero pad quad.
+  auto stage_load = [&](int op, int ch, u32x4* reg) {
+    const u32x4* base = ops + (size_t)op * RP * QRS;
+#pragma unroll
+    for (int i = 0; i < S::PER_THREAD; ++i) {
+      int e = tid + i * kThreads;
+      e = e < S::NV ? e : S::NV - 1;
+      const int row = e / QC;
+      int q = ch * QC + e % QC;
+      q = q < QR ? q : QR;
+      reg[i] = base[row * QRS + q];
+    }
+  };
+  auto stage_store = [&](u32x4* buf, const u32x4* reg) {
+#pragma unroll
+    for (int i = 0; i < S::PER_THREAD; ++i) {
+      const int e = tid + i * kThreads;
+      if (e < S::NV) buf[(e / QC) * QCS + e % QC] = reg[i];
+    }
+  };
+  auto row_of = [&](m2l::Src src) -> const u32x4* {
+    return src.ok ? mlev + (int64_t)src.slot * QR : zero_q;
+  };
+  // B quads of a source row: this lane group's quad of every (k step, piece).
+  auto load_b = [&](const u32x4* ms, u32x4* b) {
+#pragma unroll
+    for (int i = 0; i < KST * NP; ++i) b[i] = ms[i * 4 + kg];
+  };
+  // MFMAs of operator chunk ch (staged in buf) against B quads b.
+  auto compute_chunk = [&](const u32x4* buf, int ch, const u32x4* b) {
+    const u32x4* sa = buf + col * QCS + kg;
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc) {
+      const int ks = ch * KC + kc;
+      if (ks >= KST) break;
+#pragma unroll
+      for (int r0 = 0; r0 < RB; r0 += RG) {
+        u32x4 av[RG][NP];
+#pragma unroll
+        for (int rr = 0; rr < RG; ++rr)
+#pragma unroll
+          for (int i = 0; i < NP; ++i)
+            if (r0 + rr < RB) av[rr][i] = sa[16 * (r0 + rr) * QCS + (kc * NP + i) * 4];
+#pragma unroll
+        for (int t = 0; t < PR::N; ++t)
+#pragma unroll
+          for (int rr = 0; rr < RG; ++rr)
+            if (r0 + rr < RB)
+              acc[r0 + rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                  __builtin_bit_cast(bf16x8, av[rr][PR::a[t]]),
+                  __builtin_bit_cast(bf16x8, b[ks * NP + PR::b[t]]), acc[r0 + rr], 0, 0, 0);
+      }
+    }
+  };
+
+  constexpr bool PB = S::PREFETCH_B;
+  u32x4 reg[S::PER_THREAD];
+  u32x4 b0[KST * NP], b1[PB ? KST * NP : 1];
+  // Pipeline over the class's offsets: offset i is computed while the
+  // operator of the next stage and the B quads of offset i + 1 are loaded and
+  // the source slot of offset i + 2 is looked up.
+  int i = 0, dx, dy, dz, ndx, ndy, ndz;
+  int op = m2l::il_offset(pi, 0, dx, dy, dz);
+  int nop = m2l::il_offset(pi, 1, ndx, ndy, ndz);
+  m2l::Src s_cur = tl.lookup(sSlot, dx, dy, dz);
+  m2l::Src s_next = tl.lookup(sSlot, ndx, ndy, ndz);
+  bool wave_any = false;
+  if (PB) {
+    load_b(row_of(s_cur), b0);
+    wave_any = __any(s_cur.ok);
+  }
+  stage_load(op, 0, reg);
+  stage_store(sT[0], reg);
+  __syncthreads();
+  int cur = 0;
+
+  auto do_offset = [&](u32x4* bc, u32x4* bn) -> bool {
+    const bool more = i + 1 < kIL;
+    int fdx, fdy, fdz;
+    const int fop = m2l::il_offset(pi, i + 2 < kIL ? i + 2 : kIL - 1, fdx, fdy, fdz);
+    const m2l::Src s_far = tl.lookup(sSlot, fdx, fdy, fdz);
+    if (!PB) {
+      load_b(row_of(s_cur), bc);
+      wave_any = __any(s_cur.ok);
+    }
+#pragma unroll
+    for (int ch = 0; ch < NCH; ++ch) {
+      const bool last_chunk = ch == NCH - 1;
+      stage_load(last_chunk ? (more ? nop : op) : op, last_chunk ? 0 : ch + 1, reg);
+      if (PB && ch == 0) load_b(row_of(s_next), bn);
+      if (wave_any) compute_chunk(sT[cur], ch, bc);
+      if (last_chunk && wave_any) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const f32x4 y = acc[r] - comp[r];
+          const f32x4 t = sum[r] + y;
+          comp[r] = (t - sum[r]) - y;
+          sum[r] = t;
+          acc[r] = f32x4{0, 0, 0, 0};
+        }
+      }
+      if (last_chunk && !more) return false;
+      stage_store(sT[cur ^ 1], reg);
+      __syncthreads();
+      cur ^= 1;
+    }
+    ++i;
+    op = nop;
+    dx = ndx;
+    dy = ndy;
+    dz = ndz;
+    nop = fop;
+    ndx = fdx;
+    ndy = fdy;
+    ndz = fdz;
+    if (PB) wave_any = __any(s_next.ok);
+    s_cur = s_next;
+    s_next = s_far;
+    return true;
+  };
+  if (PB) {
+    while (do_offset(b0, b1) && do_offset(b1, b0)) {
+    }
+  } else {
+    while (do_offset(b0, b0)) {
+    }
+  }
+
+  if (!tl.col_ok) return;
+  float* o = out + (tl.lvl_off + tl.target_slot(a)) * NC;
+  // Accumulator layout of the 16x16 FP32-output MFMAs: lane l holds column
+  // l % 16, rows 4 (l / 16) + i.
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * r + 4 * kg + e;
+      if (row < NC) o[row] = sum[r][e];
+    }
+}
+
+template <int P>
+struct M2LBfRun {
+  template <int NP>
+  static hipError_t go(fmm_plan_s* Pl, hipStream_t s) {
+    const Layout& lay = Pl->lay;
+    const int nc = Pl->nc, kst = m2lb_ksteps(nc);
+    // split the multipoles of levels 2..L (levels 0, 1 have no M2L)
+    const int64_t box0 = lay.lvl_off[2], nbox = lay.nbox - box0;
+    u32x4* mq = wsp<u32x4>(Pl, lay.multb);
+    const int qr = m2lb_row_quads(nc, NP);
+    k_split_mult<NP><<<grid_for(nbox * kst * 4, kBlock), kBlock, 0, s>>>(
+        wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox,
+        mq + box0 * qr);
+    const m2l::Args a = m2l::make_args(Pl);
+    k_m2l_bf<P, NP><<<m2l::grid_of(a), kThreads, 0, s>>>(a, mq, wsp<u32x4>(Pl, lay.zero_row),
+                                                        wsp<u32x4>(Pl, lay.op_m2lb),
+                                                        wsp<float>(Pl, lay.m2l_out));
+    return hipGetLastError();
+  }
+  static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
+    return Pl->m2l_np == 2 ? go<2>(Pl, s) : go<3>(Pl, s);
+  }
+};
+
+}  // namespace
+
+hipError_t launch_m2l_bf16(fmm_plan_s* P, hipStream_t s) { return dispatch_p<M2LBfRun>(P->p, P, s); }
+
+}  // namespace fmm

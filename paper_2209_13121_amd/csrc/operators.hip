@@ -21,7 +21,7 @@
 // [octant][input k (padded to KP)][output row (padded to RP)]; M2L, 316
 // offsets in the M2L precision, stored [offset][output row (padded to RP)]
 // [input k (stride m2l_kstride_of)].
-#include "fmm_internal.h"
+#include "bf16_split.h"
 
 namespace fmm {
 namespace {
@@ -225,6 +225,40 @@ __global__ void k_gen_m2l(int p, int rp, int ks, T* __restrict__ ops) {
   }
 }
 
+// Operators in pieces: one thread per (operator row, k step, lane group)
+// computes its 8 FP64 entries and writes their NP quads; the last thread of
+// a row also writes the zero pad quad.
+template <int NP>
+__global__ void k_gen_m2l_bf(int p, int rp, u32x4* __restrict__ ops) {
+  __shared__ double tre[kTabMax], tim[kTabMax];
+  const int op = blockIdx.x;
+  if ((int)threadIdx.x <= 2 * p) {
+    int o[3];
+    m2l_offset(op, o);
+    // o is the target-minus-source offset (c_t - c_s)/h
+    irregular_column((double)o[0], (double)o[1], (double)o[2], 2 * p, threadIdx.x, tre, tim);
+  }
+  __syncthreads();
+  const int nc = (p + 1) * (p + 1);
+  const int kst = m2lb_ksteps(nc), qr = m2lb_row_quads(nc, NP);
+  u32x4* out = ops + (size_t)op * rp * (qr + 1);
+  for (int e = threadIdx.x; e < rp * kst * 4; e += blockDim.x) {
+    const int row = e / (kst * 4), ks = e / 4 % kst, g = e % 4;
+    uint32_t pc[8][NP];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 32 * ks + 8 * g + j;
+      split_f64<NP>((k < nc && row < nc) ? m2l_entry(p, row, k, tre, tim) : 0.0, pc[j]);
+    }
+    u32x4 q[NP];
+    pack_quads<NP>(pc, q);
+    u32x4* o = out + (size_t)row * (qr + 1);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) o[(ks * NP + i) * 4 + g] = q[i];
+    if (ks == kst - 1 && g == 3) o[qr] = u32x4{0, 0, 0, 0};
+  }
+}
+
 }  // namespace
 
 hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
@@ -233,7 +267,11 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
   const int kp = m2l_k_pad(P->p), rp = m2l_rows_pad(P->p);
   k_gen_shift<<<16, kBlock, 0, s>>>(P->p, kp, rp, wsp<double>(P, lay.op_m2m),
                                     wsp<double>(P, lay.op_l2l));
-  if (P->mixed)
+  if (P->m2l_np == 2)
+    k_gen_m2l_bf<2><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, wsp<u32x4>(P, lay.op_m2lb));
+  else if (P->m2l_np == 3)
+    k_gen_m2l_bf<3><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, wsp<u32x4>(P, lay.op_m2lb));
+  else if (P->mixed)
     k_gen_m2l<float><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, m2l_kstride_of(P->nc, 4),
                                                    wsp<float>(P, lay.op_m2l32));
   else

@@ -325,7 +325,7 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
   }
   k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(count, lay.nleaf, 0u);
   {  // the zero row M2L reads for sources outside the domain
-    const int64_t words = 2 * (int64_t)mstride(P->p);
+    const int64_t words = (int64_t)(zero_row_bytes(P->p, P->m2l_np) / 4);
     k_fill_u32<<<grid_for(words, kBlock), kBlock, 0, s>>>(wsp<uint32_t>(P, lay.zero_row), words, 0u);
   }
   k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(fill, lay.nleaf, 0u);

@@ -21,13 +21,13 @@ def device():
 
 
 def run_gpu(pos, q, depth, p, precision=B.FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
-            check=True):
+            check=True, m2l_kind=B.FMM_M2L_AUTO):
     """Plan + evaluate on the GPU; returns numpy (phi, force, energy, status)."""
     import torch
     dev = device()
     tp = torch.from_numpy(np.ascontiguousarray(pos, dtype=np.float64)).to(dev)
     tq = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float64)).to(dev)
-    f = B.FMM(tp, p=p, depth=depth, precision=precision, lo=lo, side=side)
+    f = B.FMM(tp, p=p, depth=depth, precision=precision, lo=lo, side=side, m2l_kind=m2l_kind)
     phi, force, energy = f.evaluate(tq)
     st = f.check()
     torch.cuda.synchronize()

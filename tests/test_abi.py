@@ -45,16 +45,32 @@ def test_config_validation(lib):
         with pytest.raises(B.FMMError) as ei:
             B.fmm_workspace_size(cfg, n)
         assert ei.value.status == code, (field, bad)
-    cfg = B.make_config(precision=B.FMM_PREC_MIXED, m2l_kind=B.FMM_M2L_F64)
-    with pytest.raises(B.FMMError) as ei:
-        B.fmm_workspace_size(cfg, n)
-    assert ei.value.status == 6
+    for prec, kind in [(B.FMM_PREC_MIXED, B.FMM_M2L_F64), (B.FMM_PREC_FP64, B.FMM_M2L_F32),
+                       (B.FMM_PREC_FP64, B.FMM_M2L_BF16X2), (B.FMM_PREC_FP64, B.FMM_M2L_BF16X3)]:
+        cfg = B.make_config(precision=prec, m2l_kind=kind)
+        with pytest.raises(B.FMMError) as ei:
+            B.fmm_workspace_size(cfg, n)
+        assert ei.value.status == 6, (prec, kind)
     cfg = B.make_config(side=float("nan"))
     with pytest.raises(B.FMMError):
         B.fmm_workspace_size(cfg, n)
     for bad_n in (0, -5, 2**31):
         with pytest.raises(B.FMMError):
             B.fmm_workspace_size(B.make_config(), bad_n)
+
+
+def test_split_bf16_workspace(lib):
+    # The split-BF16 M2L keeps BF16 pieces of every multipole and operator in
+    # place of the FP32 operators: 3 pieces need more room than 2.
+    n = 4096
+    for p in (0, 4, 8, 12):
+        f32 = B.fmm_workspace_size(B.make_config(depth=3, p=p, precision=B.FMM_PREC_MIXED,
+                                                 m2l_kind=B.FMM_M2L_F32), n)
+        x2 = B.fmm_workspace_size(B.make_config(depth=3, p=p, precision=B.FMM_PREC_MIXED,
+                                                m2l_kind=B.FMM_M2L_BF16X2), n)
+        x3 = B.fmm_workspace_size(B.make_config(depth=3, p=p, precision=B.FMM_PREC_MIXED,
+                                                m2l_kind=B.FMM_M2L_BF16X3), n)
+        assert f32 > 0 and x3 > x2, p
 
 
 def test_workspace_size_monotone(lib):

@@ -121,15 +121,24 @@ MIXED_CASES = [
     ("n30000-L4-p8", 30000, "gauss", 41, 4, 8),
     ("n8000-L3-p10", 8000, "pm1", 42, 3, 10),
     ("n2000-L2-p6", 2000, "gauss", 43, 2, 6),
+    ("n3000-L3-p1", 3000, "pm1", 44, 3, 1),
+    ("n3000-L3-p12", 3000, "gauss", 45, 3, 12),
 ]
 
 
+MIXED_KINDS = {"f32": B.FMM_M2L_F32, "bf16x3": B.FMM_M2L_BF16X3, "auto": B.FMM_M2L_AUTO}
+
+
+@pytest.mark.parametrize("kind", sorted(MIXED_KINDS))
 @pytest.mark.parametrize("case", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
-def test_mixed_within_gate(case):
+def test_mixed_within_gate(case, kind):
+    # Three BF16 pieces reproduce FP32 operands exactly and the dropped piece
+    # products are below 2^-24 relative: both M2L forms share the FP32 gate.
     name, n, charges, seed, depth, p = case
-    log(f"[mixed] {name}")
+    log(f"[mixed {kind}] {name}")
     pos, q = make(n, charges, seed)
-    phi, force, e, _ = run_gpu(pos, q, depth, p, precision=B.FMM_PREC_MIXED)
+    phi, force, e, _ = run_gpu(pos, q, depth, p, precision=B.FMM_PREC_MIXED,
+                               m2l_kind=MIXED_KINDS[kind])
     phi_o, force_o, e_o = oracle.fmm(pos, q, depth, p)
     log(f"  dE {energy_rel(e, e_o):.2e} dF {rel(force, force_o):.2e} dphi {rel(phi, phi_o):.2e}")
     assert energy_rel(e, e_o) <= 1e-6
@@ -138,11 +147,28 @@ def test_mixed_within_gate(case):
     assert energy_rel(e, half_sum_q_phi(q, phi)) <= 1e-13
 
 
-def test_headline_mixed_sampled():
+def test_mixed_bf16x2_accuracy():
+    # Two pieces carry about 16 significant bits per product: a documented
+    # looser mode, checked against its own bound (about 2^-16 of the far field).
+    n, depth, p = 30000, 4, 8
+    log("[mixed bf16x2] n30000-L4-p8")
+    pos, q = make(n, "gauss", 41)
+    phi, force, e, _ = run_gpu(pos, q, depth, p, precision=B.FMM_PREC_MIXED,
+                               m2l_kind=B.FMM_M2L_BF16X2)
+    phi_o, force_o, e_o = oracle.fmm(pos, q, depth, p)
+    log(f"  dE {energy_rel(e, e_o):.2e} dF {rel(force, force_o):.2e} dphi {rel(phi, phi_o):.2e}")
+    assert rel(phi, phi_o) <= 1e-4
+    assert rel(force, force_o) <= 1e-4
+    assert energy_rel(e, e_o) <= 1e-4
+
+
+@pytest.mark.parametrize("kind", ["f32", "bf16x3"])
+def test_headline_mixed_sampled(kind):
     wl = W.HEADLINE
-    log(f"[mixed] {wl.name} (sampled)")
+    log(f"[mixed {kind}] {wl.name} (sampled)")
     pos, q = wl.make()
-    phi, force, e, _ = run_gpu(pos, q, wl.depth, wl.p, precision=B.FMM_PREC_MIXED)
+    phi, force, e, _ = run_gpu(pos, q, wl.depth, wl.p, precision=B.FMM_PREC_MIXED,
+                               m2l_kind=MIXED_KINDS[kind])
     t = np.random.default_rng(6).choice(wl.n, 512, replace=False)
     phi_o, force_o, _ = oracle.fmm(pos, q, wl.depth, wl.p, targets=t)
     log(f"  sampled dF {rel(force[t], force_o):.2e} dphi {rel(phi[t], phi_o):.2e}")
@@ -156,12 +182,14 @@ def test_headline_mixed_sampled():
         assert energy_rel(e, ref["energy"]) <= 1e-6
 
 
-@pytest.mark.parametrize("precision", [B.FMM_PREC_FP64, B.FMM_PREC_MIXED])
-def test_deterministic(precision):
-    log(f"[determinism] precision {precision}")
+@pytest.mark.parametrize("precision,kind", [(B.FMM_PREC_FP64, B.FMM_M2L_AUTO),
+                                            (B.FMM_PREC_MIXED, B.FMM_M2L_F32),
+                                            (B.FMM_PREC_MIXED, B.FMM_M2L_BF16X3)])
+def test_deterministic(precision, kind):
+    log(f"[determinism] precision {precision} m2l {kind}")
     pos, q = W.uniform_gauss(50000, 51)
-    a = run_gpu(pos, q, 4, 6, precision=precision)
-    b = run_gpu(pos, q, 4, 6, precision=precision)
+    a = run_gpu(pos, q, 4, 6, precision=precision, m2l_kind=kind)
+    b = run_gpu(pos, q, 4, 6, precision=precision, m2l_kind=kind)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
 
 
