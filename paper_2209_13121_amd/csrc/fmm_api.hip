@@ -75,7 +75,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     lay->m2l_out = take((mixed ? sizeof(float) : sizeof(double)) * NB * nce);
     lay->loc_exp64 = take(sizeof(double) * NB * ms);
     lay->leaf_loc32 = mixed ? take(sizeof(float) * NL * ms) : 0;
-    const size_t tile = (size_t)m2l_k_pad(p) * m2l_rows_pad(p);
+    const size_t tile = (size_t)shift_kpad(nc) * m2l_rows_pad(p);
     lay->op_m2m = take(sizeof(double) * 8 * tile);
     lay->op_l2l = take(sizeof(double) * 8 * tile);
     const size_t el = mixed ? sizeof(float) : sizeof(double);
@@ -85,7 +85,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     if (np) {
       const size_t rq = (size_t)m2lb_row_quads(nc, np);
       lay->multb = take(16 * NB * rq);
-      lay->op_m2lb = take(16 * (size_t)kNumM2LOps * m2l_rows_pad(p) * (rq + 1));
+      lay->op_m2lb = take(16 * (size_t)kNumM2LOps * m2lb_op_quads(nc, np));
     }
   }
   lay->work = take(sizeof(int64_t) * 2);

@@ -32,6 +32,9 @@ inline int mstride(int p) { return mstride_of(ncoef(p)); }
 // Operator tile sizes: rows padded to 16-row MFMA blocks, K to 4-deep steps.
 inline int m2l_rows_pad(int p) { return ((ncoef(p) + 15) / 16) * 16; }
 inline int m2l_k_pad(int p) { return ((ncoef(p) + 3) / 4) * 4; }
+// M2M / L2L octant operators are stored [octant][row (16-row blocks)][k], k
+// padded to a multiple of 8 (zero).
+__host__ __device__ constexpr int shift_kpad(int nc) { return ((nc + 7) / 8) * 8; }
 // M2L operators are stored [row][k] with k-stride V (4 V nq + 1) elements, V
 // the elements per 16-byte vector and nq = ceil(ncoef / 4V): every 16-byte
 // k-quad a lane reads is inside the row (zero padded), and the odd quad stride
@@ -41,11 +44,34 @@ __host__ __device__ constexpr int m2l_kstride_of(int nc, int elem) {
 }
 
 // Split-BF16 M2L: k runs in steps of 32 (16x16x32 BF16 MFMA), each split into
-// 4 lane groups of 8; a row of an operator or a source box holds, for every
-// k step and piece, 4 16-byte quads: quad (ks * np + piece) * 4 + g covers
-// k = 32 ks + 8 g + j, j = 0..7 (zero past ncoef).
+// 4 lane groups g of 8 k values (k = 32 ks + 8 g + j, zero past ncoef).
+//  * A source box holds quad (ks * np + piece) * 4 + g for every k step and
+//    piece (m2lb_row_quads quads).
+//  * An operator is stored in chunks of kc k steps (as many as two LDS
+//    buffers hold), each chunk [row][g][k step][piece] with the g blocks gq
+//    quads apart (gq = kc * np made odd) and rows 4 gq + 2 quads apart.  A
+//    16-byte LDS read serves 32 lanes at a time and is free of bank conflicts
+//    when their quads are distinct modulo 32: 16 rows at a stride of 2 mod 4
+//    fill the even residues and the odd g offset the odd ones.
 __host__ __device__ constexpr int m2lb_ksteps(int nc) { return (nc + 31) / 32; }
 __host__ __device__ constexpr int m2lb_row_quads(int nc, int np) { return m2lb_ksteps(nc) * np * 4; }
+constexpr int kM2lbLdsBudget = 140 * 1024;  // two operator chunk buffers
+__host__ __device__ constexpr int m2lb_gq(int kc, int np) { return (kc * np) | 1; }
+__host__ __device__ constexpr int m2lb_qcs(int kc, int np) { return 4 * m2lb_gq(kc, np) + 2; }
+__host__ __device__ constexpr int m2lb_rows(int nc) { return ((nc + 15) / 16) * 16; }
+__host__ __device__ constexpr int m2lb_kc_fit(int nc, int np, int n) {
+  return n <= 1 ? 1
+                : (2 * m2lb_rows(nc) * m2lb_qcs(n, np) * 16 <= kM2lbLdsBudget ? n
+                                                                            : m2lb_kc_fit(nc, np, n - 1));
+}
+__host__ __device__ constexpr int m2lb_kc(int nc, int np) { return m2lb_kc_fit(nc, np, m2lb_ksteps(nc)); }
+__host__ __device__ constexpr int m2lb_nch(int nc, int np) {
+  return (m2lb_ksteps(nc) + m2lb_kc(nc, np) - 1) / m2lb_kc(nc, np);
+}
+// Quads of one operator (all chunks).
+__host__ __device__ constexpr int m2lb_op_quads(int nc, int np) {
+  return m2lb_nch(nc, np) * m2lb_rows(nc) * m2lb_qcs(m2lb_kc(nc, np), np);
+}
 
 // Bytes of the all-zero source row that M2L reads outside the domain (large
 // enough for the FP64, FP32 and split-BF16 row forms).
@@ -67,7 +93,7 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t m2l_out;          // M2L results, all levels (compute precision)
   size_t loc_exp64;        // local expansions FP64, all levels (row stride mstride)
   size_t leaf_loc32;       // leaf local expansions FP32 (mixed; row stride mstride)
-  size_t op_m2m, op_l2l;   // 8 padded operators each, FP64
+  size_t op_m2m, op_l2l;   // 8 octant operators each, FP64 [oct][row][k] (shift_kpad)
   size_t op_m2l64, op_m2l32;
   size_t multb;            // split-BF16 M2L: multipoles as BF16 pieces, all boxes
   size_t op_m2lb;          // split-BF16 M2L: operators as BF16 pieces
@@ -117,6 +143,7 @@ void prof_begin(fmm_plan_s* P, int phase, hipStream_t s);
 void prof_end(fmm_plan_s* P, hipStream_t s);
 
 // ---- passes (each file defines its launchers) ------------------------------
+hipError_t fill_u32(uint32_t* a, int64_t n, uint32_t v, hipStream_t s);  // a[0..n) = v
 hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s);
 hipError_t launch_operators(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_upward(fmm_plan_s* P, const double* d_q, hipStream_t s);

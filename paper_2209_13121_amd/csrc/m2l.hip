@@ -17,12 +17,12 @@
 //  * K order: lane group g at sub-step s of k-quad chunk q works on
 //    k = 4V q + V g + s (V elements per 16-byte vector), so each lane's A and B
 //    values for a chunk are one 16-byte vector each.
-//  * A operand (operator rows): T_d is stored [row][k] with an odd stride in
-//    16-byte quads and staged in LDS (double-buffered across offsets: the next
-//    operator's global loads are in flight while the current one feeds the
-//    MFMAs); one ds_read_b128 gives a lane its V values of a 16-row block, and
-//    the reads of chunk q+1 are issued before the MFMAs of chunk q.  All 128
-//    targets share each staged operator.
+//  * A operand (operator rows): T_d is stored [row][k] and staged in LDS
+//    (double-buffered across offsets: the next operator's global loads are in
+//    flight while the current one feeds the MFMAs) in a row layout free of
+//    LDS bank conflicts (see Shape); one ds_read_b128 gives a lane its V
+//    values of a 16-row block, and the reads of chunk q+1 are issued before
+//    the MFMAs of chunk q.  All 128 targets share each staged operator.
 //  * B operand (source coefficients): 16-byte vectors from global memory; a
 //    whole offset's vectors are prefetched while the previous offset's MFMAs
 //    run (two register sets used alternately) where the registers allow.
@@ -110,13 +110,31 @@ struct Shape {
   static constexpr int S_LAST = NC - G * (NQ - 1) < V ? NC - G * (NQ - 1) : V;
   static constexpr int KS = m2l_kstride_of(NC, (int)sizeof(T));  // global row stride
   // quad chunks per staged operator chunk: as many as fit two LDS buffers
-  static constexpr int fit_nqc(int n) {
-    return n <= 1 ? 1 : (2 * ROWS * V * (4 * n + 1) * (int)sizeof(T) <= kLdsBudget ? n : fit_nqc(n - 1));
+  // LDS row layout of a staged chunk of n quad chunks, in 16-byte vectors.
+  // A 16-byte LDS read serves 32 lanes at a time and is free of bank
+  // conflicts when their vectors are distinct modulo 32.
+  //  * Conflict-free form: [g][quad chunk], the 4 lane groups g GQ vectors
+  //    apart (GQ odd) and rows 4 GQ + 2 apart: 16 rows at a stride of 2 mod 4
+  //    fill the even residues, the odd g offset the odd ones.
+  //  * Compact form, where the first needs more operator chunks: [quad
+  //    chunk][g], rows 4 n + 1 apart (adjacent lane groups share banks).
+  static constexpr int gq_of(int n) { return n | 1; }
+  static constexpr int row_cf(int n) { return 4 * gq_of(n) + 2; }
+  static constexpr int row_compact(int n) { return 4 * n + 1; }
+  static constexpr int fit_cf(int n) {
+    return n <= 1 ? 1 : (2 * ROWS * row_cf(n) * 16 <= kLdsBudget ? n : fit_cf(n - 1));
   }
+  static constexpr int fit_compact(int n) {
+    return n <= 1 ? 1 : (2 * ROWS * row_compact(n) * 16 <= kLdsBudget ? n : fit_compact(n - 1));
+  }
+  static constexpr bool CF = fit_cf(NQ) == fit_compact(NQ);
+  static constexpr int fit_nqc(int n) { return CF ? fit_cf(n) : fit_compact(n); }
   static constexpr int NQC = fit_nqc(NQ);
   static constexpr int NCH = (NQ + NQC - 1) / NQC;  // operator chunks
   static constexpr int KC = G * NQC;                // k per operator chunk
-  static constexpr int KCS = V * (4 * NQC + 1);     // LDS row stride (odd quads)
+  static constexpr int GOFF = CF ? gq_of(NQC) : 1;  // vectors between lane groups
+  static constexpr int QOFF = CF ? 1 : 4;            // vectors between quad chunks
+  static constexpr int KCS = V * (CF ? row_cf(NQC) : row_compact(NQC));  // LDS row stride
   static constexpr int VPR = KC / V;                // vectors per row per chunk
   static constexpr int NV = ROWS * VPR;             // vectors per chunk
   static constexpr int PER_THREAD = (NV + kThreads - 1) / kThreads;
@@ -180,8 +198,9 @@ __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restri
     for (int i = 0; i < S::PER_THREAD; ++i) {
       const int e = tid + i * kThreads;
       if (e < S::NV) {
-        const int row = e / S::VPR, kv = e % S::VPR;
-        *reinterpret_cast<vec_t*>(buf + row * KCS + kv * V) = reg[i];
+        const int row = e / S::VPR, kv = e % S::VPR;  // kv = 4 (quad chunk) + g
+        *reinterpret_cast<vec_t*>(buf + row * KCS + ((kv % 4) * S::GOFF + (kv / 4) * S::QOFF) * V) =
+            reg[i];
       }
     }
   };
@@ -205,8 +224,8 @@ __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restri
   auto compute_chunk = [&](const T* buf, int ch, const vec_t* b) {
     acc_t* dst = Mfma<T>::kChain ? acc : sum;
     T& tdst = Mfma<T>::kChain ? tacc : tsum;
-    const T* sa = buf + col * KCS + V * kg;
-    const T* st = buf + (NC - 1) * KCS + V * kg;  // tail row (same for all 16 columns)
+    const T* sa = buf + col * KCS + V * S::GOFF * kg;
+    const T* st = buf + (NC - 1) * KCS + V * S::GOFF * kg;  // tail row (same for all 16 columns)
     vec_t av[2][RBM], at[2];
 #pragma unroll
     for (int r = 0; r < RBM; ++r) av[0][r] = *reinterpret_cast<const vec_t*>(sa + 16 * r * KCS);
@@ -218,8 +237,9 @@ __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restri
       if (qc + 1 < NQC && q + 1 < NQ) {
 #pragma unroll
         for (int r = 0; r < RBM; ++r)
-          av[(qc + 1) & 1][r] = *reinterpret_cast<const vec_t*>(sa + 16 * r * KCS + G * (qc + 1));
-        if (TAIL) at[(qc + 1) & 1] = *reinterpret_cast<const vec_t*>(st + G * (qc + 1));
+          av[(qc + 1) & 1][r] =
+              *reinterpret_cast<const vec_t*>(sa + 16 * r * KCS + V * S::QOFF * (qc + 1));
+        if (TAIL) at[(qc + 1) & 1] = *reinterpret_cast<const vec_t*>(st + V * S::QOFF * (qc + 1));
       }
       const int ns = (q == NQ - 1) ? S::S_LAST : V;
 #pragma unroll

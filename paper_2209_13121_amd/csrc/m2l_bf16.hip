@@ -22,9 +22,8 @@
 //    staged in LDS per offset in k-step chunks, double-buffered.
 //  * Sources: the FP32 multipoles of every level, split once per evaluation
 //    into BF16 pieces (k_split_mult) so the M2L loop only loads quads.
-//  * Accumulation: each offset's product is a fresh FP32 chain (smallest
-//    piece products first); the chains are summed across offsets with Kahan
-//    compensation, as in the FP32 form.
+//  * Accumulation: FP32 chains over kFlush consecutive offsets (smallest
+//    piece products first), summed with Kahan compensation.
 #include "bf16_split.h"
 #include "m2l_common.h"
 
@@ -33,10 +32,21 @@ namespace {
 
 using m2l::kThreads;
 
+// Tuning (measured at p = 8 on MI355X): row blocks per group of A loads,
+// and offsets per FP32 chain -- the chain is added to the compensated sum
+// after every kFlush offsets and after the last (chains of 4 offsets are 72
+// piece products long; the Kahan update is then a quarter of its per-offset
+// cost and the result as accurate).
+#ifndef M2LB_RG
+#define M2LB_RG 2
+#endif
+#ifndef M2LB_FLUSH
+#define M2LB_FLUSH 4
+#endif
+constexpr int kFlush = M2LB_FLUSH;
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kLdsBudget = 140 * 1024;  // two operator buffers (plus the slot halo)
 
 // Piece products (a piece, b piece) with i + j < NP, smallest first.
 template <int NP>
@@ -84,19 +94,16 @@ struct Shape {
   static constexpr int RB = (NC + 15) / 16;  // 16-row blocks
   static constexpr int RP = RB * 16;
   static constexpr int KST = m2lb_ksteps(NC);       // 32-wide k steps
-  static constexpr int QR = m2lb_row_quads(NC, NP);  // quads per row (= per source box)
-  static constexpr int QRS = QR + 1;                 // global operator row stride
-  // k steps per staged chunk: as many as fit two LDS buffers
-  static constexpr int fit_kc(int n) {
-    return n <= 1 ? 1 : (2 * RP * (n * NP * 4 + 1) * 16 <= kLdsBudget ? n : fit_kc(n - 1));
-  }
-  static constexpr int KC = fit_kc(KST);
-  static constexpr int NCH = (KST + KC - 1) / KC;  // chunks per operator
-  static constexpr int QC = KC * NP * 4;           // quads per row per chunk
-  static constexpr int QCS = QC + 1;               // LDS row stride (odd)
-  static constexpr int NV = RP * QC;               // quads per chunk
+  static constexpr int QR = m2lb_row_quads(NC, NP);  // quads per source box
+  static constexpr int KC = m2lb_kc(NC, NP);         // k steps per staged chunk
+  static constexpr int NCH = m2lb_nch(NC, NP);       // chunks per operator
+  static constexpr int GQ = m2lb_gq(KC, NP);         // quads between lane groups g
+  static constexpr int QCS = m2lb_qcs(KC, NP);       // quads between rows
+  static constexpr int CQ = RP * QCS;                // quads per stored chunk
+  static constexpr int QD = 4 * GQ;                  // quads of a row the MFMAs read
+  static constexpr int NV = NC * QD;                 // quads staged per chunk
   static constexpr int PER_THREAD = (NV + kThreads - 1) / kThreads;
-  static constexpr int RG = RB < 3 ? RB : 3;       // row blocks interleaved per A load
+  static constexpr int RG = RB < M2LB_RG ? RB : M2LB_RG;  // row blocks interleaved per A load
   // Prefetch the next offset's B quads (a second register set) where the
   // registers allow it.
   static constexpr bool PREFETCH_B = KST * NP <= 9;
@@ -109,8 +116,8 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
                                                      float* __restrict__ out) {
   typedef Shape<P, NP> S;
   typedef Prod<NP> PR;
-  constexpr int NC = S::NC, RB = S::RB, RP = S::RP, KST = S::KST, QR = S::QR, QRS = S::QRS;
-  constexpr int KC = S::KC, NCH = S::NCH, QC = S::QC, QCS = S::QCS, RG = S::RG;
+  constexpr int NC = S::NC, RB = S::RB, RP = S::RP, KST = S::KST, QR = S::QR;
+  constexpr int KC = S::KC, NCH = S::NCH, GQ = S::GQ, QCS = S::QCS, RG = S::RG;
   __shared__ u32x4 sT[2][RP * QCS];
   __shared__ uint32_t sSlot[m2l::kHalo];
   __shared__ int sBox[6];
@@ -127,27 +134,29 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   for (int r = 0; r < RB; ++r) sum[r] = comp[r] = acc[r] = f32x4{0, 0, 0, 0};
 
   // Operator chunk ch of operator op into registers / into an LDS buffer.
-  // Quad e of a chunk is row e / QC, quad e % QC; quads past the stored row
-  // (a partial last chunk) read the row's zero pad quad.
+  // Chunks are stored in their LDS layout; only the NC real rows and the
+  // quads the MFMAs read are staged (loads are clamped so that every lane
+  // issues the same loads).  Rows NC..RP-1 of both buffers stay zero.
   auto stage_load = [&](int op, int ch, u32x4* reg) {
-    const u32x4* base = ops + (size_t)op * RP * QRS;
+    const u32x4* base = ops + ((size_t)op * NCH + ch) * S::CQ;
 #pragma unroll
     for (int i = 0; i < S::PER_THREAD; ++i) {
       int e = tid + i * kThreads;
       e = e < S::NV ? e : S::NV - 1;
-      const int row = e / QC;
-      int q = ch * QC + e % QC;
-      q = q < QR ? q : QR;
-      reg[i] = base[row * QRS + q];
+      reg[i] = base[(e / S::QD) * QCS + e % S::QD];
     }
   };
   auto stage_store = [&](u32x4* buf, const u32x4* reg) {
 #pragma unroll
     for (int i = 0; i < S::PER_THREAD; ++i) {
       const int e = tid + i * kThreads;
-      if (e < S::NV) buf[(e / QC) * QCS + e % QC] = reg[i];
+      if (e < S::NV) buf[(e / S::QD) * QCS + e % S::QD] = reg[i];
     }
   };
+  for (int e = tid; e < 2 * (RP - NC) * QCS; e += kThreads) {
+    const int b = e / ((RP - NC) * QCS);
+    sT[b][NC * QCS + e % ((RP - NC) * QCS)] = u32x4{0, 0, 0, 0};
+  }
   auto row_of = [&](m2l::Src src) -> const u32x4* {
     return src.ok ? mlev + (int64_t)src.slot * QR : zero_q;
   };
@@ -158,7 +167,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   };
   // MFMAs of operator chunk ch (staged in buf) against B quads b.
   auto compute_chunk = [&](const u32x4* buf, int ch, const u32x4* b) {
-    const u32x4* sa = buf + col * QCS + kg;
+    const u32x4* sa = buf + col * QCS + kg * GQ;
 #pragma unroll
     for (int kc = 0; kc < KC; ++kc) {
       const int ks = ch * KC + kc;
@@ -170,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
         for (int rr = 0; rr < RG; ++rr)
 #pragma unroll
           for (int i = 0; i < NP; ++i)
-            if (r0 + rr < RB) av[rr][i] = sa[16 * (r0 + rr) * QCS + (kc * NP + i) * 4];
+            if (r0 + rr < RB) av[rr][i] = sa[16 * (r0 + rr) * QCS + kc * NP + i];
 #pragma unroll
         for (int t = 0; t < PR::N; ++t)
 #pragma unroll
@@ -219,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
       stage_load(last_chunk ? (more ? nop : op) : op, last_chunk ? 0 : ch + 1, reg);
       if (PB && ch == 0) load_b(row_of(s_next), bn);
       if (wave_any) compute_chunk(sT[cur], ch, bc);
-      if (last_chunk && wave_any) {
+      if (last_chunk && (kFlush == 1 ? wave_any : ((i + 1) % kFlush == 0 || !more))) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           const f32x4 y = acc[r] - comp[r];

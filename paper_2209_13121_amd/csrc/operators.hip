@@ -185,7 +185,7 @@ __host__ __device__ inline double m2l_entry(int p, int row, int col, const doubl
 }
 
 // M2M and L2L tables: block b < 8 builds M2M of octant b, block 8 + b L2L,
-// stored [octant][k (padded to kp)][row (padded to rp)], zero padded.
+// stored [octant][row (padded to rp)][k (padded to kp)], zero padded.
 __global__ void k_gen_shift(int p, int kp, int rp, double* __restrict__ m2m,
                             double* __restrict__ l2l) {
   __shared__ double tre[kTabMax], tim[kTabMax];
@@ -199,8 +199,8 @@ __global__ void k_gen_shift(int p, int kp, int rp, double* __restrict__ m2m,
   __syncthreads();
   const int nc = (p + 1) * (p + 1);
   double* out = (is_l2l ? l2l : m2m) + (size_t)oct * kp * rp;
-  for (int e = threadIdx.x; e < kp * rp; e += blockDim.x) {
-    const int col = e / rp, row = e % rp;
+  for (int e = threadIdx.x; e < kp * rp; e += blockDim.x) {  // [row][k]
+    const int row = e / kp, col = e % kp;
     out[e] = (col < nc && row < nc) ? shift_entry(p, is_l2l, row, col, tre, tim) : 0.0;
   }
 }
@@ -225,11 +225,11 @@ __global__ void k_gen_m2l(int p, int rp, int ks, T* __restrict__ ops) {
   }
 }
 
-// Operators in pieces: one thread per (operator row, k step, lane group)
-// computes its 8 FP64 entries and writes their NP quads; the last thread of
-// a row also writes the zero pad quad.
+// Operators in pieces, in the chunked LDS layout of the split-BF16 M2L: one
+// thread per (operator row, k step, lane group) computes its 8 FP64 entries
+// and writes their NP quads.  Pad quads are zeroed beforehand.
 template <int NP>
-__global__ void k_gen_m2l_bf(int p, int rp, u32x4* __restrict__ ops) {
+__global__ void k_gen_m2l_bf(int p, u32x4* __restrict__ ops) {
   __shared__ double tre[kTabMax], tim[kTabMax];
   const int op = blockIdx.x;
   if ((int)threadIdx.x <= 2 * p) {
@@ -240,8 +240,9 @@ __global__ void k_gen_m2l_bf(int p, int rp, u32x4* __restrict__ ops) {
   }
   __syncthreads();
   const int nc = (p + 1) * (p + 1);
-  const int kst = m2lb_ksteps(nc), qr = m2lb_row_quads(nc, NP);
-  u32x4* out = ops + (size_t)op * rp * (qr + 1);
+  const int kst = m2lb_ksteps(nc), rp = m2lb_rows(nc), kc = m2lb_kc(nc, NP);
+  const int gq = m2lb_gq(kc, NP), qcs = m2lb_qcs(kc, NP);
+  u32x4* out = ops + (size_t)op * m2lb_op_quads(nc, NP);
   for (int e = threadIdx.x; e < rp * kst * 4; e += blockDim.x) {
     const int row = e / (kst * 4), ks = e / 4 % kst, g = e % 4;
     uint32_t pc[8][NP];
@@ -252,10 +253,9 @@ __global__ void k_gen_m2l_bf(int p, int rp, u32x4* __restrict__ ops) {
     }
     u32x4 q[NP];
     pack_quads<NP>(pc, q);
-    u32x4* o = out + (size_t)row * (qr + 1);
+    u32x4* o = out + ((size_t)(ks / kc) * rp + row) * qcs + g * gq + (ks % kc) * NP;
 #pragma unroll
-    for (int i = 0; i < NP; ++i) o[(ks * NP + i) * 4 + g] = q[i];
-    if (ks == kst - 1 && g == 3) o[qr] = u32x4{0, 0, 0, 0};
+    for (int i = 0; i < NP; ++i) o[i] = q[i];
   }
 }
 
@@ -264,14 +264,17 @@ __global__ void k_gen_m2l_bf(int p, int rp, u32x4* __restrict__ ops) {
 hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
   const Layout& lay = P->lay;
   prof_begin(P, FMM_PHASE_OPERATORS, s);
-  const int kp = m2l_k_pad(P->p), rp = m2l_rows_pad(P->p);
+  const int kp = shift_kpad(P->nc), rp = m2l_rows_pad(P->p);
   k_gen_shift<<<16, kBlock, 0, s>>>(P->p, kp, rp, wsp<double>(P, lay.op_m2m),
                                     wsp<double>(P, lay.op_l2l));
-  if (P->m2l_np == 2)
-    k_gen_m2l_bf<2><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, wsp<u32x4>(P, lay.op_m2lb));
-  else if (P->m2l_np == 3)
-    k_gen_m2l_bf<3><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, wsp<u32x4>(P, lay.op_m2lb));
-  else if (P->mixed)
+  if (P->m2l_np) {
+    const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(P->nc, P->m2l_np) * 4;
+    fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads
+    if (P->m2l_np == 2)
+      k_gen_m2l_bf<2><<<kNumM2LOps, kBlock, 0, s>>>(P->p, wsp<u32x4>(P, lay.op_m2lb));
+    else
+      k_gen_m2l_bf<3><<<kNumM2LOps, kBlock, 0, s>>>(P->p, wsp<u32x4>(P, lay.op_m2lb));
+  } else if (P->mixed)
     k_gen_m2l<float><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, m2l_kstride_of(P->nc, 4),
                                                    wsp<float>(P, lay.op_m2l32));
   else

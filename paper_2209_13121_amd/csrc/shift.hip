@@ -4,12 +4,22 @@
 // each level is a set of dense products batched by octant:
 //   M2M  M~p[:, parents]          = sum_o A_o * M~[:, child of octant o]
 //   L2L  L~[:, children of oct o] = (1/h) M2L[:, ...] + B_o * L~[:, parents]
-// FP64 in both precision modes.  One work-group owns 128 targets (parents for
-// M2M; the octant-o children of 128 parent slots for L2L), one wave 16 of
-// them; the operator of each octant is staged in LDS (in chunks of k-rows when
-// it does not fit) and shared by the 128 targets.  The B operand is read as
-// 16-byte vectors (two coefficients), the K order of the MFMA steps being
-// permuted to match (lane group g at sub-step s of chunk q uses k = 8q + 2g + s).
+// FP64 in both precision modes.
+//  * One work-group owns one 16-row block of the expansions and 8 tiles of
+//    16 targets, one tile per wave: 128 parents for M2M, the octant-o
+//    children of 128 parents for L2L.  The row block's rows of the operators
+//    it needs (all 8 octants for M2M, octant o for L2L) are staged in LDS
+//    once and shared by the 8 waves; the grid runs over (row block, tiles),
+//    so even the coarse levels spread over many work-groups.
+//  * The translations are triangular in degree: a parent multipole of degree
+//    n takes child degrees <= n only, a child local of degree n parent
+//    degrees >= n only (the addition theorems of the solid harmonics;
+//    Greengard 1988, ch. 3).  A row block stages and runs only the k steps
+//    that can be non-zero for its rows; the skipped products are exact zeros.
+//  * K order: step t of pair q uses k = 8 q + 2 g + t in lane group g, so a
+//    lane's A and B values of a pair are one 16-byte load each.  LDS rows are
+//    a multiple of 2 mod 4 16-byte units apart, which keeps the 32 lanes a
+//    16-byte read serves at once on distinct banks.
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -18,38 +28,41 @@ namespace {
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 8;
-constexpr int kThreads = kWaves * 64;
-constexpr int kTargets = kWaves * 16;
+constexpr int kThreads = 64 * kWaves;
 
-template <int P>
+template <int P, int MODE>
 struct ShiftShape {
   static constexpr int NC = (P + 1) * (P + 1);
   static constexpr int RB = (NC + 15) / 16;
-  static constexpr int RP = RB * 16;
-  static constexpr int KP = ((NC + 3) / 4) * 4;
   static constexpr int MS = mstride_of(NC);
-  static constexpr int G = 8;                   // k per vector chunk (4 lane groups x 2)
-  static constexpr int NQ = (NC + G - 1) / G;
-  static constexpr int S_LAST = NC - G * (NQ - 1) < 2 ? NC - G * (NQ - 1) : 2;
-  static constexpr int SLD = (RP % 64 == 16 || RP % 64 == 48) ? RP : RP + 16;
-  static constexpr int FIT = (80 * 1024) / (SLD * 8) / G * G;
-  static constexpr int KC = FIT >= KP ? KP : FIT;
-  static constexpr int NCH = (KP + KC - 1) / KC;
-  static constexpr int PER_THREAD = (KC * RP / 2 + kThreads - 1) / kThreads;
-  static_assert(NCH == 1 || KC % G == 0, "operator chunks must hold whole vector chunks");
+  static constexpr int KP = shift_kpad(NC);
+  static constexpr int NQ = KP / 8;  // k pairs of steps
+  static constexpr int RS = (KP / 2) % 4 == 2 ? KP / 2 : KP / 2 + (6 - (KP / 2) % 4) % 4;  // row stride (16 B)
+  static constexpr int NOCT = MODE == 0 ? 8 : 1;  // octants staged
+  // M2M at large orders stages the octants in two halves (LDS size)
+  static constexpr int OCT_STAGE = NOCT * 16 * RS * 16 <= 150 * 1024 ? NOCT : NOCT / 2;
+  static_assert(RS % 4 == 2 && RS >= KP / 2, "LDS row stride");
 };
 
+// Degree of packed coefficient index c (c = n^2 .. n^2 + 2n).
+__device__ __forceinline__ int degree_of(int c) {
+  int n = (int)sqrtf((float)c);
+  while (n * n > c) --n;
+  while ((n + 1) * (n + 1) <= c) ++n;
+  return n;
+}
+
 struct ShiftArgs {
-  int mode;            // 0 = M2M, 1 = L2L
   int l;               // level of the targets
   int mixed;           // source (M2M) / destination (L2L leaf) is FP32
   int leaf;            // L2L: this level is the leaf level
-  int64_t ntargets;    // M2M: parents at level l; L2L: parents at level l-1 (per octant)
-  int64_t ntile;       // tiles of 128 per octant (L2L) or in all (M2M)
+  int64_t nparent;     // M2M: parents at level l; L2L: parents at level l-1
+  int64_t ngroups;     // work-groups in the launch
   const uint32_t* s2c_child;  // slot -> coord of the child level
-  const double* ops;          // 8 padded operators [oct][KP][RP]
+  const double* ops;          // 8 operators [oct][row][KP]
   const void* src;            // M2M: child multipoles (stride MS); L2L: parent locals (stride MS)
   double* dst64;              // M2M: parent multipoles; L2L: child locals (stride MS)
   float* dst32;               // M2M mixed: FP32 copy of the parents; L2L mixed leaf: leaf locals
@@ -57,134 +70,165 @@ struct ShiftArgs {
   const DevParams* dp;
 };
 
-template <int P>
+template <int P, int MODE>
 __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
-  typedef ShiftShape<P> S;
-  constexpr int NC = S::NC, RB = S::RB, RP = S::RP, KP = S::KP, MS = S::MS, SLD = S::SLD;
-  constexpr int G = S::G, NQ = S::NQ, KC = S::KC, NCH = S::NCH;
-  __shared__ __attribute__((aligned(16))) double sT[KC * SLD];
-
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  typedef ShiftShape<P, MODE> S;
+  constexpr int NC = S::NC, RB = S::RB, MS = S::MS, KP = S::KP, NQ = S::NQ, RS = S::RS;
+  constexpr int OCT_STAGE = S::OCT_STAGE;
+  __shared__ f64x2 sA[OCT_STAGE * 16 * RS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  const int64_t g = blockIdx.x;
-  const int oct_l2l = a.mode == 1 ? (int)(g / a.ntile) : 0;
-  const int64_t tile = a.mode == 1 ? g % a.ntile : g;
-  const int64_t ps = tile * kTargets + wave * 16 + col;  // parent slot of this column
-  const bool ok = ps < a.ntargets;
+  // group -> (row block, 8 tiles); L2L groups of the 8 octants of the same
+  // parents are adjacent (they read the same parent locals).  XCD-aware
+  // order: hardware group b runs on XCD b % 8 and each XCD gets a contiguous
+  // range of logical groups, so the groups that read the same sources share
+  // an L2.
+  const int64_t per_xcd = (a.ngroups + 7) / 8;
+  const int64_t g = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (g >= a.ngroups) return;  // uniform over the work-group
+  const int rb = (int)(g % RB);
+  const int64_t rest = g / RB;
+  const int oct_l2l = MODE == 1 ? (int)(rest % 8) : 0;
+  const int64_t pgroup = MODE == 1 ? rest / 8 : rest;
+  const int64_t ps = (pgroup * kWaves + wave) * 16 + col;  // parent slot of this column
+  const bool ok = ps < a.nparent;
 
-  // child of each octant: children of slot ps are slots 8 ps .. 8 ps + 7
-  int child_of[8];
-#pragma unroll
-  for (int o = 0; o < 8; ++o) child_of[o] = 0;
+  // child slot of each octant (children of slot ps are slots 8 ps .. 8 ps + 7),
+  // packed 3 bits per octant
+  uint32_t child_bits = 0;
   if (ok) {
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       int x, y, z;
       unpack_coord(a.s2c_child[8 * ps + c], x, y, z);
-      child_of[((x & 1) << 2) | ((y & 1) << 1) | (z & 1)] = c;
+      child_bits |= (uint32_t)c << (3 * (((x & 1) << 2) | ((y & 1) << 1) | (z & 1)));
     }
   }
+  auto child_of = [&](int oct) { return (int)((child_bits >> (3 * oct)) & 7u); };
 
-  f64x4 acc[RB];
-#pragma unroll
-  for (int r = 0; r < RB; ++r) acc[r] = f64x4{0, 0, 0, 0};
+  // k pairs this row block can touch (exact zeros outside)
+  const int row0 = 16 * rb;
+  int q0, q1;
+  if (MODE == 0) {  // lower: k of degree <= deg(last row)
+    const int d = degree_of(min(row0 + 15, NC - 1));
+    q0 = 0;
+    q1 = ((d + 1) * (d + 1) + 7) / 8;
+  } else {  // upper: k of degree >= deg(first row)
+    const int d = degree_of(row0);
+    q0 = (d * d) / 8;
+    q1 = NQ;
+  }
 
-  const int nops = a.mode == 0 ? 8 : 1;
-  for (int o = 0; o < nops; ++o) {
-    const int oct = a.mode == 0 ? o : oct_l2l;
-    // this lane's B operand: the octant-oct child (M2M) or the parent (L2L)
-    f64x2 b[NQ];
-    {
-      int64_t row_of_src = -1;
-      if (ok) row_of_src = a.mode == 0 ? 8 * ps + child_of[oct] : ps;
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int k0 = G * q + 2 * kg;
-        b[q] = f64x2{0.0, 0.0};
-        if (row_of_src >= 0 && k0 < MS) {
-          if (a.mode == 0 && a.mixed) {
-            const f32x2 v = *reinterpret_cast<const f32x2*>(
-                static_cast<const float*>(a.src) + row_of_src * MS + k0);
-            b[q] = f64x2{(double)v[0], (double)v[1]};
-          } else {
-            b[q] = *reinterpret_cast<const f64x2*>(static_cast<const double*>(a.src) +
-                                                   row_of_src * MS + k0);
-          }
-        }
-      }
+  f64x4 acc0 = f64x4{0, 0, 0, 0}, acc1 = f64x4{0, 0, 0, 0};
+  for (int o0 = 0; o0 < S::NOCT; o0 += OCT_STAGE) {
+    // stage rows row0..row0+15, pairs q0..q1-1, of octants o0.. (M2M) or oct_l2l (L2L)
+    if (o0 > 0) __syncthreads();
+    const int npair = q1 - q0;  // 16-byte units per row = 4 per pair
+    for (int e = tid; e < OCT_STAGE * 16 * 4 * npair; e += kThreads) {
+      const int u = e % (4 * npair), r = e / (4 * npair) % 16, oo = e / (4 * npair * 16);
+      const int oct = MODE == 0 ? o0 + oo : oct_l2l;
+      sA[(oo * 16 + r) * RS + 4 * q0 + u] = *reinterpret_cast<const f64x2*>(
+          a.ops + ((size_t)oct * (RB * 16) + row0 + r) * KP + 8 * q0 + 2 * u);
     }
-    for (int ch = 0; ch < NCH; ++ch) {
-      // stage k-rows [ch*KC, ...) of the operator
-      const int rows = (ch + 1) * KC <= KP ? KC : KP - ch * KC;
-      const f64x2* srcv =
-          reinterpret_cast<const f64x2*>(a.ops + (size_t)oct * KP * RP + (size_t)ch * KC * RP);
-      __syncthreads();
-      for (int e = tid; e < rows * RP / 2; e += kThreads) {
-        const int k = (2 * e) / RP, row = (2 * e) % RP;
-        *reinterpret_cast<f64x2*>(sT + k * SLD + row) = srcv[e];
-      }
-      __syncthreads();
-      const double* sTc = sT + col;
-      const int kbase = ch * KC;
+    __syncthreads();
+    // B pairs of octant oct: unconditional loads at clamped addresses (so
+    // a whole octant's loads are in flight together), then zeroed where the
+    // source does not exist or k is past the row
+    auto load_b = [&](int oct, f64x2* bv) {
+      const bool have = ok;
+      const int64_t srow = !have ? 0 : (MODE == 0 ? 8 * ps + child_of(oct) : ps);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
-        if (NCH > 1 && (G * q < kbase || G * q >= kbase + KC)) continue;
-        const int ns = (q == NQ - 1) ? S::S_LAST : 2;
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-          if (s >= ns) break;
-          int k = G * q + 2 * kg + s;
-          k = k < KP ? k : KP - 1;  // rows past KP meet zero B values
-          const double bv = b[q][s];
-#pragma unroll
-          for (int r = 0; r < RB; ++r)
-            acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(sTc[(k - kbase) * SLD + 16 * r], bv,
-                                                          acc[r], 0, 0, 0);
+        const int k = 8 * q + 2 * kg;
+        const int k0 = k < MS ? k : MS - 2;
+        f64x2 v;
+        if (MODE == 0 && a.mixed) {
+          const f32x2 w = *reinterpret_cast<const f32x2*>(static_cast<const float*>(a.src) +
+                                                          srow * MS + k0);
+          v = f64x2{(double)w[0], (double)w[1]};
+        } else {
+          v = *reinterpret_cast<const f64x2*>(static_cast<const double*>(a.src) + srow * MS + k0);
         }
+        bv[q] = (have && k < MS) ? v : f64x2{0.0, 0.0};
+      }
+    };
+    f64x2 bcur[NQ], bnext[NQ];
+    load_b(MODE == 0 ? o0 : oct_l2l, bcur);
+#pragma unroll
+    for (int oo = 0; oo < OCT_STAGE; ++oo) {
+      if (oo + 1 < OCT_STAGE) load_b(o0 + oo + 1, bnext);  // M2M: next octant in flight
+      const f64x2* sa = sA + (oo * 16 + col) * RS + kg;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (q < q0 || q >= q1) continue;  // uniform over the work-group
+        const f64x2 av = sa[4 * q];
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bcur[q][0], acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bcur[q][1], acc1, 0, 0, 0);
+      }
+      if (oo + 1 < OCT_STAGE) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) bcur[q] = bnext[q];
       }
     }
   }
+  const f64x4 acc = acc0 + acc1;
 
-  if (!ok) return;
-  // f64 accumulator layout: lane holds column col, rows 16 r + kg + 4 i
-  if (a.mode == 0) {
-    double* o64 = a.dst64 + ps * MS;
-    float* o32 = a.dst32 ? a.dst32 + ps * MS : nullptr;
+  // The f64 accumulator gives lane (col, kg) rows 16 rb + kg + 4 i.  Transpose
+  // across the 4 lanes of a column so that it holds rows 16 rb + 4 kg + j,
+  // j = 0..3, and writes them as one 16- or 32-byte vector: in round t lane
+  // (col, j) offers its value i = (j - t) mod 4 and lane (col, kg) takes it
+  // from lane (col, (kg + t) mod 4), which is row 4 kg + (kg + t) mod 4.
+  double v[4];
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 16 * r + kg + 4 * i;
-        if (row < MS) {  // rows NC..MS-1 are zero (zero operator rows)
-          o64[row] = acc[r][i];
-          if (o32) o32[row] = (float)acc[r][i];
-        }
-      }
+  for (int t = 0; t < 4; ++t) {
+    const int i_send = (kg - t) & 3;
+    const double send = i_send == 0 ? acc[0] : i_send == 1 ? acc[1] : i_send == 2 ? acc[2] : acc[3];
+    const int from = ((kg + t) & 3) * 16 + col;
+    const double got = __shfl(send, from);
+    const int j = (kg + t) & 3;
+    if (j == 0) v[0] = got;
+    if (j == 1) v[1] = got;
+    if (j == 2) v[2] = got;
+    if (j == 3) v[3] = got;
+  }
+  const int rr = row0 + 4 * kg;  // this lane's 4 rows; MS % 4 == 0, so all or none < MS
+  if (!ok || rr >= MS) return;
+  if (MODE == 0) {  // rows NC..MS-1 are zero (zero operator rows)
+    *reinterpret_cast<f64x2*>(a.dst64 + ps * MS + rr) = f64x2{v[0], v[1]};
+    *reinterpret_cast<f64x2*>(a.dst64 + ps * MS + rr + 2) = f64x2{v[2], v[3]};
+    if (a.dst32)
+      *reinterpret_cast<f32x4*>(a.dst32 + ps * MS + rr) =
+          f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
   } else {
-    const int64_t cs = 8 * ps + child_of[oct_l2l];
+    const int64_t cs = 8 * ps + child_of(oct_l2l);
     const double inv_h = (double)(1 << a.l) / a.dp->side;
 #pragma unroll
-    for (int r = 0; r < RB; ++r)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 16 * r + kg + 4 * i;
-        if (row >= MS) continue;
-        double v = acc[r][i];
-        if (row < NC)
-          v += inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + row]
-                                : static_cast<const double*>(a.m2l)[cs * NC + row]);
-        if (a.leaf && a.mixed)
-          a.dst32[cs * MS + row] = (float)v;
-        else
-          a.dst64[cs * MS + row] = v;
-      }
+    for (int j = 0; j < 4; ++j)
+      if (rr + j < NC)
+        v[j] += inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + rr + j]
+                                 : static_cast<const double*>(a.m2l)[cs * NC + rr + j]);
+    if (a.leaf && a.mixed) {
+      *reinterpret_cast<f32x4*>(a.dst32 + cs * MS + rr) =
+          f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    } else {
+      *reinterpret_cast<f64x2*>(a.dst64 + cs * MS + rr) = f64x2{v[0], v[1]};
+      *reinterpret_cast<f64x2*>(a.dst64 + cs * MS + rr + 2) = f64x2{v[2], v[3]};
+    }
   }
 }
 
 template <int P>
 struct ShiftRun {
-  static hipError_t run(ShiftArgs a, int64_t groups, hipStream_t s) {
-    k_shift<P><<<(unsigned)groups, kThreads, 0, s>>>(a);
+  static hipError_t run(ShiftArgs a, int mode, hipStream_t s) {
+    typedef ShiftShape<P, 0> S;
+    const int64_t pgroups = (a.nparent + 16 * kWaves - 1) / (16 * kWaves);
+    a.ngroups = pgroups * S::RB * (mode == 1 ? 8 : 1);
+    const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
+    if (mode == 0)
+      k_shift<P, 0><<<grid, kThreads, 0, s>>>(a);
+    else
+      k_shift<P, 1><<<grid, kThreads, 0, s>>>(a);
     return hipGetLastError();
   }
 };
@@ -214,11 +258,9 @@ hipError_t launch_m2m(fmm_plan_s* P, hipStream_t s) {
   float* m32 = P->mixed ? wsp<float>(P, lay.mult32) : nullptr;
   for (int l = P->L - 1; l >= 2; --l) {
     ShiftArgs a = {};
-    a.mode = 0;
     a.l = l;
     a.mixed = (l + 1 == P->L && P->mixed) ? 1 : 0;  // leaf multipoles are FP32 in the mixed mode
-    a.ntargets = (int64_t)1 << (3 * l);
-    a.ntile = (a.ntargets + kTargets - 1) / kTargets;
+    a.nparent = (int64_t)1 << (3 * l);
     a.s2c_child = wsp<uint32_t>(P, lay.slot2coord) + lay.lvl_off[l + 1];
     a.ops = wsp<double>(P, lay.op_m2m);
     a.src = a.mixed ? (const void*)(m32 + lay.lvl_off[l + 1] * ms)
@@ -226,7 +268,7 @@ hipError_t launch_m2m(fmm_plan_s* P, hipStream_t s) {
     a.dst64 = m64 + lay.lvl_off[l] * ms;
     a.dst32 = m32 ? m32 + lay.lvl_off[l] * ms : nullptr;
     a.dp = wsp<DevParams>(P, lay.params);
-    hipError_t e = dispatch_p<ShiftRun>(P->p, a, a.ntile, s);
+    hipError_t e = dispatch_p<ShiftRun>(P->p, a, 0, s);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();
@@ -252,12 +294,10 @@ hipError_t launch_l2l(fmm_plan_s* P, hipStream_t s) {
   }
   for (int l = 3; l <= L; ++l) {
     ShiftArgs a = {};
-    a.mode = 1;
     a.l = l;
     a.mixed = P->mixed ? 1 : 0;
     a.leaf = l == L ? 1 : 0;
-    a.ntargets = (int64_t)1 << (3 * (l - 1));
-    a.ntile = (a.ntargets + kTargets - 1) / kTargets;
+    a.nparent = (int64_t)1 << (3 * (l - 1));
     a.s2c_child = wsp<uint32_t>(P, lay.slot2coord) + lay.lvl_off[l];
     a.ops = wsp<double>(P, lay.op_l2l);
     a.src = l64 + lay.lvl_off[l - 1] * ms;
@@ -266,7 +306,7 @@ hipError_t launch_l2l(fmm_plan_s* P, hipStream_t s) {
     a.m2l = P->mixed ? (const void*)(wsp<float>(P, lay.m2l_out) + lay.lvl_off[l] * nc)
                      : (const void*)(wsp<double>(P, lay.m2l_out) + lay.lvl_off[l] * nc);
     a.dp = dp;
-    hipError_t e = dispatch_p<ShiftRun>(P->p, a, 8 * a.ntile, s);
+    hipError_t e = dispatch_p<ShiftRun>(P->p, a, 1, s);
     if (e != hipSuccess) return e;
   }
   return hipGetLastError();

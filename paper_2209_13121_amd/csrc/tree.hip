@@ -299,6 +299,11 @@ __global__ void k_zero_work(unsigned long long* work) {
 
 }  // namespace
 
+hipError_t fill_u32(uint32_t* a, int64_t n, uint32_t v, hipStream_t s) {
+  if (n > 0) k_fill_u32<<<grid_for(n, kBlock), kBlock, 0, s>>>(a, n, v);
+  return hipGetLastError();
+}
+
 hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
   const Layout& lay = P->lay;
   const int64_t n = P->n;
