@@ -100,9 +100,12 @@ def m2l_traffic(variant):
     return traffic if src_hash == m2l_source_hash(variant) else None
 
 
-def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream):
+def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream, breakdown_steps=3):
     """Run warmup + steps of (plan + evaluate); returns ms/step, outputs of the
-    last step and the per-phase kernel durations over the timed steps."""
+    last step, the M2L kernel durations over the timed steps (HIP events on
+    the launch stream around that pass only, so the other passes run
+    unbroken) and the per-pass durations of breakdown_steps further, untimed
+    steps with every pass recorded."""
     n = q.numel()
     phi = torch.empty(n, dtype=torch.float64, device=pos.device)
     force = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
@@ -119,23 +122,36 @@ def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream):
     t0 = time.perf_counter()
     for _ in range(steps):
         p = B.fmm_plan(cfg, n, pos, ws, stream)
-        B.fmm_profile_enable(p, True)
+        B.fmm_profile_enable(p, True, phases=["m2l"])
         B.fmm_evaluate(p, q, phi, force, energy, stream)
         plans.append(p)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
-    # kernel durations recorded with HIP events on the launch stream
-    phases = {}
-    for p in plans:
-        for k, (t, c) in B.fmm_profile_read(p).items():
-            a = phases.setdefault(k, [0.0, 0])
-            a[0] += t
-            a[1] += c
+
+    def collect(plans):
+        out = {}
+        for p in plans:
+            for k, (t, c) in B.fmm_profile_read(p).items():
+                a = out.setdefault(k, [0.0, 0])
+                a[0] += t
+                a[1] += c
+        return out
+    m2l = collect(plans)["m2l"]
     st = B.fmm_check(plans[-1])
     work = B.fmm_plan_work(plans[-1])
     for p in plans:
         B.fmm_destroy(p)
-    return ms, phi, force, energy, phases, st, work
+    plans = []
+    for _ in range(breakdown_steps):
+        p = B.fmm_plan(cfg, n, pos, ws, stream)
+        B.fmm_profile_enable(p, True)
+        B.fmm_evaluate(p, q, phi, force, energy, stream)
+        plans.append(p)
+    torch.cuda.synchronize()
+    phases = {k: [t / breakdown_steps, c / breakdown_steps] for k, (t, c) in collect(plans).items()}
+    for p in plans:
+        B.fmm_destroy(p)
+    return ms, phi, force, energy, m2l, phases, st, work
 
 
 def cpu_baseline(pos, q, wl, nboxes):
@@ -185,10 +201,11 @@ def main():
         nbytes = B.fmm_workspace_size(cfg, wl.n)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         print(f"[bench] {name}: workspace {nbytes / 2**20:.0f} MiB", file=sys.stderr, flush=True)
-        ms, phi, force, energy, phases, st, work = timed_steps(
+        ms, phi, force, energy, m2l, phases, st, work = timed_steps(
             B, torch, pos, q, cfg, ws, args.steps, args.warmup, stream)
         results[name] = dict(ms=ms, phi=phi.cpu().numpy(), force=force.cpu().numpy(),
-                             energy=float(energy.cpu()[0]), phases=phases, status=st, work=work)
+                             energy=float(energy.cpu()[0]), m2l=m2l, phases=phases, status=st,
+                             work=work)
         print(f"[bench] {name}: {ms:.3f} ms/step, status {st}", file=sys.stderr, flush=True)
         del ws
         torch.cuda.empty_cache()
@@ -197,7 +214,7 @@ def main():
         r = results[args.only]
         print(json.dumps({"only": args.only, "ms_per_step": r["ms"],
                           "value": wl.n / (r["ms"] / 1e3), "status": r["status"],
-                          "phases_ms_per_step": {k: v[0] / args.steps for k, v in r["phases"].items()}}),
+                          "phases_ms_per_step": {k: v[0] for k, v in r["phases"].items()}}),
               flush=True)
         return
     golden_path = os.path.join(HERE, "tests", "golden", "headline_oracle.json")
@@ -216,7 +233,7 @@ def main():
         matrix-core flops per launch (piece products for the split forms) over
         that duration, against the dense peak of its own dtype."""
         _, _, kernel, _, dtype, nprod = VARIANTS[name]
-        t, c = results[name]["phases"]["m2l"]
+        t, c = results[name]["m2l"]
         avg_ms = t / c
         flops = nprod * m2l_flops
         ach = flops / (avg_ms / 1e3) / 1e12
@@ -233,7 +250,7 @@ def main():
                 np.linalg.norm(r["force"] - f64["force"]) / np.linalg.norm(f64["force"])),
             "rel_phi_err_vs_fp64_gpu": float(
                 np.linalg.norm(r["phi"] - f64["phi"]) / np.linalg.norm(f64["phi"])),
-            "phases_ms_per_step": {k: v[0] / args.steps for k, v in r["phases"].items()},
+            "phases_ms_per_step": {k: v[0] for k, v in r["phases"].items()},
             "m2l": m2l_rate(name),
         }
     hl = variants[HEADLINE]

@@ -171,11 +171,14 @@ fmm_status fmm_plan_cube(fmm_plan_t *plan, double lo[3], double *side);
  * function; returns 0 for arguments out of range. */
 uint64_t fmm_hilbert_index(uint32_t ix, uint32_t iy, uint32_t iz, int32_t bits);
 
-/* Kernel-duration recording.  While enabled, the library records HIP events on
- * the call's stream around each pass it launches.  fmm_profile_read waits for
- * them, writes for each pass (FMM_PHASE_*) the summed duration in ms and the
- * number of launches, and clears the record.  Capacity: 8192 launches between
- * reads (later launches are not recorded). */
+/* Kernel-duration recording.  fmm_profile_enable(plan, mask) selects the
+ * passes to time: bit (1 << FMM_PHASE_x) for pass x, FMM_PROFILE_ALL for every
+ * pass, 0 for none (the default).  For each selected pass the library records
+ * HIP events on the call's stream around its launches (each event pair costs
+ * a few microseconds of stream time).  fmm_profile_read waits for them, writes
+ * for each pass (FMM_PHASE_*) the summed duration in ms and the number of
+ * launches, and clears the record.  Capacity: 8192 launches between reads
+ * (later launches are not recorded). */
 enum {
   FMM_PHASE_TREE = 0,   /* quantise, keys, count, scan, scatter, leaf sort, gather */
   FMM_PHASE_OPERATORS,  /* translation-operator tables */
@@ -188,7 +191,8 @@ enum {
   FMM_PHASE_ENERGY,
   FMM_PHASE_COUNT
 };
-fmm_status fmm_profile_enable(fmm_plan_t *plan, int enable);
+#define FMM_PROFILE_ALL 0x1ff
+fmm_status fmm_profile_enable(fmm_plan_t *plan, int phase_mask);
 fmm_status fmm_profile_read(fmm_plan_t *plan, double ms[FMM_PHASE_COUNT],
                             int32_t launches[FMM_PHASE_COUNT]);
 

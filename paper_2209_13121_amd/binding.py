@@ -180,8 +180,15 @@ def fmm_hilbert_index(ix, iy, iz, bits):
     return int(load().fmm_hilbert_index(ix, iy, iz, bits))
 
 
-def fmm_profile_enable(plan, on=True):
-    _check(load().fmm_profile_enable(plan, 1 if on else 0), "fmm_profile_enable")
+FMM_PROFILE_ALL = 0x1FF
+
+
+def fmm_profile_enable(plan, on=True, phases=None):
+    """Time the passes named in phases (default: every pass) while on."""
+    mask = 0
+    if on:
+        mask = FMM_PROFILE_ALL if phases is None else sum(1 << PHASES.index(p) for p in phases)
+    _check(load().fmm_profile_enable(plan, mask), "fmm_profile_enable")
 
 
 def fmm_profile_read(plan):

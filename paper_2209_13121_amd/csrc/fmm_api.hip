@@ -96,7 +96,8 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
 static inline fmm_status from_hip(hipError_t e) { return e == hipSuccess ? FMM_OK : FMM_E_DEVICE; }
 
 void prof_begin(fmm_plan_s* P, int phase, hipStream_t s) {
-  if (!P->profile || P->nrec >= kMaxProfile) return;
+  P->prof_open = false;
+  if (!((P->profile_mask >> phase) & 1u) || P->nrec >= kMaxProfile) return;
   ProfileRec& r = P->rec[P->nrec];
   if (P->nrec >= P->nevents_created) {
     if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
@@ -104,10 +105,12 @@ void prof_begin(fmm_plan_s* P, int phase, hipStream_t s) {
   }
   r.phase = phase;
   hipEventRecord(r.start, s);
+  P->prof_open = true;
 }
 
 void prof_end(fmm_plan_s* P, hipStream_t s) {
-  if (!P->profile || P->nrec >= kMaxProfile || P->nrec >= P->nevents_created) return;
+  if (!P->prof_open) return;
+  P->prof_open = false;
   hipEventRecord(P->rec[P->nrec].stop, s);
   P->nrec++;
 }
@@ -294,9 +297,10 @@ uint64_t fmm_hilbert_index(uint32_t ix, uint32_t iy, uint32_t iz, int32_t bits) 
   return hilbert_index(ix, iy, iz, bits);
 }
 
-fmm_status fmm_profile_enable(fmm_plan_t* P, int enable) {
+fmm_status fmm_profile_enable(fmm_plan_t* P, int phase_mask) {
   if (!P) return FMM_E_INVALID_ARG;
-  P->profile = enable != 0;
+  P->profile_mask = (uint32_t)phase_mask & ((1u << FMM_PHASE_COUNT) - 1u);
+  P->prof_open = false;
   return FMM_OK;
 }
 

@@ -125,7 +125,8 @@ struct fmm_plan_s {
   hipStream_t last_stream;
   bool has_charges;  // fmm_evaluate has run: sorted charges are in the workspace
   // profiling
-  bool profile;
+  uint32_t profile_mask;  // passes (bit 1 << FMM_PHASE_*) whose launches are timed
+  bool prof_open;         // prof_begin recorded a start event not yet closed
   int nrec;
   fmm::ProfileRec* rec;  // kMaxProfile entries, events created lazily
   int nevents_created;
