@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restri
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
   m2l::Tile tl;
-  if (!tl.setup(a, wave, col, sSlot, sBox)) return;  // uniform over the work-group
+  if (!tl.setup(a, wave * 16 + col, sSlot, sBox)) return;  // uniform over the work-group
   const int pi = tl.pi;
   const bool col_ok = tl.col_ok;
   const T* mlev = mult + tl.lvl_off * MS;

@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
   m2l::Tile tl;
-  if (!tl.setup(a, wave, col, sSlot, sBox)) return;  // uniform over the work-group
+  if (!tl.setup(a, wave * 16 + col, sSlot, sBox)) return;  // uniform over the work-group
   const int pi = tl.pi;
   const u32x4* mlev = multq + tl.lvl_off * QR;
 

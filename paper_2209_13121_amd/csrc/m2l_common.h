@@ -10,7 +10,7 @@
 //
 // One work-group owns 128 targets of one parity class at one level: the
 // parity-pi children of 128 consecutive, aligned parent slots in Hilbert
-// order.  Each of its 8 waves owns 16 of them (one MFMA column block).
+// order, 8 waves of 16 targets (one MFMA column block each).
 #ifndef FMM_M2L_COMMON_H_
 #define FMM_M2L_COMMON_H_
 
@@ -102,10 +102,10 @@ struct Tile {
   int hx0, hy0, hz0, hx1, hy1, hz1, hey, hez;  // halo box (clamped to the level)
   int64_t lvl_off;                             // first box of level l
 
-  // Decode the group, find this lane's target (column `col` of wave `wave`)
+  // Decode the group, find this lane's target (number tix of the tile's 128)
   // and stage the halo's slots in sSlot.  Returns false, uniformly over the
   // work-group, for a group past the end.  Contains barriers.
-  __device__ bool setup(const Args& a, int wave, int col, uint32_t* sSlot, int* sBox) {
+  __device__ bool setup(const Args& a, int tix, uint32_t* sSlot, int* sBox) {
     // XCD-aware order: hardware group b runs on XCD b % 8; each XCD gets a
     // contiguous range of logical groups.
     const int64_t per_xcd = (a.ngroups + 7) / 8;
@@ -122,7 +122,7 @@ struct Tile {
     const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
     nb = 1 << l;
     lvl_off = a.lvl_off[l];
-    const int64_t ps = tile * kTargetsPerGroup + wave * 16 + col;
+    const int64_t ps = tile * kTargetsPerGroup + tix;
     col_ok = ps < np;
     tx = ty = tz = 0;
     if (col_ok) {

@@ -268,12 +268,14 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
   k_gen_shift<<<16, kBlock, 0, s>>>(P->p, kp, rp, wsp<double>(P, lay.op_m2m),
                                     wsp<double>(P, lay.op_l2l));
   if (P->m2l_np) {
-    const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(P->nc, P->m2l_np) * 4;
+    const int np = P->m2l_np;
+    const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(P->nc, np) * 4;
     fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads
-    if (P->m2l_np == 2)
-      k_gen_m2l_bf<2><<<kNumM2LOps, kBlock, 0, s>>>(P->p, wsp<u32x4>(P, lay.op_m2lb));
+    u32x4* ob = wsp<u32x4>(P, lay.op_m2lb);
+    if (np == 2)
+      k_gen_m2l_bf<2><<<kNumM2LOps, kBlock, 0, s>>>(P->p, ob);
     else
-      k_gen_m2l_bf<3><<<kNumM2LOps, kBlock, 0, s>>>(P->p, wsp<u32x4>(P, lay.op_m2lb));
+      k_gen_m2l_bf<3><<<kNumM2LOps, kBlock, 0, s>>>(P->p, ob);
   } else if (P->mixed)
     k_gen_m2l<float><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, m2l_kstride_of(P->nc, 4),
                                                    wsp<float>(P, lay.op_m2l32));
