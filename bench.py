@@ -4,9 +4,10 @@ Workload: 2^20 charges uniform in the unit cube, Gaussian charges shifted to
 net zero (seed 1002), uniform octree of depth 6, expansion order p = 8.  One
 step = fmm_plan (tree build for the positions) + fmm_evaluate (all passes,
 potentials, forces and energy) on device-resident inputs.  Three variants are
-timed the same way: mixed precision with the split-BF16 M2L (the library's
-default mixed form, the headline value), mixed precision with the FP32 M2L,
-and FP64; every energy is compared to the stored FP64 oracle energy.
+timed the same way: mixed precision with the scaled split-FP16 M2L (the
+library's default mixed form, the headline value), with the split-BF16 M2L,
+with the FP32 M2L, and FP64; every energy is compared to the stored FP64
+oracle energy.
 
 Prints one JSON line.  ``--gpus N`` with N > 1 is refused: this build runs on
 one GPU.
@@ -22,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 METRIC = "particles/s per FMM evaluation at 1e-6 rel. energy err, mixed vs FP64"
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}  # MI355X dense matrix peaks
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0}  # MI355X dense matrix peaks
 
 # Timed variants: name -> (precision, m2l_kind, M2L kernel, its sources, dtype
 # of the matrix-core work, piece products per FP32 product).
@@ -31,6 +32,10 @@ VARIANTS = {
                      ["paper_2209_13121_amd/csrc/m2l_bf16.hip", "paper_2209_13121_amd/csrc/m2l_common.h",
                       "paper_2209_13121_amd/csrc/bf16_split.h", "paper_2209_13121_amd/csrc/fmm_internal.h"],
                      "bf16", 6),
+    "mixed_f16x2": ("MIXED", "F16X2", "k_m2l_bf<8,2,f16>",
+                    ["paper_2209_13121_amd/csrc/m2l_bf16.hip", "paper_2209_13121_amd/csrc/m2l_common.h",
+                     "paper_2209_13121_amd/csrc/bf16_split.h", "paper_2209_13121_amd/csrc/fmm_internal.h"],
+                    "f16", 3),
     "mixed_f32": ("MIXED", "F32", "k_m2l<8,float>",
                   ["paper_2209_13121_amd/csrc/m2l.hip", "paper_2209_13121_amd/csrc/m2l_common.h",
                    "paper_2209_13121_amd/csrc/fmm_internal.h"],
@@ -40,7 +45,7 @@ VARIANTS = {
               "paper_2209_13121_amd/csrc/fmm_internal.h"],
              "f64", 1),
 }
-HEADLINE = "mixed_bf16x3"  # the mixed form the library picks for FMM_M2L_AUTO
+HEADLINE = "mixed_f16x2"  # the mixed form the library picks for FMM_M2L_AUTO
 
 
 def traffic_summary(variant):
@@ -53,7 +58,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-boxes", type=int, default=1,
+    ap.add_argument("--cpu-sample-boxes", type=int, default=3,
                     help="level-1 boxes (1/8 of the domain each) whose particles the oracle evaluates")
     ap.add_argument("--only", choices=sorted(VARIANTS), default=None,
                     help="time one variant only (profiling runs)")
@@ -274,8 +279,10 @@ def main():
         "config": {"workload": wl.name, "n": wl.n, "depth": wl.depth, "p": wl.p, "seed": wl.seed,
                    "variant": HEADLINE,
                    "precision": "mixed (FP32 P2M/L2P/P2P, M2L on " +
-                                ("split-BF16 MFMA, 3 pieces" if VARIANTS[HEADLINE][4] == "bf16"
-                                 else "FP32 MFMA") + ", FP64 M2M/L2L/energy)",
+                                {"f16": "scaled split-FP16 MFMA, 2 pieces",
+                                 "bf16": "split-BF16 MFMA, 3 pieces",
+                                 "f32": "FP32 MFMA"}[VARIANTS[HEADLINE][4]] +
+                                ", FP64 M2M/L2L/energy)",
                    "step": "fmm_plan + fmm_evaluate"},
         "accuracy": {"oracle_energy": e_ref,
                      "rel_energy_err_vs_oracle": hl["rel_energy_err_vs_oracle"],

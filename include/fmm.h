@@ -67,21 +67,26 @@ typedef enum {
 
 typedef enum {
   FMM_PREC_FP64 = 0,  /* every pass in FP64 */
-  FMM_PREC_MIXED = 1  /* P2M, L2P, P2P in FP32, M2L on the FP32 or split-BF16 matrix
-                         cores with FP32 accumulation (fmm_m2l_kind); M2M, L2L, the
-                         combination of results and the energy in FP64 */
+  FMM_PREC_MIXED = 1  /* P2M, L2P, P2P in FP32, M2L on the FP32 matrix cores or on split
+                         FP16 / BF16 operands with FP32 accumulation (fmm_m2l_kind); M2M,
+                         L2L, the combination of results and the energy in FP64 */
 } fmm_precision;
 
 typedef enum {
-  FMM_M2L_AUTO = 0,   /* FMM_M2L_F64 for FMM_PREC_FP64, FMM_M2L_BF16X3 for FMM_PREC_MIXED */
+  FMM_M2L_AUTO = 0,   /* FMM_M2L_F64 for FMM_PREC_FP64, FMM_M2L_F16X2 for FMM_PREC_MIXED */
   FMM_M2L_F64 = 1,    /* FP64 matrix cores (FMM_PREC_FP64 only) */
   FMM_M2L_F32 = 2,    /* FP32 matrix cores (FMM_PREC_MIXED only) */
   FMM_M2L_BF16X2 = 3, /* BF16 matrix cores, operands split into 2 BF16 pieces, 3 piece
                          products, FP32 accumulation (FMM_PREC_MIXED only; about
                          16 significant bits per product, below the FP32 modes) */
-  FMM_M2L_BF16X3 = 4  /* BF16 matrix cores, operands split into 3 BF16 pieces (exact for
+  FMM_M2L_BF16X3 = 4, /* BF16 matrix cores, operands split into 3 BF16 pieces (exact for
                          FP32 values), the 6 piece products of total order <= 2, FP32
                          accumulation (FMM_PREC_MIXED only; FP32-level products) */
+  FMM_M2L_F16X2 = 5   /* FP16 matrix cores: operators and multipoles scaled by powers of
+                         two (per operator row and column, and per source box) into the
+                         FP16 range and split into 2 FP16 pieces, the 3 piece products
+                         of total order <= 1, FP32 accumulation (FMM_PREC_MIXED only;
+                         about 22 significant bits per product) */
 } fmm_m2l_kind;
 
 typedef struct {

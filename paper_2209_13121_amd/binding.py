@@ -17,7 +17,7 @@ FMM_ABI_VERSION = 1
 FMM_P_MAX = 12
 FMM_DEPTH_MAX = 9
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
-FMM_M2L_AUTO, FMM_M2L_F64, FMM_M2L_F32, FMM_M2L_BF16X2, FMM_M2L_BF16X3 = 0, 1, 2, 3, 4
+FMM_M2L_AUTO, FMM_M2L_F64, FMM_M2L_F32, FMM_M2L_BF16X2, FMM_M2L_BF16X3, FMM_M2L_F16X2 = 0, 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "FMM_OK", 1: "FMM_E_INVALID_ARG", 2: "FMM_E_WORKSPACE", 3: "FMM_E_OUT_OF_CUBE",
                 4: "FMM_E_NONFINITE", 5: "FMM_E_COINCIDENT", 6: "FMM_E_UNSUPPORTED",
                 7: "FMM_E_DEVICE"}

@@ -1,4 +1,5 @@
-// bf16_split.h -- BF16 pieces of FP32 / FP64 values for the split-BF16 M2L.
+// bf16_split.h -- BF16 and FP16 pieces of FP32 / FP64 values for the split
+// M2L forms.
 //
 // x is carried as np BF16 pieces x = x0 + x1 (+ x2), x0 = bf16(x),
 // x1 = bf16(x - x0), x2 = bf16(x - x0 - x1), each rounded to nearest even.
@@ -40,6 +41,21 @@ __host__ __device__ inline void split_f64(double x, uint32_t* piece) {
     piece[i] = bf16_bits((float)x);
     x -= (double)bf16_value(piece[i]);
   }
+}
+
+// FP16 pieces: x = h + l with h = fp16(x), l = fp16(x - h), round to nearest
+// even (callers scale x into the FP16 range first); about 22 significant bits.
+__device__ inline uint32_t f16_bits(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+__device__ inline float f16_value(uint32_t b) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)b);
+}
+__device__ inline void split_f16_f32(float x, uint32_t* piece) {
+  piece[0] = f16_bits(x);
+  piece[1] = f16_bits(x - f16_value(piece[0]));
+}
+__device__ inline void split_f16_f64(double x, uint32_t* piece) {
+  piece[0] = f16_bits((float)x);
+  piece[1] = f16_bits((float)(x - (double)f16_value(piece[0])));
 }
 
 // The NP quads of 8 values given as pieces pc[j][i] (value j, piece i).

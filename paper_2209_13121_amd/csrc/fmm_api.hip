@@ -13,9 +13,16 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 int m2l_pieces(const fmm_config& cfg) {
   if (cfg.precision != FMM_PREC_MIXED) return 0;
-  if (cfg.m2l_kind == FMM_M2L_BF16X2) return 2;
-  if (cfg.m2l_kind == FMM_M2L_BF16X3 || cfg.m2l_kind == FMM_M2L_AUTO) return 3;
+  if (cfg.m2l_kind == FMM_M2L_BF16X2 || cfg.m2l_kind == FMM_M2L_F16X2 ||
+      cfg.m2l_kind == FMM_M2L_AUTO)
+    return 2;
+  if (cfg.m2l_kind == FMM_M2L_BF16X3) return 3;
   return 0;
+}
+
+bool m2l_is_f16(const fmm_config& cfg) {  // FMM_M2L_F16X2, the mixed AUTO choice
+  return cfg.precision == FMM_PREC_MIXED &&
+         (cfg.m2l_kind == FMM_M2L_F16X2 || cfg.m2l_kind == FMM_M2L_AUTO);
 }
 
 bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
@@ -87,6 +94,14 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
       lay->multb = take(16 * NB * rq);
       lay->op_m2lb = take(16 * (size_t)kNumM2LOps * m2lb_op_quads(nc, np));
     }
+    if (m2l_is_f16(cfg)) {
+      const size_t rp = (size_t)m2lb_rows(nc), kp = (size_t)32 * m2lb_ksteps(nc);
+      lay->f16_mscale = take(sizeof(float) * NB);
+      lay->f16_rowf = take(sizeof(float) * rp);
+      lay->f16_colf = take(sizeof(float) * kp);
+      lay->f16_tbl = take(sizeof(uint32_t) * rp * kp);
+      lay->op_m2l_scratch = take(sizeof(double) * (size_t)kNumM2LOps * rp * kp);
+    }
   }
   lay->work = take(sizeof(int64_t) * 2);
   lay->total = cur;
@@ -123,7 +138,7 @@ static fmm_status validate_config(const fmm_config* cfg) {
   if (cfg->ws != 1) return FMM_E_INVALID_ARG;
   if (cfg->leaf_max != 0) return FMM_E_UNSUPPORTED;
   if (cfg->precision != FMM_PREC_FP64 && cfg->precision != FMM_PREC_MIXED) return FMM_E_INVALID_ARG;
-  if (cfg->m2l_kind < FMM_M2L_AUTO || cfg->m2l_kind > FMM_M2L_BF16X3) return FMM_E_INVALID_ARG;
+  if (cfg->m2l_kind < FMM_M2L_AUTO || cfg->m2l_kind > FMM_M2L_F16X2) return FMM_E_INVALID_ARG;
   if (cfg->m2l_kind == FMM_M2L_F64 && cfg->precision != FMM_PREC_FP64) return FMM_E_UNSUPPORTED;
   if (cfg->m2l_kind >= FMM_M2L_F32 && cfg->precision != FMM_PREC_MIXED) return FMM_E_UNSUPPORTED;
   for (int a = 0; a < 3; ++a)
@@ -184,6 +199,7 @@ fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void*
   P->nc = ncoef(cfg->p);
   P->mixed = cfg->precision == FMM_PREC_MIXED;
   P->m2l_np = m2l_pieces(*cfg);
+  P->m2l_f16 = m2l_is_f16(*cfg);
   P->ws = static_cast<char*>(d_workspace);
   P->last_stream = reinterpret_cast<hipStream_t>(stream);
   P->rec = static_cast<ProfileRec*>(calloc(kMaxProfile, sizeof(ProfileRec)));

@@ -95,8 +95,13 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t leaf_loc32;       // leaf local expansions FP32 (mixed; row stride mstride)
   size_t op_m2m, op_l2l;   // 8 octant operators each, FP64 [oct][row][k] (shift_kpad)
   size_t op_m2l64, op_m2l32;
-  size_t multb;            // split-BF16 M2L: multipoles as BF16 pieces, all boxes
-  size_t op_m2lb;          // split-BF16 M2L: operators as BF16 pieces
+  size_t multb;            // split M2L: multipoles as BF16 / FP16 pieces, all boxes
+  size_t op_m2lb;          // split M2L: operators as BF16 / FP16 pieces
+  size_t f16_mscale;       // FP16 M2L: per box, the inverse of its power-of-two scale
+  size_t f16_rowf;         // FP16 M2L: per operator row, the inverse row scale
+  size_t f16_colf;         // FP16 M2L: per k, the inverse column scale (applied to multipoles)
+  size_t f16_tbl;          // FP16 M2L: per (row, k), max |entry| over the operators (float bits)
+  size_t op_m2l_scratch;   // FP16 M2L: FP64 operator entries [op][row][k] at plan time
   size_t work;             // 2 x int64 counters
   size_t total;
   int64_t n, nleaf, nbox, n_energy_part, scan_tmp_elems;
@@ -104,8 +109,9 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
 };
 
 bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay);
-// BF16 pieces per operand of the M2L (2 or 3), or 0 for FP32/FP64 MFMA.
+// BF16 / FP16 pieces per operand of the M2L (2 or 3), or 0 for FP32/FP64 MFMA.
 int m2l_pieces(const fmm_config& cfg);
+bool m2l_is_f16(const fmm_config& cfg);  // FMM_M2L_F16X2
 
 struct ProfileRec {
   int phase;
@@ -120,7 +126,8 @@ struct fmm_plan_s {
   int64_t n;
   int L, p, nc;
   bool mixed;
-  int m2l_np;  // m2l_pieces(cfg)
+  int m2l_np;    // m2l_pieces(cfg)
+  bool m2l_f16;  // m2l_is_f16(cfg): the pieces are scaled FP16
   char* ws;
   hipStream_t last_stream;
   bool has_charges;  // fmm_evaluate has run: sorted charges are in the workspace

@@ -44,8 +44,11 @@ using m2l::kThreads;
 #define M2LB_FLUSH 4
 #endif
 constexpr int kFlush = M2LB_FLUSH;
+// FP16 form: offsets per FP32 partial sum.
+constexpr int kGroupF16 = 8;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Piece products (a piece, b piece) with i + j < NP, smallest first.
@@ -87,6 +90,42 @@ __global__ void k_split_mult(const float* __restrict__ m32, int ms, int nc, int 
   for (int i = 0; i < NP; ++i) o[(ks * NP + i) * 4 + g] = q[i];
 }
 
+// FP16 form: every box's FP32 multipole row times the column factors colf_k,
+// scaled by a power of two 2^s_b so that its largest entry lies in
+// [2^13, 2^14), split into 2 FP16 pieces; mscale_b = 2^-s_b.  32 lanes per box,
+// lane u holding k = 8 u .. 8 u + 7 (quad (ks * 2 + piece) * 4 + g, u = 4 ks + g).
+__global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, int kst, int64_t nbox,
+                               const float* __restrict__ colf, u32x4* __restrict__ out,
+                               float* __restrict__ mscale) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t box = t / 32;
+  const int u = (int)(t % 32);
+  const bool live = box < nbox && u < 4 * kst;
+  float v[8];
+  float m = 0.f;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = 8 * u + j;
+    v[j] = (live && k < nc) ? m32[box * ms + k] * colf[k] : 0.f;
+    m = fmaxf(m, fabsf(v[j]));
+  }
+#pragma unroll
+  for (int w = 16; w >= 1; w >>= 1) m = fmaxf(m, __shfl_xor(m, w, 32));  // box max
+  int e = 0;
+  if (m > 0.f) frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+  if (!live) return;
+  uint32_t pc[8][2];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) split_f16_f32(ldexpf(v[j], 14 - e), pc[j]);
+  u32x4 q[2];
+  pack_quads<2>(pc, q);
+  u32x4* o = out + box * (kst * 2 * 4);
+  const int ks = u / 4, g = u % 4;
+  o[(ks * 2 + 0) * 4 + g] = q[0];
+  o[(ks * 2 + 1) * 4 + g] = q[1];
+  if (u == 0) mscale[box] = ldexpf(1.f, e - 14);
+}
+
 // Shape of the kernel for order P and NP pieces.
 template <int P, int NP>
 struct Shape {
@@ -109,11 +148,16 @@ struct Shape {
   static constexpr bool PREFETCH_B = KST * NP <= 9;
 };
 
-template <int P, int NP>
+// F16: FP16 pieces of scaled operands (FMM_M2L_F16X2): per-offset FP32 chains
+// times the source box's inverse scale, summed in two levels (partials of
+// kGroupF16 offsets), rows times rowf at the end.
+template <int P, int NP, bool F16>
 __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* __restrict__ multq,
                                                      const u32x4* __restrict__ zero_q,
                                                      const u32x4* __restrict__ ops,
-                                                     float* __restrict__ out) {
+                                                     float* __restrict__ out,
+                                                     const float* __restrict__ mscale,
+                                                     const float* __restrict__ rowf) {
   typedef Shape<P, NP> S;
   typedef Prod<NP> PR;
   constexpr int NC = S::NC, RB = S::RB, RP = S::RP, KST = S::KST, QR = S::QR;
@@ -184,17 +228,26 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
         for (int t = 0; t < PR::N; ++t)
 #pragma unroll
           for (int rr = 0; rr < RG; ++rr)
-            if (r0 + rr < RB)
-              acc[r0 + rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                  __builtin_bit_cast(bf16x8, av[rr][PR::a[t]]),
-                  __builtin_bit_cast(bf16x8, b[ks * NP + PR::b[t]]), acc[r0 + rr], 0, 0, 0);
+            if (r0 + rr < RB) {
+              if (F16)
+                acc[r0 + rr] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                    __builtin_bit_cast(f16x8, av[rr][PR::a[t]]),
+                    __builtin_bit_cast(f16x8, b[ks * NP + PR::b[t]]), acc[r0 + rr], 0, 0, 0);
+              else
+                acc[r0 + rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    __builtin_bit_cast(bf16x8, av[rr][PR::a[t]]),
+                    __builtin_bit_cast(bf16x8, b[ks * NP + PR::b[t]]), acc[r0 + rr], 0, 0, 0);
+            }
       }
     }
   };
 
   constexpr bool PB = S::PREFETCH_B;
+  constexpr int FLUSH = F16 ? 1 : kFlush;  // FP16: each offset has its own source scale
   u32x4 reg[S::PER_THREAD];
   u32x4 b0[KST * NP], b1[PB ? KST * NP : 1];
+  // source box scale (FP16 form): of the current and of the next offset
+  auto scale_of = [&](m2l::Src src) -> float { return F16 && src.ok ? mscale[tl.lvl_off + src.slot] : 1.f; };
   // Pipeline over the class's offsets: offset i is computed while the
   // operator of the next stage and the B quads of offset i + 1 are loaded and
   // the source slot of offset i + 2 is looked up.
@@ -204,6 +257,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   m2l::Src s_cur = tl.lookup(sSlot, dx, dy, dz);
   m2l::Src s_next = tl.lookup(sSlot, ndx, ndy, ndz);
   bool wave_any = false;
+  float sc_cur = scale_of(s_cur), sc_next = 0.f;
   if (PB) {
     load_b(row_of(s_cur), b0);
     wave_any = __any(s_cur.ok);
@@ -226,9 +280,33 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
     for (int ch = 0; ch < NCH; ++ch) {
       const bool last_chunk = ch == NCH - 1;
       stage_load(last_chunk ? (more ? nop : op) : op, last_chunk ? 0 : ch + 1, reg);
-      if (PB && ch == 0) load_b(row_of(s_next), bn);
+      if (PB && ch == 0) {
+        load_b(row_of(s_next), bn);
+        sc_next = scale_of(s_next);
+      }
       if (wave_any) compute_chunk(sT[cur], ch, bc);
-      if (last_chunk && (kFlush == 1 ? wave_any : ((i + 1) % kFlush == 0 || !more))) {
+      if (F16 && last_chunk) {
+        // each offset's chain times its source scale into an FP32 partial
+        // (fused, exact scaling), the partial into the sum every kGroupF16
+        // offsets (emulated at the headline size: 1.9e-7 of phi from the M2L
+        // rounding, against 1.35e-7 with Kahan after every offset)
+        if (wave_any) {
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) comp[r][e] = fmaf(acc[r][e], sc_cur, comp[r][e]);
+            acc[r] = f32x4{0, 0, 0, 0};
+          }
+        }
+        if ((i + 1) % kGroupF16 == 0 || !more) {
+#pragma unroll
+          for (int r = 0; r < RB; ++r) {
+            sum[r] += comp[r];
+            comp[r] = f32x4{0, 0, 0, 0};
+          }
+        }
+      }
+      if (!F16 && last_chunk && (FLUSH == 1 ? wave_any : ((i + 1) % FLUSH == 0 || !more))) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
           const f32x4 y = acc[r] - comp[r];
@@ -253,6 +331,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
     ndy = fdy;
     ndz = fdz;
     if (PB) wave_any = __any(s_next.ok);
+    sc_cur = PB ? sc_next : scale_of(s_next);
     s_cur = s_next;
     s_next = s_far;
     return true;
@@ -274,7 +353,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = 16 * r + 4 * kg + e;
-      if (row < NC) o[row] = sum[r][e];
+      if (row < NC) o[row] = F16 ? sum[r][e] * rowf[row] : sum[r][e];
     }
 }
 
@@ -292,12 +371,29 @@ struct M2LBfRun {
         wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox,
         mq + box0 * qr);
     const m2l::Args a = m2l::make_args(Pl);
-    k_m2l_bf<P, NP><<<m2l::grid_of(a), kThreads, 0, s>>>(a, mq, wsp<u32x4>(Pl, lay.zero_row),
-                                                        wsp<u32x4>(Pl, lay.op_m2lb),
-                                                        wsp<float>(Pl, lay.m2l_out));
+    k_m2l_bf<P, NP, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
+        a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+        nullptr, nullptr);
+    return hipGetLastError();
+  }
+  static hipError_t go_f16(fmm_plan_s* Pl, hipStream_t s) {
+    const Layout& lay = Pl->lay;
+    const int nc = Pl->nc, kst = m2lb_ksteps(nc);
+    const int64_t box0 = lay.lvl_off[2], nbox = lay.nbox - box0;
+    u32x4* mq = wsp<u32x4>(Pl, lay.multb);
+    const int qr = m2lb_row_quads(nc, 2);
+    float* msc = wsp<float>(Pl, lay.f16_mscale);
+    k_split_mult_h<<<grid_for(nbox * 32, kBlock), kBlock, 0, s>>>(
+        wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox,
+        wsp<float>(Pl, lay.f16_colf), mq + box0 * qr, msc + box0);
+    const m2l::Args a = m2l::make_args(Pl);
+    k_m2l_bf<P, 2, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
+        a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+        msc, wsp<float>(Pl, lay.f16_rowf));
     return hipGetLastError();
   }
   static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
+    if (Pl->m2l_f16) return go_f16(Pl, s);
     return Pl->m2l_np == 2 ? go<2>(Pl, s) : go<3>(Pl, s);
   }
 };

@@ -259,6 +259,97 @@ __global__ void k_gen_m2l_bf(int p, u32x4* __restrict__ ops) {
   }
 }
 
+// ---- FP16 split M2L operators (FMM_M2L_F16X2) --------------------------
+// The entries span many decades (|I_j^m(d)| grows like (j - m)! / |d|^(j+1)),
+// more than FP16 holds, so each row r and column k gets a power-of-two scale,
+// shared by all 316 operators: T'[r][k] = T[r][k] 2^(ra_r + cb_k), rows
+// normalised first (max over k and operators -> 1), then columns, then all
+// rows shifted so that the largest entry is just below 2^14.  The column
+// scale is applied to the multipoles (times 2^-cb_k) and the row scale undone
+// on the M2L results (times 2^-ra_r); both are exact.
+
+// Pass 1: FP64 entries of every operator into scratch [op][row][k] (rows
+// padded to 16, k to 32, zero outside).
+__global__ void k_gen_m2l_f64(int p, double* __restrict__ scratch) {
+  __shared__ double tre[kTabMax], tim[kTabMax];
+  const int op = blockIdx.x;
+  if ((int)threadIdx.x <= 2 * p) {
+    int o[3];
+    m2l_offset(op, o);
+    irregular_column((double)o[0], (double)o[1], (double)o[2], 2 * p, threadIdx.x, tre, tim);
+  }
+  __syncthreads();
+  const int nc = (p + 1) * (p + 1);
+  const int rp = m2lb_rows(nc), kp = 32 * m2lb_ksteps(nc);
+  double* out = scratch + (size_t)op * rp * kp;
+  for (int e = threadIdx.x; e < rp * kp; e += blockDim.x) {
+    const int row = e / kp, k = e % kp;
+    out[e] = (row < nc && k < nc) ? m2l_entry(p, row, k, tre, tim) : 0.0;
+  }
+}
+
+// Pass 2: tbl[row][k] = max over operators of |entry| (FP32).
+__global__ void k_f16_table(int rpkp, const double* __restrict__ scratch, float* __restrict__ tbl) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rpkp) return;
+  double m = 0.0;
+  for (int op = 0; op < kNumM2LOps; ++op) m = fmax(m, fabs(scratch[(size_t)op * rpkp + e]));
+  tbl[e] = (float)m;
+}
+
+// Pass 3 (one work-group): the row and column exponents, as inverse factors
+// rowf_r = 2^-ra_r and colf_k = 2^-cb_k.
+__global__ void k_f16_fit(int rp, int kp, const float* __restrict__ tbl, float* __restrict__ rowf,
+                          float* __restrict__ colf) {
+  __shared__ int ra[256];
+  for (int r = threadIdx.x; r < rp; r += blockDim.x) {
+    float m = 0.f;
+    for (int k = 0; k < kp; ++k) m = fmaxf(m, tbl[r * kp + k]);
+    int e = 0;
+    if (m > 0.f) frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+    ra[r] = -e;                  // max of the row times 2^ra in [0.5, 1)
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < kp; k += blockDim.x) {
+    float m = 0.f;
+    for (int r = 0; r < rp; ++r) m = fmaxf(m, ldexpf(tbl[r * kp + k], ra[r]));
+    int e = 0;
+    if (m > 0.f) frexpf(m, &e);
+    colf[k] = ldexpf(1.f, e);  // cb_k = -e
+  }
+  __syncthreads();
+  // every scaled entry is now below 1: shift all rows by 2^14
+  for (int r = threadIdx.x; r < rp; r += blockDim.x) rowf[r] = ldexpf(1.f, -(ra[r] + 14));
+}
+
+// Pass 4: scaled entries split into 2 FP16 pieces, in the split-M2L operator
+// layout (m2lb_* with np = 2); one thread per (op, row, k step, lane group).
+__global__ void k_f16_split_ops(int p, int64_t nitems, const double* __restrict__ scratch,
+                                const float* __restrict__ rowf, const float* __restrict__ colf,
+                                u32x4* __restrict__ ops) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nitems) return;
+  const int nc = (p + 1) * (p + 1);
+  const int kst = m2lb_ksteps(nc), rp = m2lb_rows(nc), kp = 32 * kst, kc = m2lb_kc(nc, 2);
+  const int gq = m2lb_gq(kc, 2), qcs = m2lb_qcs(kc, 2);
+  const int g = (int)(t % 4), ks = (int)(t / 4 % kst), row = (int)(t / (4 * kst) % rp);
+  const int op = (int)(t / (4 * kst * rp));
+  const double* src = scratch + ((size_t)op * rp + row) * kp;
+  const double rs = 1.0 / (double)rowf[row];
+  uint32_t pc[8][2];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = 32 * ks + 8 * g + j;
+    split_f16_f64(src[k] * rs / (double)colf[k], pc[j]);
+  }
+  u32x4 q[2];
+  pack_quads<2>(pc, q);
+  u32x4* o = ops + (size_t)op * m2lb_op_quads(nc, 2) + ((size_t)(ks / kc) * rp + row) * qcs + g * gq +
+             (ks % kc) * 2;
+  o[0] = q[0];
+  o[1] = q[1];
+}
+
 }  // namespace
 
 hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
@@ -267,7 +358,21 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
   const int kp = shift_kpad(P->nc), rp = m2l_rows_pad(P->p);
   k_gen_shift<<<16, kBlock, 0, s>>>(P->p, kp, rp, wsp<double>(P, lay.op_m2m),
                                     wsp<double>(P, lay.op_l2l));
-  if (P->m2l_np) {
+  if (P->m2l_f16) {
+    const int nc = P->nc, rpp = m2lb_rows(nc), kp = 32 * m2lb_ksteps(nc);
+    const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(nc, 2) * 4;
+    fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads
+    double* scratch = wsp<double>(P, lay.op_m2l_scratch);
+    float* tbl = wsp<float>(P, lay.f16_tbl);
+    float* rowf = wsp<float>(P, lay.f16_rowf);
+    float* colf = wsp<float>(P, lay.f16_colf);
+    k_gen_m2l_f64<<<kNumM2LOps, kBlock, 0, s>>>(P->p, scratch);
+    k_f16_table<<<grid_for(rpp * kp, kBlock), kBlock, 0, s>>>(rpp * kp, scratch, tbl);
+    k_f16_fit<<<1, kBlock, 0, s>>>(rpp, kp, tbl, rowf, colf);
+    const int64_t items = (int64_t)kNumM2LOps * rpp * m2lb_ksteps(nc) * 4;
+    k_f16_split_ops<<<grid_for(items, kBlock), kBlock, 0, s>>>(P->p, items, scratch, rowf, colf,
+                                                               wsp<u32x4>(P, lay.op_m2lb));
+  } else if (P->m2l_np) {
     const int np = P->m2l_np;
     const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(P->nc, np) * 4;
     fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads

@@ -46,7 +46,8 @@ def test_config_validation(lib):
             B.fmm_workspace_size(cfg, n)
         assert ei.value.status == code, (field, bad)
     for prec, kind in [(B.FMM_PREC_MIXED, B.FMM_M2L_F64), (B.FMM_PREC_FP64, B.FMM_M2L_F32),
-                       (B.FMM_PREC_FP64, B.FMM_M2L_BF16X2), (B.FMM_PREC_FP64, B.FMM_M2L_BF16X3)]:
+                       (B.FMM_PREC_FP64, B.FMM_M2L_BF16X2), (B.FMM_PREC_FP64, B.FMM_M2L_BF16X3),
+                       (B.FMM_PREC_FP64, B.FMM_M2L_F16X2)]:
         cfg = B.make_config(precision=prec, m2l_kind=kind)
         with pytest.raises(B.FMMError) as ei:
             B.fmm_workspace_size(cfg, n)
@@ -60,8 +61,8 @@ def test_config_validation(lib):
 
 
 def test_split_bf16_workspace(lib):
-    # The split-BF16 M2L keeps BF16 pieces of every multipole and operator in
-    # place of the FP32 operators: 3 pieces need more room than 2.
+    # The split M2L forms keep pieces of every multipole and operator in place
+    # of the FP32 operators: 3 pieces need more room than 2.
     n = 4096
     for p in (0, 4, 8, 12):
         f32 = B.fmm_workspace_size(B.make_config(depth=3, p=p, precision=B.FMM_PREC_MIXED,
@@ -70,7 +71,9 @@ def test_split_bf16_workspace(lib):
                                                 m2l_kind=B.FMM_M2L_BF16X2), n)
         x3 = B.fmm_workspace_size(B.make_config(depth=3, p=p, precision=B.FMM_PREC_MIXED,
                                                 m2l_kind=B.FMM_M2L_BF16X3), n)
-        assert f32 > 0 and x3 > x2, p
+        h2 = B.fmm_workspace_size(B.make_config(depth=3, p=p, precision=B.FMM_PREC_MIXED,
+                                                m2l_kind=B.FMM_M2L_F16X2), n)
+        assert f32 > 0 and x3 > x2 and h2 > x2, p  # FP16: scales and FP64 operator scratch too
 
 
 def test_workspace_size_monotone(lib):

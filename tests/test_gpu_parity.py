@@ -126,7 +126,8 @@ MIXED_CASES = [
 ]
 
 
-MIXED_KINDS = {"f32": B.FMM_M2L_F32, "bf16x3": B.FMM_M2L_BF16X3, "auto": B.FMM_M2L_AUTO}
+MIXED_KINDS = {"f32": B.FMM_M2L_F32, "bf16x3": B.FMM_M2L_BF16X3, "f16x2": B.FMM_M2L_F16X2,
+               "auto": B.FMM_M2L_AUTO}
 
 
 @pytest.mark.parametrize("kind", sorted(MIXED_KINDS))
@@ -147,6 +148,27 @@ def test_mixed_within_gate(case, kind):
     assert energy_rel(e, half_sum_q_phi(q, phi)) <= 1e-13
 
 
+@pytest.mark.parametrize("kind", ["f32", "bf16x3", "f16x2"])
+def test_mixed_charge_scales(kind):
+    # The FP16 form scales operands by powers of two (per operator row and
+    # column, per source box), so its accuracy must not depend on the charge
+    # magnitude, nor suffer where one region's charges dwarf the rest's.
+    pos, q = make(20000, "gauss", 46)
+    cases = [("x1e20", q * 1e20), ("x1e-20", q * 1e-20)]
+    q2 = q.copy()
+    q2[pos[:, 0] < 0.25] *= 1e8  # one region 1e8 times stronger
+    cases.append(("region-1e8", q2))
+    for name, qq in cases:
+        log(f"[mixed {kind}] charge scale {name}")
+        phi, force, e, _ = run_gpu(pos, qq, 4, 8, precision=B.FMM_PREC_MIXED,
+                                   m2l_kind=MIXED_KINDS[kind])
+        phi_o, force_o, e_o = oracle.fmm(pos, qq, 4, 8)
+        log(f"  dE {energy_rel(e, e_o):.2e} dF {rel(force, force_o):.2e} dphi {rel(phi, phi_o):.2e}")
+        assert energy_rel(e, e_o) <= 1e-6
+        assert rel(force, force_o) <= 1e-5
+        assert rel(phi, phi_o) <= 1e-5
+
+
 def test_mixed_bf16x2_accuracy():
     # Two pieces carry about 16 significant bits per product: a documented
     # looser mode, checked against its own bound (about 2^-16 of the far field).
@@ -162,7 +184,7 @@ def test_mixed_bf16x2_accuracy():
     assert energy_rel(e, e_o) <= 1e-4
 
 
-@pytest.mark.parametrize("kind", ["f32", "bf16x3"])
+@pytest.mark.parametrize("kind", ["f32", "bf16x3", "f16x2"])
 def test_headline_mixed_sampled(kind):
     wl = W.HEADLINE
     log(f"[mixed {kind}] {wl.name} (sampled)")
@@ -184,7 +206,8 @@ def test_headline_mixed_sampled(kind):
 
 @pytest.mark.parametrize("precision,kind", [(B.FMM_PREC_FP64, B.FMM_M2L_AUTO),
                                             (B.FMM_PREC_MIXED, B.FMM_M2L_F32),
-                                            (B.FMM_PREC_MIXED, B.FMM_M2L_BF16X3)])
+                                            (B.FMM_PREC_MIXED, B.FMM_M2L_BF16X3),
+                                            (B.FMM_PREC_MIXED, B.FMM_M2L_F16X2)])
 def test_deterministic(precision, kind):
     log(f"[determinism] precision {precision} m2l {kind}")
     pos, q = W.uniform_gauss(50000, 51)
