@@ -92,14 +92,15 @@ __global__ void k_split_mult(const float* __restrict__ m32, int ms, int nc, int 
 
 // FP16 form: every box's FP32 multipole row times the column factors colf_k,
 // scaled by a power of two 2^s_b so that its largest entry lies in
-// [2^13, 2^14), split into 2 FP16 pieces; mscale_b = 2^-s_b.  32 lanes per box,
-// lane u holding k = 8 u .. 8 u + 7 (quad (ks * 2 + piece) * 4 + g, u = 4 ks + g).
+// [2^13, 2^14), split into 2 FP16 pieces; mscale_b = 2^-s_b.  lpb (16 or 32)
+// lanes per box, lane u holding k = 8 u .. 8 u + 7 (quad (ks * 2 + piece) * 4 + g,
+// u = 4 ks + g).
 __global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, int kst, int64_t nbox,
-                               const float* __restrict__ colf, u32x4* __restrict__ out,
+                               int lpb, const float* __restrict__ colf, u32x4* __restrict__ out,
                                float* __restrict__ mscale) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t box = t / 32;
-  const int u = (int)(t % 32);
+  const int64_t box = t / lpb;
+  const int u = (int)(t % lpb);
   const bool live = box < nbox && u < 4 * kst;
   float v[8];
   float m = 0.f;
@@ -110,7 +111,8 @@ __global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, in
     m = fmaxf(m, fabsf(v[j]));
   }
 #pragma unroll
-  for (int w = 16; w >= 1; w >>= 1) m = fmaxf(m, __shfl_xor(m, w, 32));  // box max
+  for (int w = 16; w >= 1; w >>= 1)
+    if (w < lpb) m = fmaxf(m, __shfl_xor(m, w, lpb));  // box max
   int e = 0;
   if (m > 0.f) frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
   if (!live) return;
@@ -127,7 +129,7 @@ __global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, in
 }
 
 // Shape of the kernel for order P and NP pieces.
-template <int P, int NP>
+template <int P, int NP, bool F16 = false>
 struct Shape {
   static constexpr int NC = (P + 1) * (P + 1);
   static constexpr int RB = (NC + 15) / 16;  // 16-row blocks
@@ -142,7 +144,11 @@ struct Shape {
   static constexpr int QD = 4 * GQ;                  // quads of a row the MFMAs read
   static constexpr int NV = NC * QD;                 // quads staged per chunk
   static constexpr int PER_THREAD = (NV + kThreads - 1) / kThreads;
-  static constexpr int RG = RB < M2LB_RG ? RB : M2LB_RG;  // row blocks interleaved per A load
+  // row blocks whose MFMA chains are interleaved (per group of A loads):
+  // all of them in the FP16 form (measured: -7 % time at p = 8), fewer in the
+  // BF16 forms, whose extra piece would not fit the registers
+  static constexpr int RGW = F16 ? 6 : M2LB_RG;
+  static constexpr int RG = RB < RGW ? RB : RGW;
   // Prefetch the next offset's B quads (a second register set) where the
   // registers allow it.
   static constexpr bool PREFETCH_B = KST * NP <= 9;
@@ -158,7 +164,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
                                                      float* __restrict__ out,
                                                      const float* __restrict__ mscale,
                                                      const float* __restrict__ rowf) {
-  typedef Shape<P, NP> S;
+  typedef Shape<P, NP, F16> S;
   typedef Prod<NP> PR;
   constexpr int NC = S::NC, RB = S::RB, RP = S::RP, KST = S::KST, QR = S::QR;
   constexpr int KC = S::KC, NCH = S::NCH, GQ = S::GQ, QCS = S::QCS, RG = S::RG;
@@ -383,8 +389,9 @@ struct M2LBfRun {
     u32x4* mq = wsp<u32x4>(Pl, lay.multb);
     const int qr = m2lb_row_quads(nc, 2);
     float* msc = wsp<float>(Pl, lay.f16_mscale);
-    k_split_mult_h<<<grid_for(nbox * 32, kBlock), kBlock, 0, s>>>(
-        wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox,
+    const int lpb = 4 * kst <= 16 ? 16 : 32;
+    k_split_mult_h<<<grid_for(nbox * lpb, kBlock), kBlock, 0, s>>>(
+        wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox, lpb,
         wsp<float>(Pl, lay.f16_colf), mq + box0 * qr, msc + box0);
     const m2l::Args a = m2l::make_args(Pl);
     k_m2l_bf<P, 2, true><<<m2l::grid_of(a), kThreads, 0, s>>>(

@@ -184,13 +184,16 @@ __host__ __device__ inline double m2l_entry(int p, int row, int col, const doubl
   return real_entry(m, iim, oim, x1, x2);
 }
 
-// M2M and L2L tables: block b < 8 builds M2M of octant b, block 8 + b L2L,
-// stored [octant][row (padded to rp)][k (padded to kp)], zero padded.
+// M2M and L2L tables: blocks 8 s + b (s < kShiftSplit) build rows of the
+// M2M of octant b, blocks 8 (kShiftSplit + s) + b those of the L2L, stored
+// [octant][row (padded to rp)][k (padded to kp)], zero padded.
+constexpr int kShiftSplit = 8;
 __global__ void k_gen_shift(int p, int kp, int rp, double* __restrict__ m2m,
                             double* __restrict__ l2l) {
   __shared__ double tre[kTabMax], tim[kTabMax];
   const int oct = blockIdx.x & 7;
-  const bool is_l2l = blockIdx.x >= 8;
+  const bool is_l2l = (int)(blockIdx.x >> 3) >= kShiftSplit;
+  const int part = (blockIdx.x >> 3) % kShiftSplit;
   if (threadIdx.x == 0) {
     double w[3];
     octant_vector(oct, w);
@@ -199,7 +202,9 @@ __global__ void k_gen_shift(int p, int kp, int rp, double* __restrict__ m2m,
   __syncthreads();
   const int nc = (p + 1) * (p + 1);
   double* out = (is_l2l ? l2l : m2m) + (size_t)oct * kp * rp;
-  for (int e = threadIdx.x; e < kp * rp; e += blockDim.x) {  // [row][k]
+  const int rows = (rp + kShiftSplit - 1) / kShiftSplit, r0 = part * rows;
+  const int r1 = r0 + rows < rp ? r0 + rows : rp;
+  for (int e = r0 * kp + threadIdx.x; e < r1 * kp; e += blockDim.x) {  // [row][k]
     const int row = e / kp, col = e % kp;
     out[e] = (col < nc && row < nc) ? shift_entry(p, is_l2l, row, col, tre, tim) : 0.0;
   }
@@ -269,10 +274,12 @@ __global__ void k_gen_m2l_bf(int p, u32x4* __restrict__ ops) {
 // on the M2L results (times 2^-ra_r); both are exact.
 
 // Pass 1: FP64 entries of every operator into scratch [op][row][k] (rows
-// padded to 16, k to 32, zero outside).
+// padded to 16, k to 32, zero outside); kGenSplit blocks per operator, each
+// a range of rows.
+constexpr int kGenSplit = 4;
 __global__ void k_gen_m2l_f64(int p, double* __restrict__ scratch) {
   __shared__ double tre[kTabMax], tim[kTabMax];
-  const int op = blockIdx.x;
+  const int op = blockIdx.x / kGenSplit, part = blockIdx.x % kGenSplit;
   if ((int)threadIdx.x <= 2 * p) {
     int o[3];
     m2l_offset(op, o);
@@ -282,7 +289,9 @@ __global__ void k_gen_m2l_f64(int p, double* __restrict__ scratch) {
   const int nc = (p + 1) * (p + 1);
   const int rp = m2lb_rows(nc), kp = 32 * m2lb_ksteps(nc);
   double* out = scratch + (size_t)op * rp * kp;
-  for (int e = threadIdx.x; e < rp * kp; e += blockDim.x) {
+  const int rows = (rp + kGenSplit - 1) / kGenSplit, r0 = part * rows;
+  const int r1 = r0 + rows < rp ? r0 + rows : rp;
+  for (int e = r0 * kp + threadIdx.x; e < r1 * kp; e += blockDim.x) {
     const int row = e / kp, k = e % kp;
     out[e] = (row < nc && k < nc) ? m2l_entry(p, row, k, tre, tim) : 0.0;
   }
@@ -356,7 +365,7 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
   const Layout& lay = P->lay;
   prof_begin(P, FMM_PHASE_OPERATORS, s);
   const int kp = shift_kpad(P->nc), rp = m2l_rows_pad(P->p);
-  k_gen_shift<<<16, kBlock, 0, s>>>(P->p, kp, rp, wsp<double>(P, lay.op_m2m),
+  k_gen_shift<<<16 * kShiftSplit, kBlock, 0, s>>>(P->p, kp, rp, wsp<double>(P, lay.op_m2m),
                                     wsp<double>(P, lay.op_l2l));
   if (P->m2l_f16) {
     const int nc = P->nc, rpp = m2lb_rows(nc), kp = 32 * m2lb_ksteps(nc);
@@ -366,7 +375,7 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
     float* tbl = wsp<float>(P, lay.f16_tbl);
     float* rowf = wsp<float>(P, lay.f16_rowf);
     float* colf = wsp<float>(P, lay.f16_colf);
-    k_gen_m2l_f64<<<kNumM2LOps, kBlock, 0, s>>>(P->p, scratch);
+    k_gen_m2l_f64<<<kNumM2LOps * kGenSplit, kBlock, 0, s>>>(P->p, scratch);
     k_f16_table<<<grid_for(rpp * kp, kBlock), kBlock, 0, s>>>(rpp * kp, scratch, tbl);
     k_f16_fit<<<1, kBlock, 0, s>>>(rpp, kp, tbl, rowf, colf);
     const int64_t items = (int64_t)kNumM2LOps * rpp * m2lb_ksteps(nc) * 4;
