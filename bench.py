@@ -99,7 +99,7 @@ def m2l_traffic(variant):
     src_hash, traffic = None, None
     for line in open(path):
         if line.startswith("source sha256:"):
-            src_hash = line.split()[-1]
+            src_hash = line.split()[2]  # "source sha256: <hash>  (<files>)"
         if line.startswith("traffic_bytes_per_launch"):
             traffic = float(line.split()[-1])
     return traffic if src_hash == m2l_source_hash(variant) else None
@@ -124,14 +124,21 @@ def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream, breakdown_step
     for p in plans:
         B.fmm_destroy(p)
     plans = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    ev[0].record(stream)
+    for i in range(steps):
         p = B.fmm_plan(cfg, n, pos, ws, stream)
         B.fmm_profile_enable(p, True, phases=["m2l"])
         B.fmm_evaluate(p, q, phi, force, energy, stream)
+        ev[i + 1].record(stream)
         plans.append(p)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    per_step = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    step_stats = {"median_ms": per_step[steps // 2] if steps % 2 else
+                  0.5 * (per_step[steps // 2 - 1] + per_step[steps // 2]),
+                  "min_ms": per_step[0]}
 
     def collect(plans):
         out = {}
@@ -156,7 +163,39 @@ def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream, breakdown_step
     phases = {k: [t / breakdown_steps, c / breakdown_steps] for k, (t, c) in collect(plans).items()}
     for p in plans:
         B.fmm_destroy(p)
-    return ms, phi, force, energy, m2l, phases, st, work
+    return ms, step_stats, phi, force, energy, m2l, phases, st, work
+
+
+def p2p_evidence(B, torch, pos, q, stream, depth=4, reps=3):
+    """The near-field pass at a leaf occupancy where it carries real work: the
+    same charges on a depth-4 tree (256 per leaf on average).  Returns, per
+    precision, the P2P pass time (k_near, HIP events on the launch stream),
+    the ordered pair count of the plan and the rate at 19 flop per pair."""
+    n = q.numel()
+    phi = torch.empty(n, dtype=torch.float64, device=pos.device)
+    force = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
+    out = {}
+    for prec, peak in (("MIXED", 157.3), ("FP64", 78.6)):
+        cfg = B.make_config(p=8, depth=depth, precision=getattr(B, "FMM_PREC_" + prec))
+        ws = torch.empty(B.fmm_workspace_size(cfg, n), dtype=torch.uint8, device=pos.device)
+        t = c = 0.0
+        for r in range(reps + 1):
+            p = B.fmm_plan(cfg, n, pos, ws, stream)
+            B.fmm_profile_enable(p, True, phases=["p2p"])
+            B.fmm_evaluate(p, q, phi, force, None, stream)
+            torch.cuda.synchronize()
+            if r:  # the first is a warm-up
+                tt, cc = B.fmm_profile_read(p)["p2p"]
+                t += tt
+                c += cc
+            pairs = B.fmm_plan_work(p)[1]
+            B.fmm_destroy(p)
+        del ws
+        ms = t / c
+        tf = 19.0 * pairs / (ms / 1e3) / 1e12
+        out[prec.lower()] = {"depth": depth, "pairs": pairs, "avg_ms": ms, "tflops": tf,
+                             "vector_peak_tflops": peak, "frac": tf / peak}
+    return out
 
 
 def cpu_baseline(pos, q, wl, nboxes):
@@ -206,9 +245,10 @@ def main():
         nbytes = B.fmm_workspace_size(cfg, wl.n)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         print(f"[bench] {name}: workspace {nbytes / 2**20:.0f} MiB", file=sys.stderr, flush=True)
-        ms, phi, force, energy, m2l, phases, st, work = timed_steps(
+        ms, step_stats, phi, force, energy, m2l, phases, st, work = timed_steps(
             B, torch, pos, q, cfg, ws, args.steps, args.warmup, stream)
-        results[name] = dict(ms=ms, phi=phi.cpu().numpy(), force=force.cpu().numpy(),
+        results[name] = dict(ms=ms, step_stats=step_stats, phi=phi.cpu().numpy(),
+                             force=force.cpu().numpy(),
                              energy=float(energy.cpu()[0]), m2l=m2l, phases=phases, status=st,
                              work=work)
         print(f"[bench] {name}: {ms:.3f} ms/step, status {st}", file=sys.stderr, flush=True)
@@ -250,6 +290,7 @@ def main():
     for name, r in results.items():
         variants[name] = {
             "value": wl.n / (r["ms"] / 1e3), "ms_per_step": r["ms"], "status": r["status"],
+            "step_events_ms": r["step_stats"],
             "rel_energy_err_vs_oracle": erel(r["energy"]),
             "rel_rms_force_err_vs_fp64_gpu": float(
                 np.linalg.norm(r["force"] - f64["force"]) / np.linalg.norm(f64["force"])),
@@ -273,6 +314,7 @@ def main():
         "unit": "particles/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": hl["ms_per_step"],
+        "step_events_ms": hl["step_events_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": VARIANTS[HEADLINE][4] + "/f32",
         "data": "synthetic",
@@ -293,6 +335,8 @@ def main():
         "p2p_pairs": p2p_pairs,
         "roofline": roofline,
     }
+    print("[bench] p2p at depth 4", file=sys.stderr, flush=True)
+    out["p2p_depth4"] = p2p_evidence(B, torch, pos, q, stream)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pos_np, q_np, wl, args.cpu_sample_boxes)
