@@ -36,7 +36,10 @@ def load_library(path):
                                       ctypes.POINTER(ctypes.c_int32), d, d]
     lib.oracle_chain.argtypes = [ctypes.c_int, ctypes.c_int, i64, d, d, d, d, d, i64, d, d,
                                  ctypes.c_void_p]
-    for f in (lib.oracle_direct, lib.oracle_fmm, lib.oracle_leaf_cells, lib.oracle_chain):
+    lib.oracle_fmm_adaptive.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, ctypes.c_int, d,
+                                        ctypes.c_double, d, d, d, ctypes.POINTER(i64)]
+    for f in (lib.oracle_direct, lib.oracle_fmm, lib.oracle_leaf_cells, lib.oracle_chain,
+              lib.oracle_fmm_adaptive):
         f.restype = ctypes.c_int
     return lib
 
@@ -138,3 +141,26 @@ def chain(kind, p, src, q, x, c1, c2=(0, 0, 0), c3=(0, 0, 0)):
     if st:
         raise OracleError(st)
     return phi, grad
+
+
+ADAPTIVE_STATS = ("boxes", "leaves", "deepest", "u", "v", "w", "x", "p2p_pairs", "m2l_pairs")
+
+
+def fmm_adaptive(pos, q, leaf_max, max_depth, p, lo=(0.0, 0.0, 0.0), side=1.0, lib=None):
+    """FP64 FMM on the adaptive octree (boxes with more than leaf_max
+    particles divided, down to level max_depth; U, V, W, X lists).  Returns
+    (phi, force, energy, stats) with the tree's integer statistics."""
+    pos = _f64(pos, (-1, 3))
+    q = _f64(q)
+    n = len(q)
+    lo = _f64(lo)
+    phi = np.zeros(n)
+    force = np.zeros((n, 3))
+    e = np.zeros(1)
+    st_arr = np.zeros(len(ADAPTIVE_STATS), dtype=np.int64)
+    st = (lib or _lib()).oracle_fmm_adaptive(
+        n, _dp(pos), _dp(q), int(leaf_max), int(max_depth), int(p), _dp(lo), float(side),
+        _dp(phi), _dp(force), _dp(e), st_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    if st:
+        raise OracleError(st)
+    return phi, force, float(e[0]), dict(zip(ADAPTIVE_STATS, (int(v) for v in st_arr)))

@@ -653,3 +653,414 @@ int oracle_chain(int chain, int p, int64_t ns, const double *src, const double *
   free(C);
   return ORACLE_OK;
 }
+
+/* ======================================================================== */
+/* Adaptive octree FMM.                                                      */
+/* ======================================================================== */
+/*
+ * Tree (Cheng, Greengard & Rokhlin 1999, sec. 4; Carrier, Greengard &
+ * Rokhlin, SIAM J. Sci. Stat. Comput. 9:669 (1988)): the root is the cube; a
+ * box holding more than leaf_max particles is divided into its 8 children
+ * while its level is below max_depth.  All 8 children of a divided box are
+ * kept (an empty child is an empty leaf: it holds nothing and receives
+ * nothing, so the result is the same as with empty children dropped).  A
+ * particle's box at level l is its cell at max_depth shifted right by
+ * max_depth - l (the uniform tree's cell rule).
+ *
+ * "Adjacent" means the closed cubes touch; boxes may differ in size.
+ * Lists of a box b:
+ *   U(b), b a leaf: every leaf adjacent to b, b included        -> P2P
+ *   V(b): children of the colleagues (adjacent same-level boxes) of b's
+ *         parent that are not adjacent to b                      -> M2L
+ *   W(b), b a leaf: boxes finer than b, not adjacent to b, whose parent is
+ *         adjacent to b                                         -> M2P
+ *   X(b): leaves coarser than b, adjacent to b's parent and not adjacent to
+ *         b (b is in W of each of them)                         -> P2L
+ * Passes in the method's order: P2M at every leaf; M2M from the deepest level
+ * up to level 2; for levels 2, 3, ...: L2L from the parent (level >= 3), M2L
+ * over V, P2L over X; at every leaf: L2P (level >= 2), M2P over W, P2P over U.
+ *
+ * Two extra operators:
+ *   P2L  L_n^m += q conj(I_n^m(y - c))                 (A1 with the roles of
+ *        the two points exchanged, since 1/|x - y| is symmetric)
+ *   M2P with gradient: the multipole field's value and gradient at x are the
+ *        degree-0 and degree-1 coefficients of its local expansion about x
+ *        itself, i.e. (A3) with c_t = x and local degree <= 1.
+ */
+
+typedef struct {
+  int level, c[3];
+  int64_t parent, child0; /* child0 < 0: leaf; else children child0 .. child0+7 */
+  int64_t start, count;   /* particles order[start .. start+count) */
+} abox;
+
+typedef struct {
+  int p, nh, Lmax, leaf_max;
+  double lo[3], side;
+  int64_t n, nbox, cap;
+  abox *box;
+  int64_t lvl_first[ORACLE_LMAX + 2]; /* boxes are level-sorted (breadth first) */
+  int64_t *order;
+  int32_t *cell; /* n x 3, cell at Lmax */
+  cplx *M, *Lc;
+} atree;
+
+static void atree_free(atree *T) {
+  free(T->box);
+  free(T->order);
+  free(T->cell);
+  free(T->M);
+  free(T->Lc);
+}
+
+static int atree_push(atree *T, const abox *b) {
+  if (T->nbox == T->cap) {
+    const int64_t nc = T->cap ? 2 * T->cap : 64;
+    abox *nb = realloc(T->box, sizeof(abox) * nc);
+    if (!nb) return ORACLE_E_NOMEM;
+    T->box = nb;
+    T->cap = nc;
+  }
+  T->box[T->nbox++] = *b;
+  return ORACLE_OK;
+}
+
+static int atree_build(atree *T, int64_t n, const double *pos, int leaf_max, int Lmax, int p,
+                       const double lo_in[3], double side_in) {
+  memset(T, 0, sizeof(*T));
+  T->p = p;
+  T->nh = nharm(p);
+  T->Lmax = Lmax;
+  T->leaf_max = leaf_max;
+  T->n = n;
+  int st = resolve_cube(n, pos, lo_in, side_in, T->lo, &T->side);
+  if (st) return st;
+  T->cell = malloc(sizeof(int32_t) * 3 * (n ? n : 1));
+  T->order = malloc(sizeof(int64_t) * (n ? n : 1));
+  int64_t *tmp = malloc(sizeof(int64_t) * (n ? n : 1));
+  if (!T->cell || !T->order || !tmp) { free(tmp); return ORACLE_E_NOMEM; }
+  for (int64_t i = 0; i < n; ++i) {
+    T->order[i] = i;
+    for (int a = 0; a < 3; ++a) T->cell[3 * i + a] = leaf_cell_axis(pos[3 * i + a], T->lo[a], T->side, Lmax);
+  }
+  abox root = {0, {0, 0, 0}, -1, -1, 0, n};
+  st = atree_push(T, &root);
+  /* Breadth first, so the boxes come out sorted by level. */
+  for (int64_t b = 0; st == ORACLE_OK && b < T->nbox; ++b) {
+    const abox B = T->box[b];
+    if (B.count <= leaf_max || B.level >= Lmax) continue;
+    const int s = Lmax - (B.level + 1);
+    int64_t cnt[8] = {0}, off[8];
+    for (int64_t k = B.start; k < B.start + B.count; ++k) {
+      const int32_t *c = T->cell + 3 * T->order[k];
+      cnt[(((c[0] >> s) & 1) << 2) | (((c[1] >> s) & 1) << 1) | ((c[2] >> s) & 1)]++;
+    }
+    off[0] = B.start;
+    for (int ch = 1; ch < 8; ++ch) off[ch] = off[ch - 1] + cnt[ch - 1];
+    int64_t fill[8];
+    memcpy(fill, off, sizeof(fill));
+    for (int64_t k = B.start; k < B.start + B.count; ++k) { /* stable */
+      const int32_t *c = T->cell + 3 * T->order[k];
+      tmp[fill[(((c[0] >> s) & 1) << 2) | (((c[1] >> s) & 1) << 1) | ((c[2] >> s) & 1)]++] = T->order[k];
+    }
+    memcpy(T->order + B.start, tmp + B.start, sizeof(int64_t) * B.count);
+    T->box[b].child0 = T->nbox;
+    for (int ch = 0; ch < 8 && st == ORACLE_OK; ++ch) {
+      abox C = {B.level + 1,
+                {2 * B.c[0] + (ch >> 2), 2 * B.c[1] + ((ch >> 1) & 1), 2 * B.c[2] + (ch & 1)},
+                b, -1, off[ch], cnt[ch]};
+      st = atree_push(T, &C);
+    }
+  }
+  free(tmp);
+  if (st) return st;
+  for (int l = 0; l <= ORACLE_LMAX + 1; ++l) T->lvl_first[l] = T->nbox;
+  for (int64_t b = T->nbox - 1; b >= 0; --b) T->lvl_first[T->box[b].level] = b;
+  for (int l = ORACLE_LMAX; l >= 0; --l)
+    if (T->lvl_first[l] > T->lvl_first[l + 1]) T->lvl_first[l] = T->lvl_first[l + 1];
+  T->M = calloc((size_t)T->nbox * T->nh, sizeof(cplx));
+  T->Lc = calloc((size_t)T->nbox * T->nh, sizeof(cplx));
+  if (!T->M || !T->Lc) return ORACLE_E_NOMEM;
+  return ORACLE_OK;
+}
+
+/* Closed cubes of boxes a and b touch (any levels). */
+static int aadjacent(const abox *a, const abox *b) {
+  const int f = a->level > b->level ? a->level : b->level;
+  const int sa = f - a->level, sb = f - b->level;
+  for (int k = 0; k < 3; ++k) {
+    const int64_t alo = (int64_t)a->c[k] << sa, ahi = (int64_t)(a->c[k] + 1) << sa;
+    const int64_t blo = (int64_t)b->c[k] << sb, bhi = (int64_t)(b->c[k] + 1) << sb;
+    if (alo > bhi || blo > ahi) return 0;
+  }
+  return 1;
+}
+
+static void abox_centre(const atree *T, const abox *b, double c[3]) {
+  const double h = T->side / (double)((int64_t)1 << b->level);
+  for (int a = 0; a < 3; ++a) c[a] = T->lo[a] + (b->c[a] + 0.5) * h;
+}
+
+/* Box of level l at cell c, or -1 when the tree has no such box. */
+static int64_t abox_find(const atree *T, int l, const int c[3]) {
+  for (int a = 0; a < 3; ++a)
+    if (c[a] < 0 || c[a] >= (1 << l)) return -1;
+  int64_t b = 0;
+  for (int m = 1; m <= l; ++m) {
+    if (T->box[b].child0 < 0) return -1;
+    const int s = l - m;
+    b = T->box[b].child0 + ((((c[0] >> s) & 1) << 2) | (((c[1] >> s) & 1) << 1) | ((c[2] >> s) & 1));
+  }
+  return b;
+}
+
+/* List sink: a growable array of box indices. */
+typedef struct { int64_t *v; int64_t n, cap; int err; } alist;
+static void alist_add(alist *L, int64_t b) {
+  if (L->n == L->cap) {
+    const int64_t nc = L->cap ? 2 * L->cap : 32;
+    int64_t *nv = realloc(L->v, sizeof(int64_t) * nc);
+    if (!nv) { L->err = 1; return; }
+    L->v = nv;
+    L->cap = nc;
+  }
+  L->v[L->n++] = b;
+}
+
+/* U and W of leaf b: descend from the root through boxes adjacent to b; an
+ * adjacent leaf is in U, a non-adjacent box whose parent is adjacent and which
+ * is finer than b is in W. */
+static void collect_uw(const atree *T, int64_t b, int64_t c, alist *U, alist *W) {
+  const abox *B = T->box + b, *C = T->box + c;
+  if (!aadjacent(B, C)) {
+    if (C->level > B->level) alist_add(W, c);
+    return;
+  }
+  if (C->child0 < 0) { alist_add(U, c); return; }
+  for (int ch = 0; ch < 8; ++ch) collect_uw(T, b, C->child0 + ch, U, W);
+}
+
+/* V of box b (level >= 2). */
+static void collect_v(const atree *T, int64_t b, alist *V) {
+  const abox *B = T->box + b, *P = T->box + B->parent;
+  for (int dx = -1; dx <= 1; ++dx)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dz = -1; dz <= 1; ++dz) {
+        if (!dx && !dy && !dz) continue;
+        const int cc[3] = {P->c[0] + dx, P->c[1] + dy, P->c[2] + dz};
+        const int64_t col = abox_find(T, P->level, cc);
+        if (col < 0 || T->box[col].child0 < 0) continue;
+        for (int ch = 0; ch < 8; ++ch)
+          if (!aadjacent(B, T->box + T->box[col].child0 + ch)) alist_add(V, T->box[col].child0 + ch);
+      }
+}
+
+/* X of box b: descend from the root through boxes adjacent to b's parent,
+ * above b's level; a leaf there that is not adjacent to b is in X. */
+static void collect_x(const atree *T, int64_t b, int64_t c, alist *X) {
+  const abox *B = T->box + b, *C = T->box + c;
+  if (C->level >= B->level || !aadjacent(T->box + B->parent, C)) return;
+  if (C->child0 < 0) {
+    if (!aadjacent(B, C)) alist_add(X, c);
+    return;
+  }
+  for (int ch = 0; ch < 8; ++ch) collect_x(T, b, C->child0 + ch, X);
+}
+
+/* P2L: local expansion about c of the charge q at y. */
+static void op_p2l(int p, const double y[3], double q, const double c[3], cplx *L) {
+  cplx Ih[(ORACLE_PMAX + 1) * (ORACLE_PMAX + 1)];
+  irregular_harmonics(y[0] - c[0], y[1] - c[1], y[2] - c[2], p, Ih);
+  for (int i = 0; i < nharm(p); ++i) L[i] += q * conj(Ih[i]);
+}
+
+/* M2P with gradient: local coefficients of degree 0 and 1 about x of the
+ * multipole M about c (A3 with c_t = x), read as value and gradient. */
+static void op_m2p_grad(int p, const cplx *M, const double c[3], const double x[3], double *phi,
+                        double grad[3]) {
+  cplx Ih[(ORACLE_PMAX + 2) * (ORACLE_PMAX + 2)];
+  irregular_harmonics(x[0] - c[0], x[1] - c[1], x[2] - c[2], p + 1, Ih);
+  cplx Lk[4] = {0, 0, 0, 0}; /* (k, l) = (0,0), (1,-1), (1,0), (1,1) */
+  for (int k = 0; k <= 1; ++k)
+    for (int l = -k; l <= k; ++l) {
+      cplx acc = 0.0;
+      for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m) acc += M[hidx(n, m)] * harm_get(Ih, p + 1, n + k, m - l);
+      Lk[hidx(k, l)] = (((k + l) & 1) ? -1.0 : 1.0) * acc;
+    }
+  *phi = creal(Lk[0]);
+  /* gradient of a local expansion at its own centre (A4 at R(0)) */
+  grad[0] = creal(0.5 * (Lk[hidx(1, -1)] - Lk[hidx(1, 1)]));
+  grad[1] = creal(-0.5 * I * (Lk[hidx(1, 1)] + Lk[hidx(1, -1)]));
+  grad[2] = creal(Lk[hidx(1, 0)]);
+}
+
+/* Tree statistics reported by oracle_fmm_adaptive (integer, exact):
+ *   [0] boxes, [1] leaves, [2] deepest level, [3] sum |U| over leaves,
+ *   [4] sum |V|, [5] sum |W| over leaves, [6] sum |X|,
+ *   [7] ordered P2P pairs (sum over leaves b of n_b * sum_{c in U(b)} n_c, minus N),
+ *   [8] M2L pairs between non-empty boxes. */
+#define ORACLE_ASTATS 9
+
+int oracle_fmm_adaptive(int64_t n, const double *pos, const double *q, int leaf_max,
+                        int max_depth, int p, const double lo[3], double side, double *phi,
+                        double *force, double *energy, int64_t *stats) {
+  if (n < 0 || !pos || !q || leaf_max < 1 || max_depth < 0 || max_depth > ORACLE_LMAX || p < 0 ||
+      p > ORACLE_PMAX)
+    return ORACLE_E_INVALID_ARG;
+  atree T;
+  int st = atree_build(&T, n, pos, leaf_max, max_depth, p, lo, side);
+  if (st) { atree_free(&T); return st; }
+  const int nh = T.nh;
+  int deepest = 0;
+  for (int64_t b = 0; b < T.nbox; ++b)
+    if (T.box[b].level > deepest) deepest = T.box[b].level;
+  int64_t s_leaf = 0, s_u = 0, s_v = 0, s_w = 0, s_x = 0, s_p2p = 0, s_m2l = 0;
+  int fail = 0;
+
+  /* P2M at every leaf. */
+#pragma omp parallel for schedule(dynamic, 16)
+  for (int64_t b = 0; b < T.nbox; ++b) {
+    const abox *B = T.box + b;
+    if (B->child0 >= 0) continue;
+    double c[3];
+    abox_centre(&T, B, c);
+    for (int64_t k = B->start; k < B->start + B->count; ++k) {
+      const int64_t j = T.order[k];
+      op_p2m(p, pos + 3 * j, q[j], c, T.M + (size_t)b * nh);
+    }
+  }
+  /* M2M, deepest level first, up to level 2. */
+  for (int l = deepest - 1; l >= 2; --l) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t b = T.lvl_first[l]; b < T.lvl_first[l + 1]; ++b) {
+      const abox *B = T.box + b;
+      if (B->child0 < 0) continue;
+      double cp[3];
+      abox_centre(&T, B, cp);
+      for (int ch = 0; ch < 8; ++ch) {
+        const abox *C = T.box + B->child0 + ch;
+        double cc[3];
+        abox_centre(&T, C, cc);
+        op_m2m(p, T.M + (size_t)(B->child0 + ch) * nh, cc, cp, T.M + (size_t)b * nh);
+      }
+    }
+  }
+  /* Downward: level by level, L2L from the parent, then M2L over V, P2L over X. */
+  for (int l = 2; l <= deepest; ++l) {
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : s_v, s_x, s_m2l) reduction(| : fail)
+    for (int64_t b = T.lvl_first[l]; b < T.lvl_first[l + 1]; ++b) {
+      const abox *B = T.box + b;
+      cplx *Lb = T.Lc + (size_t)b * nh;
+      double ct[3];
+      abox_centre(&T, B, ct);
+      if (l >= 3) {
+        double cp[3];
+        abox_centre(&T, T.box + B->parent, cp);
+        op_l2l(p, T.Lc + (size_t)B->parent * nh, cp, ct, Lb);
+      }
+      alist V = {0}, X = {0};
+      collect_v(&T, b, &V);
+      collect_x(&T, b, 0, &X);
+      fail |= V.err | X.err;
+      for (int64_t k = 0; k < V.n; ++k) {
+        double cs[3];
+        abox_centre(&T, T.box + V.v[k], cs);
+        op_m2l(p, T.M + (size_t)V.v[k] * nh, cs, ct, Lb);
+        if (B->count && T.box[V.v[k]].count) s_m2l++;
+      }
+      for (int64_t k = 0; k < X.n; ++k) {
+        const abox *C = T.box + X.v[k];
+        for (int64_t m = C->start; m < C->start + C->count; ++m) {
+          const int64_t j = T.order[m];
+          op_p2l(p, pos + 3 * j, q[j], ct, Lb);
+        }
+      }
+      s_v += V.n;
+      s_x += X.n;
+      free(V.v);
+      free(X.v);
+    }
+  }
+  /* Leaves: L2P, M2P over W, P2P over U. */
+  double *phi_all = phi ? phi : malloc(sizeof(double) * (n ? n : 1));
+  if (!phi_all) { atree_free(&T); return ORACLE_E_NOMEM; }
+  int status = ORACLE_OK;
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : s_leaf, s_u, s_w, s_p2p) reduction(| : fail)
+  for (int64_t b = 0; b < T.nbox; ++b) {
+    const abox *B = T.box + b;
+    if (B->child0 >= 0) continue;
+    s_leaf++;
+    alist U = {0}, W = {0};
+    collect_uw(&T, b, 0, &U, &W);
+    fail |= U.err | W.err;
+    s_u += U.n;
+    s_w += W.n;
+    int64_t nu = 0;
+    for (int64_t k = 0; k < U.n; ++k) nu += T.box[U.v[k]].count;
+    s_p2p += B->count * nu;
+    double c[3];
+    abox_centre(&T, B, c);
+    for (int64_t k = B->start; k < B->start + B->count; ++k) {
+      const int64_t i = T.order[k];
+      const double *x = pos + 3 * i;
+      double f = 0.0, g[3] = {0.0, 0.0, 0.0};
+      if (B->level >= 2) op_l2p(p, T.Lc + (size_t)b * nh, c, x, &f, g);
+      for (int64_t w = 0; w < W.n; ++w) {
+        double cw[3], fw, gw[3];
+        abox_centre(&T, T.box + W.v[w], cw);
+        op_m2p_grad(p, T.M + (size_t)W.v[w] * nh, cw, x, &fw, gw);
+        f += fw;
+        for (int a = 0; a < 3; ++a) g[a] += gw[a];
+      }
+      ksum fn = {0, 0}, gx = {0, 0}, gy = {0, 0}, gz = {0, 0};
+      for (int64_t u = 0; u < U.n; ++u) {
+        const abox *C = T.box + U.v[u];
+        for (int64_t m = C->start; m < C->start + C->count; ++m) {
+          const int64_t j = T.order[m];
+          if (j == i) continue;
+          const double dx = x[0] - pos[3 * j], dy = x[1] - pos[3 * j + 1], dz = x[2] - pos[3 * j + 2];
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 == 0.0) {
+#pragma omp atomic write
+            status = ORACLE_E_COINCIDENT;
+            continue;
+          }
+          const double r = sqrt(r2), qr = q[j] / r, qr3 = qr / r2;
+          ksum_add(&fn, qr);
+          ksum_add(&gx, -qr3 * dx);
+          ksum_add(&gy, -qr3 * dy);
+          ksum_add(&gz, -qr3 * dz);
+        }
+      }
+      phi_all[i] = f + ksum_val(&fn);
+      if (force) {
+        force[3 * i] = -q[i] * (g[0] + ksum_val(&gx));
+        force[3 * i + 1] = -q[i] * (g[1] + ksum_val(&gy));
+        force[3 * i + 2] = -q[i] * (g[2] + ksum_val(&gz));
+      }
+    }
+    free(U.v);
+    free(W.v);
+  }
+  if (energy) {
+    ksum e = {0, 0};
+    for (int64_t i = 0; i < n; ++i) ksum_add(&e, q[i] * phi_all[i]);
+    *energy = 0.5 * ksum_val(&e);
+  }
+  if (stats) {
+    stats[0] = T.nbox;
+    stats[1] = s_leaf;
+    stats[2] = deepest;
+    stats[3] = s_u;
+    stats[4] = s_v;
+    stats[5] = s_w;
+    stats[6] = s_x;
+    stats[7] = s_p2p - n;
+    stats[8] = s_m2l;
+  }
+  if (!phi) free(phi_all);
+  atree_free(&T);
+  if (fail) return ORACLE_E_NOMEM;
+  return status;
+}
