@@ -92,10 +92,20 @@ typedef enum {
 typedef struct {
   uint32_t abi_version; /* must equal FMM_ABI_VERSION */
   int32_t p;            /* expansion order, 0..FMM_P_MAX */
-  int32_t depth;        /* leaf level L of the uniform tree, 0..FMM_DEPTH_MAX.
-                           L <= 1 has no well-separated pairs: the result is the
-                           direct sum. */
-  int32_t leaf_max;     /* reserved for adaptive trees; must be 0 */
+  int32_t depth;        /* uniform tree (leaf_max == 0): the leaf level L,
+                           0..FMM_DEPTH_MAX; L <= 1 has no well-separated pairs,
+                           so the result is the direct sum.
+                           adaptive tree (leaf_max > 0): the deepest level a box
+                           may be divided down to (depth cap), 0..FMM_DEPTH_MAX */
+  int32_t leaf_max;     /* 0: uniform tree of leaf level depth.
+                           > 0: adaptive tree (Cheng, Greengard & Rokhlin 1999,
+                           sec. 4): a box holding more than leaf_max particles is
+                           divided into its 8 children while its level is below
+                           depth; U, V, W, X lists (P2P, M2L, M2P, P2L).  The
+                           workspace holds list capacities of 40, 16 and 16
+                           entries per possible box for U, W and X; a tree whose
+                           lists exceed them fails fmm_plan with
+                           FMM_E_WORKSPACE.  < 0: FMM_E_INVALID_ARG. */
   int32_t ws;           /* well-separatedness; must be 1 */
   int32_t precision;    /* fmm_precision */
   int32_t m2l_kind;     /* fmm_m2l_kind; must agree with precision or be AUTO
@@ -123,9 +133,11 @@ fmm_status fmm_workspace_size(const fmm_config *cfg, int64_t n, size_t *bytes);
  * box-local coordinates, and the translation operators for order p.
  * d_workspace (device, 256-byte aligned, >= fmm_workspace_size bytes) is owned
  * by the caller and must stay valid and unused by others until fmm_destroy.
- * On FMM_OK *out receives a new plan (host object); work is only enqueued.
- * Errors: FMM_E_INVALID_ARG, FMM_E_WORKSPACE, FMM_E_DEVICE (nothing is
- * enqueued and *out is left unchanged on any error). */
+ * On FMM_OK *out receives a new plan (host object); work is only enqueued,
+ * except for an adaptive tree (leaf_max > 0), whose box and list counts are
+ * read back: the call then synchronises the stream twice.
+ * Errors: FMM_E_INVALID_ARG, FMM_E_WORKSPACE (also: adaptive lists over
+ * capacity), FMM_E_DEVICE (*out is left unchanged on any error). */
 fmm_status fmm_plan(const fmm_config *cfg, int64_t n, const double *d_pos, void *d_workspace,
                     size_t workspace_bytes, fmm_stream_t stream, fmm_plan_t **out);
 
@@ -203,8 +215,20 @@ fmm_status fmm_profile_read(fmm_plan_t *plan, double ms[FMM_PHASE_COUNT],
 
 /* Algorithmic work of the plan's tree (after the stream has finished the
  * plan): number of M2L (target, source) box pairs with both boxes non-empty,
- * summed over levels 2..L, and number of ordered P2P particle pairs (i != j). */
+ * summed over levels 2..L, and number of ordered P2P particle pairs (i != j).
+ * Synchronises the plan's stream. */
 fmm_status fmm_plan_work(fmm_plan_t *plan, int64_t *m2l_pairs, int64_t *p2p_pairs);
+
+/* Integer statistics of an adaptive plan's tree (Cheng, Greengard & Rokhlin
+ * 1999, sec. 4; all 8 children of a divided box counted, empty ones included):
+ *   stats[0] boxes, [1] leaves, [2] deepest level, [3] sum over leaves of |U|
+ *   (the leaf itself included), [4] sum over boxes of |V|, [5] sum of |W|,
+ *   [6] sum of |X|, [7] ordered P2P particle pairs (i != j), [8] M2L (V) pairs
+ *   with both boxes non-empty.
+ * Synchronises the plan's stream.  Errors: FMM_E_INVALID_ARG (NULL),
+ * FMM_E_UNSUPPORTED (uniform plan), FMM_E_DEVICE. */
+#define FMM_TREE_STATS 9
+fmm_status fmm_plan_tree_stats(fmm_plan_t *plan, int64_t stats[FMM_TREE_STATS]);
 
 #ifdef __cplusplus
 }

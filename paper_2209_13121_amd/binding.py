@@ -26,7 +26,7 @@ PHASES = ["tree", "operators", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "energy
 # every symbol include/fmm.h declares
 EXPORTS = ["fmm_config_default", "fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_backward",
            "fmm_check", "fmm_destroy", "fmm_status_string", "fmm_plan_leaves", "fmm_plan_cube",
-           "fmm_hilbert_index", "fmm_profile_enable", "fmm_profile_read", "fmm_plan_work"]
+           "fmm_hilbert_index", "fmm_profile_enable", "fmm_profile_read", "fmm_plan_work", "fmm_plan_tree_stats"]
 
 
 class fmm_config(ctypes.Structure):
@@ -78,13 +78,14 @@ def load(path=LIB_PATH):
     lib.fmm_profile_enable.argtypes = [vp, ctypes.c_int]
     lib.fmm_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32)]
     lib.fmm_plan_work.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+    lib.fmm_plan_tree_stats.argtypes = [vp, ctypes.POINTER(i64)]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int or name in ("fmm_workspace_size", "fmm_plan", "fmm_evaluate",
                                                  "fmm_backward", "fmm_check", "fmm_destroy",
                                                  "fmm_plan_leaves", "fmm_plan_cube",
                                                  "fmm_profile_enable", "fmm_profile_read",
-                                                 "fmm_plan_work"):
+                                                 "fmm_plan_work", "fmm_plan_tree_stats"):
             f.restype = ctypes.c_int
     if path == LIB_PATH:
         _LIB = lib
@@ -97,10 +98,12 @@ def _check(st, what):
 
 
 def make_config(p=8, depth=3, precision=FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
-                m2l_kind=FMM_M2L_AUTO):
+                m2l_kind=FMM_M2L_AUTO, leaf_max=0):
+    """leaf_max > 0 asks for the adaptive tree, depth then being its depth cap."""
     cfg = fmm_config()
     load().fmm_config_default(ctypes.byref(cfg))
     cfg.p, cfg.depth, cfg.precision, cfg.m2l_kind = p, depth, precision, m2l_kind
+    cfg.leaf_max = leaf_max
     for a in range(3):
         cfg.root_lo[a] = float(lo[a])
     cfg.root_side = float(side)
@@ -198,6 +201,16 @@ def fmm_profile_read(plan):
     return {name: (ms[i], cnt[i]) for i, name in enumerate(PHASES)}
 
 
+TREE_STATS = ("boxes", "leaves", "deepest", "u", "v", "w", "x", "p2p_pairs", "m2l_pairs")
+
+
+def fmm_plan_tree_stats(plan):
+    """Integer statistics of an adaptive plan's tree (names in TREE_STATS)."""
+    st = (ctypes.c_int64 * len(TREE_STATS))()
+    _check(load().fmm_plan_tree_stats(plan, st), "fmm_plan_tree_stats")
+    return dict(zip(TREE_STATS, (int(v) for v in st)))
+
+
 def fmm_plan_work(plan):
     a, b = ctypes.c_int64(), ctypes.c_int64()
     _check(load().fmm_plan_work(plan, ctypes.byref(a), ctypes.byref(b)), "fmm_plan_work")
@@ -208,10 +221,10 @@ class FMM:
     """Owns a workspace and a plan for one position set (torch device tensors)."""
 
     def __init__(self, pos, p=8, depth=3, precision=FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
-                 stream=None, workspace=None, m2l_kind=FMM_M2L_AUTO):
+                 stream=None, workspace=None, m2l_kind=FMM_M2L_AUTO, leaf_max=0):
         import torch
         self.n = pos.shape[0]
-        self.cfg = make_config(p, depth, precision, lo, side, m2l_kind)
+        self.cfg = make_config(p, depth, precision, lo, side, m2l_kind, leaf_max)
         nbytes = fmm_workspace_size(self.cfg, self.n)
         if workspace is None or workspace.numel() < nbytes:
             workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=pos.device)

@@ -1,0 +1,744 @@
+// adaptive.hip -- the adaptive octree: which boxes exist, their compact
+// numbering, the U, W and X lists, and the passes only the adaptive tree has
+// (P2M and L2P at leaves of any level, P2L over X, M2P over W).
+//
+// Tree (Cheng, Greengard & Rokhlin, J. Comput. Phys. 155:468 (1999), sec. 4):
+// a box holding more than leaf_max particles is divided into its 8 children
+// while its level is below the depth cap L.  The particles are sorted once by
+// their level-L Hilbert key (tree.hip), so the box of level l with Hilbert slot
+// s holds the sorted range of level-L slots [s 8^(L-l), (s+1) 8^(L-l)), and a
+// box exists when every one of its ancestors holds more than leaf_max.  All 8
+// children of a divided box exist (an empty child is an empty leaf).  The
+// existing boxes are numbered level by level in Hilbert order by an exclusive
+// scan over the dense existence flags, so each level is one contiguous block of
+// the expansion arrays and the children of a divided box are 8 consecutive
+// boxes, in the same order as the uniform tree's slots 8s .. 8s+7.
+//
+// Lists of a box b ("adjacent": the closed cubes touch, any sizes):
+//   U(b), b a leaf: the leaves adjacent to b, b included          -> P2P
+//   V(b): existing same-level boxes at the interaction-list offsets -> M2L
+//         (looked up by the M2L kernels in the dense map)
+//   W(b), b a leaf: boxes finer than b, not adjacent to b, whose parent is
+//         adjacent to b                                            -> M2P
+//   X(b): leaves coarser than b, adjacent to b's parent, not to b  -> P2L
+// Scaling as in the uniform passes: a box's multipole is stored in units of
+// its own size h (M~_n = M_n / h^n) and its local expansion as L~_n = L_n h^n,
+// so with v = (y - c)/h:
+//   P2L  L~_n^m += (1/h) q conj(I_n^m(v))      (added to the M2L result,
+//                                                whose 1/h the L2L applies)
+//   M2P  phi(x)  = (1/h) sum M~_n^m I_n^m(w),  w = (x - c)/h, gradient 1/h^2
+//        from dI_n^m/dz = -I_{n+1}^m, dI_n^m/dx = (I_{n+1}^{m+1} - I_{n+1}^{m-1})/2,
+//        dI_n^m/dy = -i (I_{n+1}^{m+1} + I_{n+1}^{m-1})/2.
+#include <math.h>
+
+#include <algorithm>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+namespace {
+
+struct ATree {
+  int L;         // depth cap
+  int leaf_max;
+  int64_t nbox;  // existing boxes
+  int64_t ls;    // stride of the three lists' count and offset arrays
+  int64_t lvl_off[FMM_DEPTH_MAX + 2];  // dense level offsets
+  int64_t ce_off[FMM_DEPTH_MAX + 2];   // compact level offsets
+  const uint32_t* start;    // level-L slot starts (8^L + 1)
+  const uint32_t* c2s;      // dense: lexicographic cell -> Hilbert slot
+  const uint32_t* s2c;      // dense: Hilbert slot -> packed cell
+  const uint32_t* present;  // dense: the box exists
+  const uint32_t* scan;     // dense: compact index of an existing box
+  const int32_t* level;     // compact
+  const uint32_t* coord;    // compact: packed cell
+  const uint32_t* range;    // compact: {first sorted particle, count}
+  const int32_t* child0;    // compact: first child or -1
+};
+
+__device__ __forceinline__ uint32_t count_of(const uint32_t* start, int L, int l, uint32_t slot) {
+  const int sh = 3 * (L - l);
+  return start[(uint64_t)(slot + 1) << sh] - start[(uint64_t)slot << sh];
+}
+
+// Compact index of the box of level l at cell (x, y, z), or -1.
+__device__ __forceinline__ int64_t find_box(const ATree& t, int l, int x, int y, int z) {
+  const int nb = 1 << l;
+  if (x < 0 || y < 0 || z < 0 || x >= nb || y >= nb || z >= nb) return -1;
+  const int64_t g = t.lvl_off[l] + t.c2s[t.lvl_off[l] + lex_index(x, y, z, l)];
+  return t.present[g] ? (int64_t)t.scan[g] : -1;
+}
+
+// Closed cubes of box a (level la) and box b (level lb >= la) touch.
+__device__ __forceinline__ bool touches(int la, int ax, int ay, int az, int lb, int bx, int by, int bz) {
+  const int s = lb - la;
+  return (ax << s) <= bx + 1 && bx <= ((ax + 1) << s) && (ay << s) <= by + 1 &&
+         by <= ((ay + 1) << s) && (az << s) <= bz + 1 && bz <= ((az + 1) << s);
+}
+
+// ---- tree ------------------------------------------------------------------
+
+__global__ void k_present(ATree t, int64_t nd, uint32_t* __restrict__ present) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nd) return;
+  int l = 0;
+  while (l < t.L && g >= t.lvl_off[l + 1]) ++l;
+  const uint32_t slot = (uint32_t)(g - t.lvl_off[l]);
+  uint32_t ok = 1;
+  for (int m = 0; m < l && ok; ++m)
+    if (count_of(t.start, t.L, m, slot >> (3 * (l - m))) <= (uint32_t)t.leaf_max) ok = 0;
+  present[g] = ok;
+}
+
+__global__ void k_level_offsets(ATree t, uint32_t* __restrict__ out) {
+  const int l = threadIdx.x;
+  if (l <= t.L + 1) out[l] = t.scan[t.lvl_off[l]];
+}
+
+__global__ void k_compact(ATree t, int64_t nd, uint32_t* __restrict__ slot_of,
+                          int32_t* __restrict__ level, uint32_t* __restrict__ coord,
+                          uint32_t* __restrict__ range, int32_t* __restrict__ child0,
+                          uint32_t* __restrict__ parent_of) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= nd || !t.present[g]) return;
+  int l = 0;
+  while (l < t.L && g >= t.lvl_off[l + 1]) ++l;
+  const uint32_t slot = (uint32_t)(g - t.lvl_off[l]);
+  const int64_t c = t.scan[g];
+  const uint32_t cnt = count_of(t.start, t.L, l, slot);
+  slot_of[c] = slot;
+  level[c] = l;
+  coord[c] = t.s2c[g];
+  range[2 * c] = t.start[(uint64_t)slot << (3 * (t.L - l))];
+  range[2 * c + 1] = cnt;
+  const bool divided = cnt > (uint32_t)t.leaf_max && l < t.L;
+  int32_t ch = -1;
+  if (divided) {
+    ch = (int32_t)t.scan[t.lvl_off[l + 1] + 8 * (int64_t)slot];
+    parent_of[ch] = (uint32_t)(c - t.ce_off[l]);
+  }
+  child0[c] = ch;
+}
+
+// Leaf of every sorted particle (the first box on its path that is not
+// divided) and its offset from the leaf centre in units of the leaf size.
+template <typename T>
+__global__ void k_gather_adaptive(ATree t, const double* __restrict__ pos,
+                                  const int32_t* __restrict__ perm, const uint32_t* __restrict__ keys,
+                                  int64_t n, const DevParams* __restrict__ dp,
+                                  uint32_t* __restrict__ sorted_leaf, Rec<T>* __restrict__ src,
+                                  Rec<double>* __restrict__ src64) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int32_t i = perm[s];
+  const uint32_t key = keys[i];
+  int l = 0;
+  uint32_t slot = 0;
+  for (; l <= t.L; ++l) {
+    slot = key >> (3 * (t.L - l));
+    if (l == t.L || count_of(t.start, t.L, l, slot) <= (uint32_t)t.leaf_max) break;
+  }
+  if (l > t.L) l = t.L;
+  const int64_t g = t.lvl_off[l] + slot;
+  sorted_leaf[s] = t.scan[g];
+  int c[3];
+  unpack_coord(t.s2c[g], c[0], c[1], c[2]);
+  const double h = dp->side / (double)(1 << l);
+  double u[3];
+  for (int a = 0; a < 3; ++a) {
+    double x = pos[3 * (int64_t)i + a];
+    if (!isfinite(x)) x = dp->lo[a];
+    u[a] = (x - (dp->lo[a] + ((double)c[a] + 0.5) * h)) / h;
+  }
+  Rec<T> r;
+  r.x = (T)u[0];
+  r.y = (T)u[1];
+  r.z = (T)u[2];
+  r.q = T(0);
+  src[s] = r;
+  if (src64) src64[s] = Rec<double>{u[0], u[1], u[2], 0.0};
+}
+
+// ---- lists -------------------------------------------------------------------
+
+constexpr int kStack = 80;  // depth-first stack: at most 7 per level below the leaf + 8
+
+// FILL = false: counts per box into cnt[list * ls + b];
+// FILL = true: entries at off[...] (the exclusive scan of the counts).
+template <bool FILL>
+__global__ void k_lists(ATree t, uint32_t* __restrict__ cnt, const uint32_t* __restrict__ off,
+                        uint32_t* __restrict__ uidx, uint32_t* __restrict__ widx,
+                        uint32_t* __restrict__ xidx, int32_t* __restrict__ flags) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= t.nbox) return;
+  const int64_t nb1 = t.ls;
+  const int l = t.level[b];
+  int bx, by, bz;
+  unpack_coord(t.coord[b], bx, by, bz);
+  uint32_t nu = 0, nw = 0, nx = 0;
+  uint32_t *pu = nullptr, *pw = nullptr, *px = nullptr;
+  if (FILL) {
+    pu = uidx + off[b];
+    pw = widx + off[nb1 + b];
+    px = xidx + off[2 * nb1 + b];
+  }
+  if (t.child0[b] < 0) {
+    // coarser leaves touching b: at level m the candidates per axis are
+    // (c - 1) >> s .. (c + 1) >> s, s = l - m
+    for (int m = 0; m < l; ++m) {
+      const int s = l - m, top = (1 << m) - 1;
+      const int x0 = max(0, (bx - 1) >> s), x1 = min(top, (bx + 1) >> s);
+      const int y0 = max(0, (by - 1) >> s), y1 = min(top, (by + 1) >> s);
+      const int z0 = max(0, (bz - 1) >> s), z1 = min(top, (bz + 1) >> s);
+      for (int x = x0; x <= x1; ++x)
+        for (int y = y0; y <= y1; ++y)
+          for (int z = z0; z <= z1; ++z) {
+            const int64_t c = find_box(t, m, x, y, z);
+            if (c < 0 || t.child0[c] >= 0 || !touches(m, x, y, z, l, bx, by, bz)) continue;
+            if (FILL) pu[nu] = (uint32_t)c;
+            ++nu;
+          }
+    }
+    // same level, then the finer boxes below divided neighbours
+    for (int dx = -1; dx <= 1; ++dx)
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dz = -1; dz <= 1; ++dz) {
+          const int64_t c = find_box(t, l, bx + dx, by + dy, bz + dz);
+          if (c < 0) continue;
+          if (t.child0[c] < 0) {
+            if (FILL) pu[nu] = (uint32_t)c;
+            ++nu;
+            continue;
+          }
+          int32_t stack[kStack];
+          int sp = 0;
+          stack[sp++] = (int32_t)c;
+          while (sp > 0) {
+            const int32_t d = stack[--sp];
+            for (int k = 0; k < 8; ++k) {
+              const int32_t e = t.child0[d] + k;
+              int ex, ey, ez;
+              unpack_coord(t.coord[e], ex, ey, ez);
+              if (!touches(l, bx, by, bz, t.level[e], ex, ey, ez)) {
+                if (FILL) pw[nw] = (uint32_t)e;
+                ++nw;
+              } else if (t.child0[e] < 0) {
+                if (FILL) pu[nu] = (uint32_t)e;
+                ++nu;
+              } else if (sp < kStack) {
+                stack[sp++] = e;
+              } else {
+                atomicOr(flags, kFlagListOverflow);
+              }
+            }
+          }
+        }
+  }
+  if (l >= 2) {
+    // coarser leaves touching the parent but not b
+    const int px0 = bx >> 1, py0 = by >> 1, pz0 = bz >> 1;
+    for (int m = 0; m < l; ++m) {
+      const int s = l - 1 - m, top = (1 << m) - 1;
+      const int x0 = max(0, (px0 - 1) >> s), x1 = min(top, (px0 + 1) >> s);
+      const int y0 = max(0, (py0 - 1) >> s), y1 = min(top, (py0 + 1) >> s);
+      const int z0 = max(0, (pz0 - 1) >> s), z1 = min(top, (pz0 + 1) >> s);
+      for (int x = x0; x <= x1; ++x)
+        for (int y = y0; y <= y1; ++y)
+          for (int z = z0; z <= z1; ++z) {
+            const int64_t c = find_box(t, m, x, y, z);
+            if (c < 0 || t.child0[c] >= 0 || touches(m, x, y, z, l, bx, by, bz)) continue;
+            if (FILL) px[nx] = (uint32_t)c;
+            ++nx;
+          }
+    }
+  }
+  if (!FILL) {
+    cnt[b] = nu;
+    cnt[nb1 + b] = nw;
+    cnt[2 * nb1 + b] = nx;
+  }
+}
+
+// Tree statistics: [0] leaves, [1] V entries, [2] M2L pairs of non-empty
+// boxes, [3] ordered P2P pairs + n (sum over leaves of n_b * sum_U n_c).
+__global__ void k_stats(ATree t, const uint32_t* __restrict__ off, const uint32_t* __restrict__ uidx,
+                        unsigned long long* __restrict__ st) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= t.nbox) return;
+  const int l = t.level[b];
+  const uint32_t nb_ = t.range[2 * b + 1];
+  int x, y, z;
+  unpack_coord(t.coord[b], x, y, z);
+  if (l >= 2) {
+    unsigned long long v = 0, vn = 0;
+    for (int dx = -3; dx <= 3; ++dx)
+      for (int dy = -3; dy <= 3; ++dy)
+        for (int dz = -3; dz <= 3; ++dz) {
+          if (abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1) continue;
+          const int sx = x + dx, sy = y + dy, sz = z + dz;
+          if (abs((sx >> 1) - (x >> 1)) > 1 || abs((sy >> 1) - (y >> 1)) > 1 ||
+              abs((sz >> 1) - (z >> 1)) > 1)
+            continue;
+          const int64_t c = find_box(t, l, sx, sy, sz);
+          if (c < 0) continue;
+          ++v;
+          if (nb_ && t.range[2 * c + 1]) ++vn;
+        }
+    atomicAdd(&st[1], v);
+    atomicAdd(&st[2], vn);
+  }
+  if (t.child0[b] < 0) {
+    atomicAdd(&st[0], 1ull);
+    unsigned long long src = 0;
+    for (uint32_t k = off[b]; k < off[b + 1]; ++k) src += t.range[2 * uidx[k] + 1];
+    atomicAdd(&st[3], (unsigned long long)nb_ * src);
+  }
+}
+
+__global__ void k_zero_stats(unsigned long long* st) {
+  if (threadIdx.x < 8) st[threadIdx.x] = 0ull;
+}
+
+// ---- harmonics -------------------------------------------------------------
+
+// Irregular solid harmonics I_n^m(x) = (n-m)! P_n^m(cos t) e^{i m f} / r^{n+1}
+// (Condon-Shortley phase; Epton & Dembart, SIAM J. Sci. Comput. 16:865 (1995))
+// for 0 <= m <= n <= Q, by the recurrences
+//   I_0^0 = 1/r,  I_m^m = -(2m-1)(x + i y)/r^2 I_{m-1}^{m-1},
+//   I_{m+1}^m = (2m+1) z/r^2 I_m^m,
+//   r^2 I_n^m = (2n-1) z I_{n-1}^m - (n+m-1)(n-m-1) I_{n-2}^m;
+// outputs indexed by tri(n, m).
+template <int Q, typename T>
+__device__ __forceinline__ void irregular_harmonics(T x, T y, T z, T* re, T* im) {
+  const T r2 = x * x + y * y + z * z;
+  const T ir2 = T(1) / r2;
+  re[0] = T(1) / sqrt(r2);
+  im[0] = T(0);
+#pragma unroll
+  for (int m = 0; m <= Q; ++m) {
+    if (m > 0) {
+      const T s = T(-(2.0 * m - 1.0)) * ir2;
+      const T pr = re[tri(m - 1, m - 1)], pi = im[tri(m - 1, m - 1)];
+      re[tri(m, m)] = s * (x * pr - y * pi);
+      im[tri(m, m)] = s * (x * pi + y * pr);
+    }
+    if (m + 1 <= Q) {
+      const T s = T(2.0 * m + 1.0) * z * ir2;
+      re[tri(m + 1, m)] = s * re[tri(m, m)];
+      im[tri(m + 1, m)] = s * im[tri(m, m)];
+    }
+#pragma unroll
+    for (int n = m + 2; n <= Q; ++n) {
+      const T a = T(2.0 * n - 1.0) * z, b = T((double)(n + m - 1) * (double)(n - m - 1));
+      re[tri(n, m)] = (a * re[tri(n - 1, m)] - b * re[tri(n - 2, m)]) * ir2;
+      im[tri(n, m)] = (a * im[tri(n - 1, m)] - b * im[tri(n - 2, m)]) * ir2;
+    }
+  }
+}
+
+// ---- passes ------------------------------------------------------------------
+
+// P2M at the leaves of levels >= 2, accumulated in FP64 from the FP64
+// offsets (as in the uniform pass); the mixed mode also stores it in FP32.
+template <int P>
+__global__ __launch_bounds__(64) void k_p2m_adaptive(ATree t, const Rec<double>* __restrict__ src,
+                                                     double* __restrict__ mult64, float* __restrict__ mult32) {
+  typedef double T;
+  constexpr int NC = (P + 1) * (P + 1);
+  constexpr int MS = mstride_of(NC);
+  constexpr int NT = (P + 1) * (P + 2) / 2;
+  const int64_t b = t.ce_off[2] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= t.nbox || t.child0[b] >= 0) return;
+  T acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = T(0);
+  const uint32_t s0 = t.range[2 * b], s1 = s0 + t.range[2 * b + 1];
+  for (uint32_t s = s0; s < s1; ++s) {
+    T re[NT], im[NT];
+    const Rec<T> r = src[s];
+    regular_harmonics<P, T>(r.x, r.y, r.z, re, im);
+    const T qq = r.q;
+#pragma unroll
+    for (int nn = 0; nn <= P; ++nn) {
+      acc[cidx_re(nn, 0)] += qq * re[tri(nn, 0)];
+#pragma unroll
+      for (int m = 1; m <= nn; ++m) {
+        acc[cidx_re(nn, m)] += qq * re[tri(nn, m)];
+        acc[cidx_im(nn, m)] -= qq * im[tri(nn, m)];
+      }
+    }
+  }
+  double* out = mult64 + b * MS;
+#pragma unroll
+  for (int c = 0; c < MS; ++c) out[c] = c < NC ? acc[c] : T(0);
+  if (mult32) {
+    float* o32 = mult32 + b * MS;
+#pragma unroll
+    for (int c = 0; c < MS; ++c) o32[c] = c < NC ? (float)acc[c] : 0.f;
+  }
+}
+
+// P2L over X(b), added to the M2L result of b (units before the 1/h of L2L):
+// q conj(I_n^m(v)) with v the source's offset from b's centre in b's units.
+template <int P, typename T>
+__global__ __launch_bounds__(64) void k_p2l(ATree t, const uint32_t* __restrict__ xoff,
+                                            const uint32_t* __restrict__ xidx,
+                                            const Rec<T>* __restrict__ src, T* __restrict__ m2l) {
+  constexpr int NC = (P + 1) * (P + 1);
+  constexpr int NT = (P + 1) * (P + 2) / 2;
+  const int64_t b = t.ce_off[2] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= t.nbox) return;
+  const uint32_t k0 = xoff[b], k1 = xoff[b + 1];
+  if (k0 == k1) return;
+  const int l = t.level[b];
+  int bc[3];
+  unpack_coord(t.coord[b], bc[0], bc[1], bc[2]);
+  T acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = T(0);
+  for (uint32_t k = k0; k < k1; ++k) {
+    const uint32_t c = xidx[k];
+    const int lc = t.level[c];  // < l
+    int cc[3];
+    unpack_coord(t.coord[c], cc[0], cc[1], cc[2]);
+    // centre offset in b's units: ((cc + 1/2) 2^(l - lc) - (bc + 1/2)), exact
+    const double sc = (double)(1 << (l - lc));
+    const T ox = (T)(((double)cc[0] + 0.5) * sc - ((double)bc[0] + 0.5));
+    const T oy = (T)(((double)cc[1] + 0.5) * sc - ((double)bc[1] + 0.5));
+    const T oz = (T)(((double)cc[2] + 0.5) * sc - ((double)bc[2] + 0.5));
+    const T sg = (T)sc;
+    const uint32_t s0 = t.range[2 * c], s1 = s0 + t.range[2 * c + 1];
+    for (uint32_t s = s0; s < s1; ++s) {
+      const Rec<T> r = src[s];
+      T re[NT], im[NT];
+      irregular_harmonics<P, T>(ox + sg * r.x, oy + sg * r.y, oz + sg * r.z, re, im);
+#pragma unroll
+      for (int nn = 0; nn <= P; ++nn) {
+        acc[cidx_re(nn, 0)] += r.q * re[tri(nn, 0)];
+#pragma unroll
+        for (int m = 1; m <= nn; ++m) {
+          acc[cidx_re(nn, m)] += r.q * re[tri(nn, m)];
+          acc[cidx_im(nn, m)] -= r.q * im[tri(nn, m)];
+        }
+      }
+    }
+  }
+  T* o = m2l + b * NC;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) o[c] += acc[c];
+}
+
+// L2P at every particle from its leaf's FP64 local expansion (zero above
+// level 2), then M2P over the leaf's W list.
+template <int P, typename T>
+__global__ __launch_bounds__(kBlock) void k_l2p_m2p(ATree t, const uint32_t* __restrict__ sorted_leaf,
+                                                    const Rec<T>* __restrict__ src, int64_t n,
+                                                    const DevParams* __restrict__ dp,
+                                                    const double* __restrict__ loc64,
+                                                    const double* __restrict__ mult64,
+                                                    const uint32_t* __restrict__ woff,
+                                                    const uint32_t* __restrict__ widx,
+                                                    double* __restrict__ far_phi,
+                                                    double* __restrict__ far_grad) {
+  constexpr int MS = mstride_of((P + 1) * (P + 1));
+  constexpr int NT = (P + 1) * (P + 2) / 2;
+  constexpr int NT1 = (P + 2) * (P + 3) / 2;
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const uint32_t leaf = sorted_leaf[s];
+  const int l = t.level[leaf];
+  const Rec<T> r = src[s];
+  double phi = 0.0, g[3] = {0.0, 0.0, 0.0};
+  if (l >= 2) {
+    const double* Lc = loc64 + (int64_t)leaf * MS;
+    T re[NT], im[NT];
+    regular_harmonics<P, T>(r.x, r.y, r.z, re, im);
+    T f = T(0), gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+    for (int nn = 0; nn <= P; ++nn) {
+      {
+        const T c = (T)Lc[cidx_re(nn, 0)];
+        f += c * re[tri(nn, 0)];
+        if (nn >= 1) {
+          gz += c * re[tri(nn - 1, 0)];
+          if (nn >= 2) {
+            gx += c * re[tri(nn - 1, 1)];
+            gy += c * im[tri(nn - 1, 1)];
+          }
+        }
+      }
+#pragma unroll
+      for (int m = 1; m <= nn; ++m) {
+        const T cr = T(2) * (T)Lc[cidx_re(nn, m)], ci = T(2) * (T)Lc[cidx_im(nn, m)];
+        f += cr * re[tri(nn, m)] - ci * im[tri(nn, m)];
+        const T ar = re[tri(nn - 1, m - 1)], ai = im[tri(nn - 1, m - 1)];
+        T br = T(0), bi = T(0), zr = T(0), zi = T(0);
+        if (m + 1 <= nn - 1) {
+          br = re[tri(nn - 1, m + 1)];
+          bi = im[tri(nn - 1, m + 1)];
+        }
+        if (m <= nn - 1) {
+          zr = re[tri(nn - 1, m)];
+          zi = im[tri(nn - 1, m)];
+        }
+        gx += T(0.5) * (cr * (br - ar) - ci * (bi - ai));
+        gy += T(0.5) * (cr * (ai + bi) + ci * (ar + br));
+        gz += cr * zr - ci * zi;
+      }
+    }
+    const double inv_h = (double)(1 << l) / dp->side;
+    phi = (double)f;
+    g[0] = inv_h * (double)gx;
+    g[1] = inv_h * (double)gy;
+    g[2] = inv_h * (double)gz;
+  }
+  const uint32_t k0 = woff[leaf], k1 = woff[leaf + 1];
+  if (k0 < k1) {
+    int lc[3];
+    unpack_coord(t.coord[leaf], lc[0], lc[1], lc[2]);
+    for (uint32_t k = k0; k < k1; ++k) {
+      const uint32_t w = widx[k];
+      const int lw = t.level[w];  // > l
+      int wc[3];
+      unpack_coord(t.coord[w], wc[0], wc[1], wc[2]);
+      // the particle's offset from w's centre in w's units, from the leaf-unit offset u:
+      // (leaf centre - w centre)/h_w + u h_leaf/h_w, the centre part exact
+      const double sc = (double)(1 << (lw - l));
+      const T vx = (T)(((double)lc[0] + 0.5) * sc - ((double)wc[0] + 0.5)) + (T)sc * r.x;
+      const T vy = (T)(((double)lc[1] + 0.5) * sc - ((double)wc[1] + 0.5)) + (T)sc * r.y;
+      const T vz = (T)(((double)lc[2] + 0.5) * sc - ((double)wc[2] + 0.5)) + (T)sc * r.z;
+      T re[NT1], im[NT1];
+      irregular_harmonics<P + 1, T>(vx, vy, vz, re, im);
+      const double* Mw = mult64 + (int64_t)w * MS;
+      T f = T(0), gx = T(0), gy = T(0), gz = T(0);
+      // I_{n+1}^{m-1} at m = 0 is I_{n+1}^{-1} = -conj(I_{n+1}^1)
+      auto ir = [&](int nn, int m) { return m >= 0 ? re[tri(nn, m)] : -re[tri(nn, 1)]; };
+      auto ii = [&](int nn, int m) { return m >= 0 ? im[tri(nn, m)] : im[tri(nn, 1)]; };
+#pragma unroll
+      for (int nn = 0; nn <= P; ++nn) {
+#pragma unroll
+        for (int m = 0; m <= nn; ++m) {
+          const T mr = (T)Mw[cidx_re(nn, m)];
+          const T mi = m ? (T)Mw[cidx_im(nn, m)] : T(0);
+          const T wgt = m ? T(2) : T(1);  // the negative orders are the conjugates
+          // Re(M I_n^m)
+          f += wgt * (mr * re[tri(nn, m)] - mi * im[tri(nn, m)]);
+          // d/dx: M (I_{n+1}^{m+1} - I_{n+1}^{m-1}) / 2
+          const T dxr = T(0.5) * (re[tri(nn + 1, m + 1)] - ir(nn + 1, m - 1));
+          const T dxi = T(0.5) * (im[tri(nn + 1, m + 1)] - ii(nn + 1, m - 1));
+          gx += wgt * (mr * dxr - mi * dxi);
+          // d/dy: M (-i/2)(I_{n+1}^{m+1} + I_{n+1}^{m-1}); (-i/2)(a + i b) = b/2 - i a/2
+          const T sr = re[tri(nn + 1, m + 1)] + ir(nn + 1, m - 1);
+          const T si = im[tri(nn + 1, m + 1)] + ii(nn + 1, m - 1);
+          gy += wgt * (mr * (T(0.5) * si) - mi * (T(-0.5) * sr));
+          // d/dz: -M I_{n+1}^m
+          gz -= wgt * (mr * re[tri(nn + 1, m)] - mi * im[tri(nn + 1, m)]);
+        }
+      }
+      const double inv_hw = (double)(1 << lw) / dp->side;
+      phi += inv_hw * (double)f;
+      g[0] += inv_hw * inv_hw * (double)gx;
+      g[1] += inv_hw * inv_hw * (double)gy;
+      g[2] += inv_hw * inv_hw * (double)gz;
+    }
+  }
+  far_phi[s] = phi;
+  far_grad[s] = g[0];
+  far_grad[n + s] = g[1];
+  far_grad[2 * n + s] = g[2];
+}
+
+ATree tree_view(fmm_plan_s* P) {
+  const Layout& lay = P->lay;
+  ATree t;
+  t.L = P->L;
+  t.leaf_max = P->cfg.leaf_max;
+  t.nbox = P->ce_off[P->L + 1];
+  t.ls = lay.bmax + 1;
+  for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) {
+    t.lvl_off[l] = lay.lvl_off[l];
+    t.ce_off[l] = P->ce_off[l];
+  }
+  t.start = wsp<uint32_t>(P, lay.leaf_start);
+  t.c2s = wsp<uint32_t>(P, lay.coord2slot);
+  t.s2c = wsp<uint32_t>(P, lay.slot2coord);
+  t.present = wsp<uint32_t>(P, lay.a_present);
+  t.scan = wsp<uint32_t>(P, lay.a_scan);
+  t.level = wsp<int32_t>(P, lay.a_level);
+  t.coord = wsp<uint32_t>(P, lay.a_coord);
+  t.range = wsp<uint32_t>(P, lay.a_range);
+  t.child0 = wsp<int32_t>(P, lay.a_child0);
+  return t;
+}
+
+template <int P>
+struct P2MAdaptiveRun {
+  static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
+    const Layout& lay = Pl->lay;
+    const ATree t = tree_view(Pl);
+    const int64_t nb = t.nbox - t.ce_off[2];
+    if (nb <= 0) return hipGetLastError();
+    k_p2m_adaptive<P><<<grid_for(nb, 64), 64, 0, s>>>(
+        t, wsp<Rec<double>>(Pl, Pl->mixed ? lay.src64 : lay.src), wsp<double>(Pl, lay.mult64),
+        Pl->mixed ? wsp<float>(Pl, lay.mult32) : nullptr);
+    return hipGetLastError();
+  }
+};
+
+template <int P>
+struct P2LRun {
+  static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
+    const Layout& lay = Pl->lay;
+    const ATree t = tree_view(Pl);
+    const int64_t nb = t.nbox - t.ce_off[2];
+    const uint32_t* xoff = wsp<uint32_t>(Pl, lay.a_off) + 2 * (lay.bmax + 1);
+    if (nb <= 0 || Pl->nlist[2] == 0) return hipGetLastError();
+    if (Pl->mixed)
+      k_p2l<P, float><<<grid_for(nb, 64), 64, 0, s>>>(t, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
+                                                      wsp<Rec<float>>(Pl, lay.src),
+                                                      wsp<float>(Pl, lay.m2l_out));
+    else
+      k_p2l<P, double><<<grid_for(nb, 64), 64, 0, s>>>(t, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
+                                                       wsp<Rec<double>>(Pl, lay.src),
+                                                       wsp<double>(Pl, lay.m2l_out));
+    return hipGetLastError();
+  }
+};
+
+template <int P>
+struct L2PM2PRun {
+  static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
+    const Layout& lay = Pl->lay;
+    const ATree t = tree_view(Pl);
+    const uint32_t* woff = wsp<uint32_t>(Pl, lay.a_off) + (lay.bmax + 1);
+    const int64_t n = Pl->n;
+    const DevParams* dp = wsp<DevParams>(Pl, lay.params);
+    if (Pl->mixed)
+      k_l2p_m2p<P, float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
+          t, wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<float>>(Pl, lay.src), n, dp,
+          wsp<double>(Pl, lay.loc_exp64), wsp<double>(Pl, lay.mult64), woff,
+          wsp<uint32_t>(Pl, lay.a_widx), wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
+    else
+      k_l2p_m2p<P, double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
+          t, wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<double>>(Pl, lay.src), n, dp,
+          wsp<double>(Pl, lay.loc_exp64), wsp<double>(Pl, lay.mult64), woff,
+          wsp<uint32_t>(Pl, lay.a_widx), wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
+    return hipGetLastError();
+  }
+};
+
+}  // namespace
+
+hipError_t launch_adaptive_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
+  const Layout& lay = P->lay;
+  const int64_t nd = lay.nbox;
+  uint32_t* present = wsp<uint32_t>(P, lay.a_present);
+  uint32_t* scan = wsp<uint32_t>(P, lay.a_scan);
+  uint32_t* small = wsp<uint32_t>(P, lay.a_small);
+  uint32_t* tmp = wsp<uint32_t>(P, lay.scan_tmp);
+  prof_begin(P, FMM_PHASE_TREE, s);
+  for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) P->ce_off[l] = 0;
+  ATree t = tree_view(P);
+  k_present<<<grid_for(nd, kBlock), kBlock, 0, s>>>(t, nd, present);
+  hipError_t e = scan_exclusive(present, nd, nd + 1, scan, tmp, s);
+  if (e != hipSuccess) return e;
+  k_level_offsets<<<1, 64, 0, s>>>(t, small);
+  uint32_t h[FMM_DEPTH_MAX + 2];
+  e = hipMemcpyAsync(h, small, sizeof(uint32_t) * (P->L + 2), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  for (int l = 0; l <= P->L + 1; ++l) P->ce_off[l] = h[l];
+  for (int l = P->L + 2; l <= FMM_DEPTH_MAX + 1; ++l) P->ce_off[l] = h[P->L + 1];
+  P->Ld = 0;
+  for (int l = 0; l <= P->L; ++l)
+    if (P->ce_off[l + 1] > P->ce_off[l]) P->Ld = l;
+  for (int l = 0; l <= FMM_DEPTH_MAX; ++l)
+    P->nsplit[l] = l < P->L ? (P->ce_off[l + 2] - P->ce_off[l + 1]) / 8 : 0;
+  const int64_t nbox = P->ce_off[P->L + 1];
+  if (nbox > lay.bmax) return hipErrorInvalidValue;  // cannot happen: bmax bounds the tree
+  t = tree_view(P);
+  k_compact<<<grid_for(nd, kBlock), kBlock, 0, s>>>(
+      t, nd, wsp<uint32_t>(P, lay.a_slot), wsp<int32_t>(P, lay.a_level), wsp<uint32_t>(P, lay.a_coord),
+      wsp<uint32_t>(P, lay.a_range), wsp<int32_t>(P, lay.a_child0), wsp<uint32_t>(P, lay.a_parent_of));
+  const DevParams* dp = wsp<DevParams>(P, lay.params);
+  if (P->mixed)
+    k_gather_adaptive<float><<<grid_for(P->n, kBlock), kBlock, 0, s>>>(
+        t, d_pos, wsp<int32_t>(P, lay.perm), wsp<uint32_t>(P, lay.keys), P->n, dp,
+        wsp<uint32_t>(P, lay.sorted_leaf), wsp<Rec<float>>(P, lay.src), wsp<Rec<double>>(P, lay.src64));
+  else
+    k_gather_adaptive<double><<<grid_for(P->n, kBlock), kBlock, 0, s>>>(
+        t, d_pos, wsp<int32_t>(P, lay.perm), wsp<uint32_t>(P, lay.keys), P->n, dp,
+        wsp<uint32_t>(P, lay.sorted_leaf), wsp<Rec<double>>(P, lay.src), nullptr);
+  // lists: count, scan each list over nbox + 1 entries, read the totals, fill
+  uint32_t* cnt = wsp<uint32_t>(P, lay.a_cnt);
+  uint32_t* off = wsp<uint32_t>(P, lay.a_off);
+  const int64_t nb1 = lay.bmax + 1;
+  int32_t* flags = wsp<int32_t>(P, lay.flags);
+  k_lists<false><<<grid_for(nbox, kBlock), kBlock, 0, s>>>(t, cnt, off, nullptr, nullptr, nullptr,
+                                                          flags);
+  for (int k = 0; k < 3; ++k) {
+    e = scan_exclusive(cnt + k * nb1, nbox, nbox + 1, off + k * nb1, tmp, s);
+    if (e != hipSuccess) return e;
+  }
+  uint32_t tot[3];
+  for (int k = 0; k < 3; ++k) {
+    e = hipMemcpyAsync(&tot[k], off + k * nb1 + nbox, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+  }
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  for (int k = 0; k < 3; ++k) P->nlist[k] = tot[k];
+  if (P->nlist[0] > lay.ucap || P->nlist[1] > lay.wcap || P->nlist[2] > lay.xcap) {
+    prof_end(P, s);
+    return hipSuccess;  // the caller reports FMM_E_WORKSPACE
+  }
+  k_lists<true><<<grid_for(nbox, kBlock), kBlock, 0, s>>>(
+      t, cnt, off, wsp<uint32_t>(P, lay.a_uidx), wsp<uint32_t>(P, lay.a_widx),
+      wsp<uint32_t>(P, lay.a_xidx), flags);
+  prof_end(P, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_adaptive_upward(fmm_plan_s* P, hipStream_t s) {
+  if (P->Ld < 2) return hipGetLastError();
+  prof_begin(P, FMM_PHASE_P2M, s);
+  hipError_t e = dispatch_p<P2MAdaptiveRun>(P->p, P, s);
+  prof_end(P, s);
+  if (e != hipSuccess) return e;
+  prof_begin(P, FMM_PHASE_M2M, s);
+  e = launch_m2m_adaptive(P, s);
+  prof_end(P, s);
+  return e;
+}
+
+hipError_t launch_adaptive_p2l(fmm_plan_s* P, hipStream_t s) {
+  if (P->Ld < 2) return hipGetLastError();
+  return dispatch_p<P2LRun>(P->p, P, s);
+}
+
+hipError_t launch_adaptive_downward(fmm_plan_s* P, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if (P->Ld >= 2) {
+    prof_begin(P, FMM_PHASE_L2L, s);
+    e = launch_l2l_adaptive(P, s);
+    prof_end(P, s);
+    if (e != hipSuccess) return e;
+  }
+  prof_begin(P, FMM_PHASE_L2P, s);
+  e = dispatch_p<L2PM2PRun>(P->p, P, s);
+  prof_end(P, s);
+  return e;
+}
+
+hipError_t launch_adaptive_stats(fmm_plan_s* P, hipStream_t s) {
+  const Layout& lay = P->lay;
+  const ATree t = tree_view(P);
+  unsigned long long* st = wsp<unsigned long long>(P, lay.a_stats);
+  k_zero_stats<<<1, 64, 0, s>>>(st);
+  if (t.nbox > 0)
+    k_stats<<<grid_for(t.nbox, kBlock), kBlock, 0, s>>>(t, wsp<uint32_t>(P, lay.a_off),
+                                                        wsp<uint32_t>(P, lay.a_uidx), st);
+  return hipGetLastError();
+}
+
+}  // namespace fmm

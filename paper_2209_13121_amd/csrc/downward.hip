@@ -95,6 +95,7 @@ struct L2PRun {
 }  // namespace
 
 hipError_t launch_downward(fmm_plan_s* P, hipStream_t s) {
+  if (P->adaptive) return launch_adaptive_downward(P, s);
   prof_begin(P, FMM_PHASE_L2L, s);
   hipError_t e = launch_l2l(P, s);
   prof_end(P, s);

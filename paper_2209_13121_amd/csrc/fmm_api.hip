@@ -3,6 +3,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 
 #include "fmm_internal.h"
@@ -39,8 +40,25 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   lay->lvl_off[L + 1] = off;
   lay->nbox = off;
   lay->n_energy_part = (n + kBlock - 1) / kBlock;
-  // scan scratch: block sums of every level of the recursive scan
-  int64_t tmp = 0, m = lay->nleaf + 1;
+  const bool adaptive = cfg.leaf_max > 0;
+  if (adaptive) {
+    // Every existing box but the root is one of 8 children of a divided box;
+    // a divided box holds more than leaf_max particles, so a level has at
+    // most min(8^l, n / (leaf_max + 1)) of them.
+    int64_t div = 0;
+    for (int l = 0; l < L; ++l)
+      div += std::min<int64_t>((int64_t)1 << (3 * l), n / ((int64_t)cfg.leaf_max + 1));
+    lay->bmax = 1 + 8 * div;
+    lay->ucap = 40 * lay->bmax;
+    lay->wcap = 16 * lay->bmax;
+    lay->xcap = 16 * lay->bmax;
+  }
+  lay->nbox_exp = adaptive ? lay->bmax : lay->nbox;
+  // scan scratch: block sums of every level of the recursive scan, for the
+  // longest scan (leaf counts; adaptive: also the dense box flags and lists)
+  int64_t longest = lay->nleaf + 1;
+  if (adaptive) longest = std::max(longest, std::max(lay->nbox + 1, lay->bmax + 1));
+  int64_t tmp = 0, m = longest;
   while (m > 1) {
     m = (m + 1023) / 1024;
     tmp += m;
@@ -53,7 +71,8 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     cur = align256(cur + (bytes ? bytes : 1));
     return at;
   };
-  const size_t N = (size_t)n, NB = (size_t)lay->nbox, NL = (size_t)lay->nleaf;
+  const size_t N = (size_t)n, NB = (size_t)lay->nbox_exp, NL = (size_t)lay->nleaf;
+  const size_t ND = (size_t)lay->nbox;  // dense boxes of every level
   lay->params = take(sizeof(DevParams));
   lay->flags = take(sizeof(int32_t) * 4);
   lay->energy_part = take(sizeof(double) * (size_t)lay->n_energy_part);
@@ -68,9 +87,10 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   lay->leaf_start = take(sizeof(uint32_t) * (NL + 1));
   lay->leaf_fill = take(sizeof(uint32_t) * NL);
   lay->scan_tmp = take(sizeof(uint32_t) * (size_t)lay->scan_tmp_elems);
-  lay->coord2slot = take(sizeof(uint32_t) * NB);
-  lay->slot2coord = take(sizeof(uint32_t) * NB);
+  lay->coord2slot = take(sizeof(uint32_t) * ND);
+  lay->slot2coord = take(sizeof(uint32_t) * ND);
   lay->src = take((mixed ? sizeof(Rec<float>) : sizeof(Rec<double>)) * N);
+  lay->src64 = mixed ? take(sizeof(Rec<double>) * N) : 0;
   lay->q64 = take(sizeof(double) * N);
   lay->far_phi = take(sizeof(double) * N);
   lay->far_grad = take(sizeof(double) * 3 * N);
@@ -81,7 +101,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     lay->mult32 = mixed ? take(sizeof(float) * NB * ms) : 0;
     lay->m2l_out = take((mixed ? sizeof(float) : sizeof(double)) * NB * nce);
     lay->loc_exp64 = take(sizeof(double) * NB * ms);
-    lay->leaf_loc32 = mixed ? take(sizeof(float) * NL * ms) : 0;
+    lay->leaf_loc32 = (mixed && !adaptive) ? take(sizeof(float) * NL * ms) : 0;
     const size_t tile = (size_t)shift_kpad(nc) * m2l_rows_pad(p);
     lay->op_m2m = take(sizeof(double) * 8 * tile);
     lay->op_l2l = take(sizeof(double) * 8 * tile);
@@ -104,6 +124,24 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     }
   }
   lay->work = take(sizeof(int64_t) * 2);
+  if (adaptive) {
+    const size_t BM = (size_t)lay->bmax;
+    lay->a_present = take(sizeof(uint32_t) * (ND + 1));
+    lay->a_scan = take(sizeof(uint32_t) * (ND + 1));
+    lay->a_slot = take(sizeof(uint32_t) * BM);
+    lay->a_level = take(sizeof(int32_t) * BM);
+    lay->a_coord = take(sizeof(uint32_t) * BM);
+    lay->a_range = take(sizeof(uint32_t) * 2 * BM);
+    lay->a_child0 = take(sizeof(int32_t) * BM);
+    lay->a_parent_of = take(sizeof(uint32_t) * BM);
+    lay->a_cnt = take(sizeof(uint32_t) * 3 * (BM + 1));
+    lay->a_off = take(sizeof(uint32_t) * 3 * (BM + 1));
+    lay->a_uidx = take(sizeof(uint32_t) * (size_t)lay->ucap);
+    lay->a_widx = take(sizeof(uint32_t) * (size_t)lay->wcap);
+    lay->a_xidx = take(sizeof(uint32_t) * (size_t)lay->xcap);
+    lay->a_small = take(sizeof(uint32_t) * 64);
+    lay->a_stats = take(sizeof(int64_t) * 8);
+  }
   lay->total = cur;
   return true;
 }
@@ -130,13 +168,29 @@ void prof_end(fmm_plan_s* P, hipStream_t s) {
   P->nrec++;
 }
 
+// Every pass before the near field: upward, M2L (+ P2L on the adaptive tree),
+// downward.
+static hipError_t run_passes(fmm_plan_s* P, const double* d_q, hipStream_t s) {
+  hipError_t e = launch_upward(P, d_q, s);
+  if (P->Ld >= 2) {
+    if (e == hipSuccess) e = launch_m2l(P, s);
+    if (e == hipSuccess && P->adaptive) {
+      prof_begin(P, FMM_PHASE_L2L, s);  // P2L builds local expansions: timed with L2L
+      e = launch_adaptive_p2l(P, s);
+      prof_end(P, s);
+    }
+  }
+  if (e == hipSuccess && (P->Ld >= 2 || P->adaptive)) e = launch_downward(P, s);
+  return e;
+}
+
 static fmm_status validate_config(const fmm_config* cfg) {
   if (!cfg) return FMM_E_INVALID_ARG;
   if (cfg->abi_version != FMM_ABI_VERSION) return FMM_E_INVALID_ARG;
   if (cfg->p < 0 || cfg->p > FMM_P_MAX) return FMM_E_INVALID_ARG;
   if (cfg->depth < 0 || cfg->depth > FMM_DEPTH_MAX) return FMM_E_INVALID_ARG;
   if (cfg->ws != 1) return FMM_E_INVALID_ARG;
-  if (cfg->leaf_max != 0) return FMM_E_UNSUPPORTED;
+  if (cfg->leaf_max < 0) return FMM_E_INVALID_ARG;
   if (cfg->precision != FMM_PREC_FP64 && cfg->precision != FMM_PREC_MIXED) return FMM_E_INVALID_ARG;
   if (cfg->m2l_kind < FMM_M2L_AUTO || cfg->m2l_kind > FMM_M2L_F16X2) return FMM_E_INVALID_ARG;
   if (cfg->m2l_kind == FMM_M2L_F64 && cfg->precision != FMM_PREC_FP64) return FMM_E_UNSUPPORTED;
@@ -200,6 +254,8 @@ fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void*
   P->mixed = cfg->precision == FMM_PREC_MIXED;
   P->m2l_np = m2l_pieces(*cfg);
   P->m2l_f16 = m2l_is_f16(*cfg);
+  P->adaptive = cfg->leaf_max > 0;
+  P->Ld = P->L;
   P->ws = static_cast<char*>(d_workspace);
   P->last_stream = reinterpret_cast<hipStream_t>(stream);
   P->rec = static_cast<ProfileRec*>(calloc(kMaxProfile, sizeof(ProfileRec)));
@@ -209,11 +265,16 @@ fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void*
   }
   hipStream_t s = P->last_stream;
   hipError_t e = launch_tree(P, d_pos, s);
-  if (e == hipSuccess && P->L >= 2) e = launch_operators(P, s);
-  if (e != hipSuccess) {
+  if (e == hipSuccess && P->adaptive) e = launch_adaptive_tree(P, d_pos, s);
+  fmm_status st2 = FMM_OK;
+  if (e == hipSuccess && P->adaptive &&
+      (P->nlist[0] > lay.ucap || P->nlist[1] > lay.wcap || P->nlist[2] > lay.xcap))
+    st2 = FMM_E_WORKSPACE;  // the tree's lists do not fit the workspace's list capacity
+  if (e == hipSuccess && st2 == FMM_OK && P->Ld >= 2) e = launch_operators(P, s);
+  if (e != hipSuccess || st2 != FMM_OK) {
     free(P->rec);
     delete P;
-    return FMM_E_DEVICE;
+    return e != hipSuccess ? FMM_E_DEVICE : st2;
   }
   *out = P;
   return FMM_OK;
@@ -224,9 +285,7 @@ fmm_status fmm_evaluate(fmm_plan_t* P, const double* d_q, double* d_phi, double*
   if (!P || !d_q) return FMM_E_INVALID_ARG;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   P->last_stream = s;
-  hipError_t e = launch_upward(P, d_q, s);
-  if (e == hipSuccess && P->L >= 2) e = launch_m2l(P, s);
-  if (e == hipSuccess && P->L >= 2) e = launch_downward(P, s);
+  hipError_t e = run_passes(P, d_q, s);
   if (e == hipSuccess)
     e = launch_near_and_finish(P, d_phi, d_force, d_energy, nullptr, nullptr, nullptr, s);
   if (e == hipSuccess) P->has_charges = true;
@@ -242,9 +301,7 @@ fmm_status fmm_backward(fmm_plan_t* P, const double* d_grad_energy, double* d_dE
   P->last_stream = s;
   // Recompute every pass from the stored sorted charges (no expansion of the
   // forward call is reused), then write the scaled gradients.
-  hipError_t e = launch_upward(P, nullptr, s);
-  if (e == hipSuccess && P->L >= 2) e = launch_m2l(P, s);
-  if (e == hipSuccess && P->L >= 2) e = launch_downward(P, s);
+  hipError_t e = run_passes(P, nullptr, s);
   if (e == hipSuccess)
     e = launch_near_and_finish(P, nullptr, nullptr, nullptr, d_grad_energy, d_dE_dq, d_dE_dx, s);
   return from_hip(e);
@@ -259,6 +316,7 @@ fmm_status fmm_check(fmm_plan_t* P) {
   if (flags & kFlagNonFinite) return FMM_E_NONFINITE;
   if (flags & kFlagOutOfCube) return FMM_E_OUT_OF_CUBE;
   if (flags & kFlagCoincident) return FMM_E_COINCIDENT;
+  if (flags & kFlagListOverflow) return FMM_E_WORKSPACE;
   return FMM_OK;
 }
 
@@ -346,8 +404,37 @@ fmm_status fmm_profile_read(fmm_plan_t* P, double ms[FMM_PHASE_COUNT],
   return st;
 }
 
+fmm_status fmm_plan_tree_stats(fmm_plan_t* P, int64_t stats[FMM_TREE_STATS]) {
+  if (!P || !stats) return FMM_E_INVALID_ARG;
+  if (!P->adaptive) return FMM_E_UNSUPPORTED;
+  hipStream_t s = P->last_stream;
+  if (launch_adaptive_stats(P, s) != hipSuccess) return FMM_E_DEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return FMM_E_DEVICE;
+  int64_t w[4];
+  if (hipMemcpy(w, P->ws + P->lay.a_stats, sizeof(w), hipMemcpyDeviceToHost) != hipSuccess)
+    return FMM_E_DEVICE;
+  stats[0] = P->ce_off[P->L + 1];  // boxes
+  stats[1] = w[0];                 // leaves
+  stats[2] = P->Ld;                // deepest level
+  stats[3] = P->nlist[0];          // U entries
+  stats[4] = w[1];                 // V entries
+  stats[5] = P->nlist[1];          // W entries
+  stats[6] = P->nlist[2];          // X entries
+  stats[7] = w[3] - P->n;          // ordered P2P pairs
+  stats[8] = w[2];                 // M2L pairs of non-empty boxes
+  return FMM_OK;
+}
+
 fmm_status fmm_plan_work(fmm_plan_t* P, int64_t* m2l_pairs, int64_t* p2p_pairs) {
   if (!P || !m2l_pairs || !p2p_pairs) return FMM_E_INVALID_ARG;
+  if (P->adaptive) {
+    int64_t st[FMM_TREE_STATS];
+    fmm_status r = fmm_plan_tree_stats(P, st);
+    if (r != FMM_OK) return r;
+    *m2l_pairs = st[8];
+    *p2p_pairs = st[7];
+    return FMM_OK;
+  }
   hipStream_t s = P->last_stream;
   if (launch_work_count(P, s) != hipSuccess) return FMM_E_DEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return FMM_E_DEVICE;

@@ -15,7 +15,7 @@ constexpr int kIL = 189;             // interaction-list offsets per parity clas
 constexpr int kMaxProfile = 8192;    // recorded launches between profile reads
 
 // Error bits raised by kernels (atomicOr into Plan::d_flags).
-enum : int32_t { kFlagOutOfCube = 1, kFlagNonFinite = 2, kFlagCoincident = 4 };
+enum : int32_t { kFlagOutOfCube = 1, kFlagNonFinite = 2, kFlagCoincident = 4, kFlagListOverflow = 8 };
 
 // Device-resident parameters of a plan (written by kernels, so that a derived
 // cube never needs a host round trip).
@@ -87,6 +87,7 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t leaf_count, leaf_start, leaf_fill, scan_tmp;
   size_t coord2slot, slot2coord;
   size_t src;              // particle records {u_x, u_y, u_z, q} in the compute precision
+  size_t src64;            // mixed: the same records in FP64 (P2P pair offsets)
   size_t q64;              // sorted charges (FP64)
   size_t far_phi, far_grad;  // far-field results per sorted particle (FP64)
   size_t mult64, mult32;   // multipole expansions, all levels (row stride mstride)
@@ -103,6 +104,21 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t f16_tbl;          // FP16 M2L: per (row, k), max |entry| over the operators (float bits)
   size_t op_m2l_scratch;   // FP16 M2L: FP64 operator entries [op][row][k] at plan time
   size_t work;             // 2 x int64 counters
+  // Adaptive tree (leaf_max > 0).  Dense over every box of levels 0..L:
+  size_t a_present;        // 1 where the box exists (all its ancestors were divided)
+  size_t a_scan;           // exclusive scan of a_present: the box's compact index
+  // Compact, one entry per existing box, level by level in Hilbert order:
+  size_t a_slot;           // Hilbert slot within the level
+  size_t a_level;          // level
+  size_t a_coord;          // packed cell coordinates
+  size_t a_range;          // {first sorted particle, count}
+  size_t a_child0;         // compact index of the first of the 8 children, or -1 (leaf)
+  size_t a_parent_of;      // at child0: the parent's index within its level
+  size_t a_cnt, a_off;     // list sizes and offsets: 3 lists (U, W, X) x (bmax + 1)
+  size_t a_uidx, a_widx, a_xidx;  // list entries (compact box indices)
+  size_t a_small;          // per-level offsets and totals read back by the host
+  size_t a_stats;          // 8 x int64 counters of the tree statistics
+  int64_t bmax, ucap, wcap, xcap, nbox_exp;  // bounds; nbox_exp = rows of the expansion arrays
   size_t total;
   int64_t n, nleaf, nbox, n_energy_part, scan_tmp_elems;
   int64_t lvl_off[FMM_DEPTH_MAX + 2];
@@ -128,6 +144,12 @@ struct fmm_plan_s {
   bool mixed;
   int m2l_np;    // m2l_pieces(cfg)
   bool m2l_f16;  // m2l_is_f16(cfg): the pieces are scaled FP16
+  // Adaptive tree: L is the depth cap, Ld the deepest level that exists.
+  bool adaptive;
+  int Ld;
+  int64_t ce_off[FMM_DEPTH_MAX + 2];  // compact index of the first box of each level
+  int64_t nsplit[FMM_DEPTH_MAX + 1];  // divided boxes per level
+  int64_t nlist[3];                   // U, W, X entries
   char* ws;
   hipStream_t last_stream;
   bool has_charges;  // fmm_evaluate has run: sorted charges are in the workspace
@@ -165,6 +187,22 @@ hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
                                   double* dEdx, hipStream_t s);
 hipError_t launch_leaves_out(fmm_plan_s* P, int32_t* d_cells, uint32_t* d_leaf, hipStream_t s);
 hipError_t launch_work_count(fmm_plan_s* P, hipStream_t s);
+hipError_t scan_exclusive(const uint32_t* in, int64_t n_valid, int64_t n, uint32_t* out,
+                          uint32_t* tmp, hipStream_t s);
+// adaptive tree (adaptive.hip)
+hipError_t launch_adaptive_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s);  // synchronises s
+hipError_t launch_adaptive_upward(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_adaptive_p2l(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_adaptive_downward(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_adaptive_stats(fmm_plan_s* P, hipStream_t s);
+// M2M / L2L over the divided boxes of the adaptive tree (shift.hip)
+hipError_t launch_m2m_adaptive(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_l2l_adaptive(fmm_plan_s* P, hipStream_t s);
+// First box and number of boxes (levels 2..) of the expansion arrays.
+inline int64_t exp_box0(const fmm_plan_s* P) { return P->adaptive ? P->ce_off[2] : P->lay.lvl_off[2]; }
+inline int64_t exp_nbox(const fmm_plan_s* P) {
+  return P->adaptive ? P->ce_off[P->Ld + 1] : P->lay.nbox;
+}
 
 // ---- device helpers --------------------------------------------------------
 

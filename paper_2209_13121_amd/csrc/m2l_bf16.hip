@@ -370,7 +370,7 @@ struct M2LBfRun {
     const Layout& lay = Pl->lay;
     const int nc = Pl->nc, kst = m2lb_ksteps(nc);
     // split the multipoles of levels 2..L (levels 0, 1 have no M2L)
-    const int64_t box0 = lay.lvl_off[2], nbox = lay.nbox - box0;
+    const int64_t box0 = exp_box0(Pl), nbox = exp_nbox(Pl) - box0;
     u32x4* mq = wsp<u32x4>(Pl, lay.multb);
     const int qr = m2lb_row_quads(nc, NP);
     k_split_mult<NP><<<grid_for(nbox * kst * 4, kBlock), kBlock, 0, s>>>(
@@ -385,7 +385,7 @@ struct M2LBfRun {
   static hipError_t go_f16(fmm_plan_s* Pl, hipStream_t s) {
     const Layout& lay = Pl->lay;
     const int nc = Pl->nc, kst = m2lb_ksteps(nc);
-    const int64_t box0 = lay.lvl_off[2], nbox = lay.nbox - box0;
+    const int64_t box0 = exp_box0(Pl), nbox = exp_nbox(Pl) - box0;
     u32x4* mq = wsp<u32x4>(Pl, lay.multb);
     const int qr = m2lb_row_quads(nc, 2);
     float* msc = wsp<float>(Pl, lay.f16_mscale);

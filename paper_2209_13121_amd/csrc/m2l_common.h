@@ -56,29 +56,39 @@ __device__ __forceinline__ int il_offset(int pi, int i, int& dx, int& dy, int& d
 }
 
 struct Args {
-  int L;
-  int64_t lvl_off[FMM_DEPTH_MAX + 2];    // box offsets per level
+  int L;                                 // deepest level with targets
+  int64_t lvl_off[FMM_DEPTH_MAX + 2];    // dense box offsets per level (c2s, s2c)
+  int64_t exp_off[FMM_DEPTH_MAX + 2];    // first row of each level in the expansion arrays
   int64_t group_off[FMM_DEPTH_MAX + 2];  // first work-group of each level (levels 2..L)
   int64_t ngroups;
   const uint32_t* c2s;
   const uint32_t* s2c;
+  // Adaptive tree only (null for the uniform one): per dense box, whether it
+  // exists and its row in the expansion arrays.
+  const uint32_t* present;
+  const uint32_t* row;
 };
 
 inline Args make_args(fmm_plan_s* Pl) {
   const Layout& lay = Pl->lay;
   Args a;
-  a.L = Pl->L;
-  for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) a.lvl_off[l] = lay.lvl_off[l];
+  a.L = Pl->adaptive ? Pl->Ld : Pl->L;
+  for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) {
+    a.lvl_off[l] = lay.lvl_off[l];
+    a.exp_off[l] = Pl->adaptive ? Pl->ce_off[l] : lay.lvl_off[l];
+  }
   int64_t g = 0;
-  for (int l = 2; l <= Pl->L; ++l) {
+  for (int l = 2; l <= a.L; ++l) {
     a.group_off[l] = g;
     const int64_t np = (int64_t)1 << (3 * (l - 1));
     g += 8 * ((np + kTargetsPerGroup - 1) / kTargetsPerGroup);
   }
-  a.group_off[Pl->L + 1] = g;
+  a.group_off[a.L + 1] = g;
   a.ngroups = g;
   a.c2s = wsp<uint32_t>(Pl, lay.coord2slot);
   a.s2c = wsp<uint32_t>(Pl, lay.slot2coord);
+  a.present = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_present) : nullptr;
+  a.row = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_scan) : nullptr;
   return a;
 }
 inline unsigned grid_of(const Args& a) { return (unsigned)(((a.ngroups + 7) / 8) * 8); }
@@ -94,17 +104,22 @@ struct Src {
   bool ok;  // inside the domain (else the source is a zero row)
 };
 
+// Staged halo entries of the adaptive tree: a box that does not exist.
+constexpr uint32_t kAbsent = 0x80000000u;
+
 // A lane's view of its work-group's tile.
 struct Tile {
   int l, pi, nb;
   int tx, ty, tz;  // this lane's target box (meaningful when col_ok)
   bool col_ok;
   int hx0, hy0, hz0, hx1, hy1, hz1, hey, hez;  // halo box (clamped to the level)
-  int64_t lvl_off;                             // first box of level l
+  int64_t lvl_off;                             // first row of level l in the expansion arrays
+  int64_t dense_off;                           // first box of level l in the dense tables
 
   // Decode the group, find this lane's target (number tix of the tile's 128)
-  // and stage the halo's slots in sSlot.  Returns false, uniformly over the
-  // work-group, for a group past the end.  Contains barriers.
+  // and stage the halo's rows in sSlot (kAbsent where the adaptive tree has no
+  // box).  Returns false, uniformly over the work-group, for a group past the
+  // end or one without any existing target.  Contains barriers.
   __device__ bool setup(const Args& a, int tix, uint32_t* sSlot, int* sBox) {
     // XCD-aware order: hardware group b runs on XCD b % 8; each XCD gets a
     // contiguous range of logical groups.
@@ -121,7 +136,8 @@ struct Tile {
     const int64_t tile = idx / 8;
     const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
     nb = 1 << l;
-    lvl_off = a.lvl_off[l];
+    lvl_off = a.exp_off[l];
+    dense_off = a.lvl_off[l];
     const int64_t ps = tile * kTargetsPerGroup + tix;
     col_ok = ps < np;
     tx = ty = tz = 0;
@@ -130,6 +146,7 @@ struct Tile {
       tx = 2 * tx + px;
       ty = 2 * ty + py;
       tz = 2 * tz + pz;
+      if (a.present) col_ok = a.present[dense_off + a.c2s[dense_off + lex_index(tx, ty, tz, l)]] != 0;
     }
     const int tid = threadIdx.x;
     if (tid < 6) sBox[tid] = tid < 3 ? nb : -1;
@@ -143,6 +160,7 @@ struct Tile {
       atomicMax(&sBox[5], tz - pz + 3);
     }
     __syncthreads();
+    if (sBox[3] == -1) return false;  // no existing target in this tile
     hx0 = sBox[0] < 0 ? 0 : sBox[0];
     hy0 = sBox[1] < 0 ? 0 : sBox[1];
     hz0 = sBox[2] < 0 ? 0 : sBox[2];
@@ -152,10 +170,16 @@ struct Tile {
     hey = hy1 - hy0 + 1;
     hez = hz1 - hz0 + 1;
     const int hn = (hx1 - hx0 + 1) * hey * hez;  // <= kHalo by the bound above
-    const uint32_t* c2s = a.c2s + lvl_off;
+    const uint32_t* c2s = a.c2s + dense_off;
     for (int e = tid; e < hn && e < kHalo; e += (int)blockDim.x) {
       const int x = hx0 + e / (hey * hez), y = hy0 + (e / hez) % hey, z = hz0 + e % hez;
-      sSlot[e] = c2s[lex_index(x, y, z, l)];
+      const uint32_t slot = c2s[lex_index(x, y, z, l)];
+      uint32_t v = slot;
+      if (a.present) {
+        const int64_t g = dense_off + slot;
+        v = a.present[g] ? (uint32_t)(a.row[g] - lvl_off) : kAbsent;
+      }
+      sSlot[e] = v;
     }
     __syncthreads();
     return true;
@@ -170,12 +194,14 @@ struct Tile {
     sx = sx < hx0 ? hx0 : (sx > hx1 ? hx1 : sx);
     sy = sy < hy0 ? hy0 : (sy > hy1 ? hy1 : sy);
     sz = sz < hz0 ? hz0 : (sz > hz1 ? hz1 : sz);
-    return Src{sSlot[((sx - hx0) * hey + (sy - hy0)) * hez + (sz - hz0)], ok};
+    const uint32_t v = sSlot[((sx - hx0) * hey + (sy - hy0)) * hez + (sz - hz0)];
+    return Src{v & ~kAbsent, ok && !(v & kAbsent)};
   }
 
-  // Slot of this lane's target (col_ok only).
+  // Row of this lane's target within its level (col_ok only).
   __device__ __forceinline__ int64_t target_slot(const Args& a) const {
-    return a.c2s[lvl_off + lex_index(tx, ty, tz, l)];
+    const uint32_t slot = a.c2s[dense_off + lex_index(tx, ty, tz, l)];
+    return a.present ? (int64_t)a.row[dense_off + slot] - lvl_off : (int64_t)slot;
   }
 };
 

@@ -68,6 +68,10 @@ struct ShiftArgs {
   float* dst32;               // M2M mixed: FP32 copy of the parents; L2L mixed leaf: leaf locals
   const void* m2l;            // L2L: M2L results of the children (stride NC, FP32 if mixed)
   const DevParams* dp;
+  // Adaptive tree: target column ps is the ps-th divided parent, whose row
+  // within its level is parent_of[8 ps] (children 8 ps .. 8 ps + 7 of the
+  // child level); null for the uniform tree (row ps).
+  const uint32_t* parent_of;
 };
 
 template <int P, int MODE>
@@ -93,6 +97,7 @@ __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
   const int64_t pgroup = MODE == 1 ? rest / 8 : rest;
   const int64_t ps = (pgroup * kWaves + wave) * 16 + col;  // parent slot of this column
   const bool ok = ps < a.nparent;
+  const int64_t prow = !ok ? 0 : (a.parent_of ? (int64_t)a.parent_of[8 * ps] : ps);
 
   // child slot of each octant (children of slot ps are slots 8 ps .. 8 ps + 7),
   // packed 3 bits per octant
@@ -137,7 +142,7 @@ __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
     // source does not exist or k is past the row
     auto load_b = [&](int oct, f64x2* bv) {
       const bool have = ok;
-      const int64_t srow = !have ? 0 : (MODE == 0 ? 8 * ps + child_of(oct) : ps);
+      const int64_t srow = !have ? 0 : (MODE == 0 ? 8 * ps + child_of(oct) : prow);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int k = 8 * q + 2 * kg;
@@ -195,10 +200,10 @@ __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
   const int rr = row0 + 4 * kg;  // this lane's 4 rows; MS % 4 == 0, so all or none < MS
   if (!ok || rr >= MS) return;
   if (MODE == 0) {  // rows NC..MS-1 are zero (zero operator rows)
-    *reinterpret_cast<f64x2*>(a.dst64 + ps * MS + rr) = f64x2{v[0], v[1]};
-    *reinterpret_cast<f64x2*>(a.dst64 + ps * MS + rr + 2) = f64x2{v[2], v[3]};
+    *reinterpret_cast<f64x2*>(a.dst64 + prow * MS + rr) = f64x2{v[0], v[1]};
+    *reinterpret_cast<f64x2*>(a.dst64 + prow * MS + rr + 2) = f64x2{v[2], v[3]};
     if (a.dst32)
-      *reinterpret_cast<f32x4*>(a.dst32 + ps * MS + rr) =
+      *reinterpret_cast<f32x4*>(a.dst32 + prow * MS + rr) =
           f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
   } else {
     const int64_t cs = 8 * ps + child_of(oct_l2l);
@@ -259,12 +264,11 @@ hipError_t launch_m2m(fmm_plan_s* P, hipStream_t s) {
   for (int l = P->L - 1; l >= 2; --l) {
     ShiftArgs a = {};
     a.l = l;
-    a.mixed = (l + 1 == P->L && P->mixed) ? 1 : 0;  // leaf multipoles are FP32 in the mixed mode
+    a.mixed = 0;  // every multipole, the leaves' included, is kept in FP64
     a.nparent = (int64_t)1 << (3 * l);
     a.s2c_child = wsp<uint32_t>(P, lay.slot2coord) + lay.lvl_off[l + 1];
     a.ops = wsp<double>(P, lay.op_m2m);
-    a.src = a.mixed ? (const void*)(m32 + lay.lvl_off[l + 1] * ms)
-                    : (const void*)(m64 + lay.lvl_off[l + 1] * ms);
+    a.src = m64 + lay.lvl_off[l + 1] * ms;
     a.dst64 = m64 + lay.lvl_off[l] * ms;
     a.dst32 = m32 ? m32 + lay.lvl_off[l] * ms : nullptr;
     a.dp = wsp<DevParams>(P, lay.params);
@@ -305,6 +309,72 @@ hipError_t launch_l2l(fmm_plan_s* P, hipStream_t s) {
     a.dst32 = (l == L && P->mixed) ? leaf32 : nullptr;
     a.m2l = P->mixed ? (const void*)(wsp<float>(P, lay.m2l_out) + lay.lvl_off[l] * nc)
                      : (const void*)(wsp<double>(P, lay.m2l_out) + lay.lvl_off[l] * nc);
+    a.dp = dp;
+    hipError_t e = dispatch_p<ShiftRun>(P->p, a, 1, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+// Adaptive tree: the same kernels over the divided boxes of each level (the
+// compact rows of a level are contiguous; children of the k-th divided box of
+// level l are rows 8k .. 8k+7 of level l + 1).  Every multipole is read in
+// FP64; every local is written in FP64.
+hipError_t launch_m2m_adaptive(fmm_plan_s* P, hipStream_t s) {
+  const Layout& lay = P->lay;
+  const int ms = mstride(P->p);
+  double* m64 = wsp<double>(P, lay.mult64);
+  float* m32 = P->mixed ? wsp<float>(P, lay.mult32) : nullptr;
+  for (int l = P->Ld - 1; l >= 2; --l) {
+    if (P->nsplit[l] == 0) continue;
+    ShiftArgs a = {};
+    a.l = l;
+    a.mixed = 0;
+    a.nparent = P->nsplit[l];
+    a.s2c_child = wsp<uint32_t>(P, lay.a_coord) + P->ce_off[l + 1];
+    a.parent_of = wsp<uint32_t>(P, lay.a_parent_of) + P->ce_off[l + 1];
+    a.ops = wsp<double>(P, lay.op_m2m);
+    a.src = m64 + P->ce_off[l + 1] * ms;
+    a.dst64 = m64 + P->ce_off[l] * ms;
+    a.dst32 = m32 ? m32 + P->ce_off[l] * ms : nullptr;
+    a.dp = wsp<DevParams>(P, lay.params);
+    hipError_t e = dispatch_p<ShiftRun>(P->p, a, 0, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_l2l_adaptive(fmm_plan_s* P, hipStream_t s) {
+  const Layout& lay = P->lay;
+  const int nc = P->nc, ms = mstride(P->p);
+  double* l64 = wsp<double>(P, lay.loc_exp64);
+  const DevParams* dp = wsp<DevParams>(P, lay.params);
+  const int64_t nb2 = P->ce_off[3] - P->ce_off[2];
+  if (nb2 > 0) {
+    if (P->mixed)
+      k_l2l_top<float><<<grid_for(nb2 * ms, kBlock), kBlock, 0, s>>>(
+          nc, ms, 2, nb2, dp, wsp<float>(P, lay.m2l_out) + P->ce_off[2] * nc,
+          l64 + P->ce_off[2] * ms, nullptr);
+    else
+      k_l2l_top<double><<<grid_for(nb2 * ms, kBlock), kBlock, 0, s>>>(
+          nc, ms, 2, nb2, dp, wsp<double>(P, lay.m2l_out) + P->ce_off[2] * nc,
+          l64 + P->ce_off[2] * ms, nullptr);
+  }
+  for (int l = 3; l <= P->Ld; ++l) {
+    if (P->nsplit[l - 1] == 0) continue;
+    ShiftArgs a = {};
+    a.l = l;
+    a.mixed = P->mixed ? 1 : 0;
+    a.leaf = 0;
+    a.nparent = P->nsplit[l - 1];
+    a.s2c_child = wsp<uint32_t>(P, lay.a_coord) + P->ce_off[l];
+    a.parent_of = wsp<uint32_t>(P, lay.a_parent_of) + P->ce_off[l];
+    a.ops = wsp<double>(P, lay.op_l2l);
+    a.src = l64 + P->ce_off[l - 1] * ms;
+    a.dst64 = l64 + P->ce_off[l] * ms;
+    a.dst32 = nullptr;
+    a.m2l = P->mixed ? (const void*)(wsp<float>(P, lay.m2l_out) + P->ce_off[l] * nc)
+                     : (const void*)(wsp<double>(P, lay.m2l_out) + P->ce_off[l] * nc);
     a.dp = dp;
     hipError_t e = dispatch_p<ShiftRun>(P->p, a, 1, s);
     if (e != hipSuccess) return e;

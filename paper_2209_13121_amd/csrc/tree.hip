@@ -148,6 +148,8 @@ __global__ void k_scan_add(uint32_t* __restrict__ out, int64_t n, const uint32_t
   if (i < n) out[i] += boff[i / 1024];
 }
 
+}  // namespace
+
 // out[0..n) = exclusive scan of in[0..n_valid) padded with zeros.
 hipError_t scan_exclusive(const uint32_t* in, int64_t n_valid, int64_t n, uint32_t* out,
                           uint32_t* tmp, hipStream_t s) {
@@ -160,6 +162,8 @@ hipError_t scan_exclusive(const uint32_t* in, int64_t n_valid, int64_t n, uint32
   }
   return hipGetLastError();
 }
+
+namespace {
 
 __global__ void k_scatter(const uint32_t* __restrict__ keys, int64_t n,
                           const uint32_t* __restrict__ start, uint32_t* __restrict__ fill,
@@ -205,7 +209,8 @@ template <typename T>
 __global__ void k_gather(const double* __restrict__ pos, const int32_t* __restrict__ perm,
                          const uint32_t* __restrict__ keys, int64_t n, int L,
                          const DevParams* __restrict__ dp, const uint32_t* __restrict__ s2c_leaf,
-                         uint32_t* __restrict__ sorted_leaf, Rec<T>* __restrict__ src) {
+                         uint32_t* __restrict__ sorted_leaf, Rec<T>* __restrict__ src,
+                         Rec<double>* __restrict__ src64) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const int32_t i = perm[s];
@@ -227,6 +232,7 @@ __global__ void k_gather(const double* __restrict__ pos, const int32_t* __restri
   r.z = (T)u[2];
   r.q = T(0);  // filled by each evaluation
   src[s] = r;
+  if (src64) src64[s] = Rec<double>{u[0], u[1], u[2], 0.0};
 }
 
 __global__ void k_leaves_out(const uint32_t* __restrict__ keys, int64_t n,
@@ -343,14 +349,16 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
   int32_t* perm = wsp<int32_t>(P, lay.perm);
   k_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(keys, n, start, fill, perm_tmp);
   k_rank<<<grid_for(n, kBlock), kBlock, 0, s>>>(perm_tmp, keys, n, start, count, perm);
-  if (P->mixed)
+  if (P->adaptive) {
+    // leaves and box-unit offsets come from the adaptive tree (adaptive.hip)
+  } else if (P->mixed)
     k_gather<float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
         d_pos, perm, keys, n, L, dp, s2c + lay.lvl_off[L], wsp<uint32_t>(P, lay.sorted_leaf),
-        wsp<Rec<float>>(P, lay.src));
+        wsp<Rec<float>>(P, lay.src), wsp<Rec<double>>(P, lay.src64));
   else
     k_gather<double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
         d_pos, perm, keys, n, L, dp, s2c + lay.lvl_off[L], wsp<uint32_t>(P, lay.sorted_leaf),
-        wsp<Rec<double>>(P, lay.src));
+        wsp<Rec<double>>(P, lay.src), nullptr);
   prof_end(P, s);
   return hipGetLastError();
 }

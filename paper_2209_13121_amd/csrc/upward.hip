@@ -2,8 +2,13 @@
 // level 2.
 //
 // P2M: M~_n^m = sum_j q_j conj(R_n^m(u_j)) with u_j the box-unit offset of
-// particle j from its leaf centre (computed by the tree pass), in the
-// compute precision (FP32 for the mixed mode, FP64 otherwise).
+// particle j from its leaf centre (computed by the tree pass), accumulated in
+// FP64 in both precision modes from the FP64 offsets; the mixed mode also
+// stores the result rounded to FP32 for the M2L pass.  (An FP32 sum of
+// neutral clusters of charges, one cluster after another, rounds every cluster's
+// partial sums the same way, so the leaf monopoles would drift by an amount
+// proportional to the particle count: a smooth, density-shaped error charge.
+// FP64 adds cost the same issue slots as FP32 ones here.)
 // M2M (shift.hip): M~p = sum over the 8 children of A[octant] M~c with the
 // level-free octant matrices, always in FP64; in the mixed mode each parent is
 // also stored rounded to FP32 for the M2L pass.
@@ -14,18 +19,21 @@ namespace {
 
 template <typename T>
 __global__ void k_gather_q(const double* __restrict__ q, const int32_t* __restrict__ perm, int64_t n,
-                           double* __restrict__ q64, Rec<T>* __restrict__ src) {
+                           double* __restrict__ q64, Rec<T>* __restrict__ src,
+                           Rec<double>* __restrict__ src64) {
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const double v = q[perm[s]];
   q64[s] = v;
   src[s].q = (T)v;
+  if (src64) src64[s].q = v;
 }
 
-template <int P, typename T>
+template <int P>
 __global__ __launch_bounds__(kBlock) void k_p2m(const uint32_t* __restrict__ start,
-                                                const Rec<T>* __restrict__ src, int64_t nleaf,
-                                                T* __restrict__ mult) {
+                                                const Rec<double>* __restrict__ src, int64_t nleaf,
+                                                double* __restrict__ mult, float* __restrict__ mult32) {
+  typedef double T;
   constexpr int NC = (P + 1) * (P + 1);
   constexpr int MS = mstride_of(NC);
   constexpr int NT = (P + 1) * (P + 2) / 2;
@@ -52,25 +60,23 @@ __global__ __launch_bounds__(kBlock) void k_p2m(const uint32_t* __restrict__ sta
   }
   T* out = mult + leaf * MS;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) out[c] = acc[c];
+  for (int c = 0; c < MS; ++c) out[c] = c < NC ? acc[c] : T(0);
+  if (mult32) {
+    float* o32 = mult32 + leaf * MS;
 #pragma unroll
-  for (int c = NC; c < MS; ++c) out[c] = T(0);
+    for (int c = 0; c < MS; ++c) o32[c] = c < NC ? (float)acc[c] : 0.f;
+  }
 }
 
 template <int P>
 struct P2MRun {
-  template <typename T>
-  static hipError_t go(fmm_plan_s* Pl, T* mult_leaf, hipStream_t s) {
-    const int64_t nleaf = Pl->lay.nleaf;
-    k_p2m<P, T><<<grid_for(nleaf, 64), 64, 0, s>>>(wsp<uint32_t>(Pl, Pl->lay.leaf_start),
-                                                   wsp<Rec<T>>(Pl, Pl->lay.src), nleaf, mult_leaf);
-    return hipGetLastError();
-  }
   static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
     const Layout& lay = Pl->lay;
-    if (Pl->mixed)
-      return go<float>(Pl, wsp<float>(Pl, lay.mult32) + lay.lvl_off[Pl->L] * mstride(Pl->p), s);
-    return go<double>(Pl, wsp<double>(Pl, lay.mult64) + lay.lvl_off[Pl->L] * mstride(Pl->p), s);
+    const int64_t nleaf = lay.nleaf, row0 = lay.lvl_off[Pl->L] * mstride(Pl->p);
+    k_p2m<P><<<grid_for(nleaf, 64), 64, 0, s>>>(
+        wsp<uint32_t>(Pl, lay.leaf_start), wsp<Rec<double>>(Pl, Pl->mixed ? lay.src64 : lay.src), nleaf,
+        wsp<double>(Pl, lay.mult64) + row0, Pl->mixed ? wsp<float>(Pl, lay.mult32) + row0 : nullptr);
+    return hipGetLastError();
   }
 };
 
@@ -82,11 +88,14 @@ hipError_t launch_upward(fmm_plan_s* P, const double* d_q, hipStream_t s) {
   if (d_q) {  // NULL: reuse the sorted charges of the last evaluation (adjoint)
     if (P->mixed)
       k_gather_q<float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
-          d_q, wsp<int32_t>(P, lay.perm), n, wsp<double>(P, lay.q64), wsp<Rec<float>>(P, lay.src));
+          d_q, wsp<int32_t>(P, lay.perm), n, wsp<double>(P, lay.q64), wsp<Rec<float>>(P, lay.src),
+          wsp<Rec<double>>(P, lay.src64));
     else
       k_gather_q<double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
-          d_q, wsp<int32_t>(P, lay.perm), n, wsp<double>(P, lay.q64), wsp<Rec<double>>(P, lay.src));
+          d_q, wsp<int32_t>(P, lay.perm), n, wsp<double>(P, lay.q64), wsp<Rec<double>>(P, lay.src),
+          nullptr);
   }
+  if (P->adaptive) return launch_adaptive_upward(P, s);
   if (P->L < 2) return hipGetLastError();
   prof_begin(P, FMM_PHASE_P2M, s);
   hipError_t e = dispatch_p<P2MRun>(P->p, P, s);

@@ -129,4 +129,4 @@ class ClusterWorkload:
 
 # Adaptive case: 10^6 three-site clusters (3e6 sites), leaves of at most 64
 # sites, p = 10, mixed precision.
-CLUSTERS = ClusterWorkload("clusters-n3000000-leaf64-p10", 1_000_000, 64, 9, 10, 1003)
+CLUSTERS = ClusterWorkload("clusters-n3000000-leaf64-p10", 1_000_000, 64, 8, 10, 1003)

@@ -21,17 +21,22 @@ def device():
 
 
 def run_gpu(pos, q, depth, p, precision=B.FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
-            check=True, m2l_kind=B.FMM_M2L_AUTO):
-    """Plan + evaluate on the GPU; returns numpy (phi, force, energy, status)."""
+            check=True, m2l_kind=B.FMM_M2L_AUTO, leaf_max=0, stats=None):
+    """Plan + evaluate on the GPU; returns numpy (phi, force, energy, status).
+    leaf_max > 0: adaptive tree (depth = its cap); a dict passed as stats
+    receives the tree statistics."""
     import torch
     dev = device()
     tp = torch.from_numpy(np.ascontiguousarray(pos, dtype=np.float64)).to(dev)
     tq = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float64)).to(dev)
-    f = B.FMM(tp, p=p, depth=depth, precision=precision, lo=lo, side=side, m2l_kind=m2l_kind)
+    f = B.FMM(tp, p=p, depth=depth, precision=precision, lo=lo, side=side, m2l_kind=m2l_kind,
+              leaf_max=leaf_max)
     phi, force, energy = f.evaluate(tq)
     st = f.check()
     torch.cuda.synchronize()
     out = (phi.cpu().numpy(), force.cpu().numpy(), float(energy.cpu().numpy()[0]), st)
+    if stats is not None and leaf_max > 0:
+        stats.update(B.fmm_plan_tree_stats(f.plan))
     f.close()
     if check and st != 0:
         raise B.FMMError(st, "device flag")

@@ -38,7 +38,7 @@ def test_status_strings(lib):
 def test_config_validation(lib):
     n = 1000
     for field, bad, code in [("p", -1, 1), ("p", 13, 1), ("depth", -1, 1), ("depth", 10, 1),
-                             ("ws", 2, 1), ("leaf_max", 64, 6), ("precision", 5, 1),
+                             ("ws", 2, 1), ("leaf_max", -1, 1), ("precision", 5, 1),
                              ("m2l_kind", 9, 1), ("abi_version", 2, 1)]:
         cfg = B.make_config()
         setattr(cfg, field, bad)
@@ -58,6 +58,23 @@ def test_config_validation(lib):
     for bad_n in (0, -5, 2**31):
         with pytest.raises(B.FMMError):
             B.fmm_workspace_size(B.make_config(), bad_n)
+
+
+def test_adaptive_workspace(lib):
+    # The adaptive layout is bounded by the possible boxes: a larger leaf
+    # capacity or a shallower cap needs less room; a uniform plan of the same
+    # depth needs none of the list or dense-flag arrays.
+    n = 100_000
+    a16 = B.fmm_workspace_size(B.make_config(depth=6, p=6, leaf_max=16), n)
+    a64 = B.fmm_workspace_size(B.make_config(depth=6, p=6, leaf_max=64), n)
+    a64c = B.fmm_workspace_size(B.make_config(depth=5, p=6, leaf_max=64), n)
+    u = B.fmm_workspace_size(B.make_config(depth=6, p=6), n)
+    assert a16 > a64 > a64c > 0
+    assert a64 != u
+    # the clustered workload at full size fits comfortably in one GPU's memory
+    big = B.fmm_workspace_size(B.make_config(depth=8, p=10, leaf_max=64,
+                                             precision=B.FMM_PREC_MIXED), 3_000_000)
+    assert big < 16 * 2**30
 
 
 def test_split_bf16_workspace(lib):
