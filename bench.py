@@ -58,6 +58,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true",
+                    help="skip the adaptive-tree workload (10^6 three-site clusters)")
+    ap.add_argument("--adaptive-only", action="store_true",
+                    help="run only the adaptive-tree workload and print its JSON object")
     ap.add_argument("--cpu-sample-boxes", type=int, default=3,
                     help="level-1 boxes (1/8 of the domain each) whose particles the oracle evaluates")
     ap.add_argument("--only", choices=sorted(VARIANTS), default=None,
@@ -198,6 +202,85 @@ def p2p_evidence(B, torch, pos, q, stream, depth=4, reps=3):
     return out
 
 
+def adaptive_bench(B, torch, args, stream):
+    """The adaptive-tree workload (10^6 three-site clusters, leaves of at most
+    64 sites, p = 10): plan + evaluate timed like the headline, mixed (FP16
+    M2L, the library default) and FP64; accuracy of mixed against FP64 and of
+    both against the exact sum on sampled sites; the M2L kernel's rate from the
+    tree's own count of non-empty M2L pairs."""
+    import numpy as np
+    import oracle
+    from paper_2209_13121_amd import workloads as W
+    wl = W.CLUSTERS
+    pos_np, q_np = wl.make()
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(pos_np).to(dev)
+    q = torch.from_numpy(q_np).to(dev)
+    res = {}
+    for name, prec, kind, dtype, nprod, kernel in (
+            ("mixed_f16x2", "MIXED", "F16X2", "f16", 3, "k_m2l_bf<10,2,f16>"),
+            ("fp64", "FP64", "AUTO", "f64", 1, "k_m2l<10,double>")):
+        cfg = B.make_config(p=wl.p, depth=wl.max_depth, precision=getattr(B, "FMM_PREC_" + prec),
+                            m2l_kind=getattr(B, "FMM_M2L_" + kind), side=0.0, leaf_max=wl.leaf_max)
+        nbytes = B.fmm_workspace_size(cfg, wl.n)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        print(f"[bench] adaptive {name}: workspace {nbytes / 2**20:.0f} MiB", file=sys.stderr, flush=True)
+        ms, step_stats, phi, force, energy, m2l, phases, st, work = timed_steps(
+            B, torch, pos, q, cfg, ws, max(5, args.steps // 2), args.warmup, stream)
+        p = B.fmm_plan(cfg, wl.n, pos, ws, stream)
+        stats = B.fmm_plan_tree_stats(p)
+        B.fmm_destroy(p)
+        t, c = m2l
+        avg = t / c
+        flops = 2.0 * (wl.p + 1) ** 4 * stats["m2l_pairs"]
+        peak = PEAK_TFLOPS[dtype]
+        res[name] = {"value": wl.n / (ms / 1e3), "ms_per_step": ms, "step_events_ms": step_stats,
+                     "status": st, "phases_ms_per_step": {k: v[0] for k, v in phases.items()},
+                     "m2l": {"kernel": kernel, "avg_launch_ms": avg, "flops_per_launch": nprod * flops,
+                             "achieved": nprod * flops / (avg / 1e3) / 1e12, "peak": peak,
+                             "frac": nprod * flops / (avg / 1e3) / 1e12 / peak,
+                             "fp32_equivalent_tflops": flops / (avg / 1e3) / 1e12},
+                     "phi": phi.cpu().numpy(), "force": force.cpu().numpy(),
+                     "energy": float(energy.cpu()[0])}
+        print(f"[bench] adaptive {name}: {ms:.3f} ms/step, status {st}", file=sys.stderr, flush=True)
+        del ws
+        torch.cuda.empty_cache()
+    m, f = res["mixed_f16x2"], res["fp64"]
+    rng = np.random.default_rng(7)
+    idx = rng.choice(wl.n, 256, replace=False)
+    phi_d, force_d, _ = oracle.direct(pos_np, q_np, targets=idx)
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    acc = {"rel_energy_err_vs_fp64_gpu": abs(m["energy"] - f["energy"]) / abs(f["energy"]),
+           "rel_rms_force_err_vs_fp64_gpu": rel(m["force"], f["force"]),
+           "rel_phi_err_vs_fp64_gpu": rel(m["phi"], f["phi"]),
+           "rel_phi_err_vs_direct_256_sampled": {"mixed": rel(m["phi"][idx], phi_d),
+                                                  "fp64": rel(f["phi"][idx], phi_d)},
+           "rel_force_err_vs_direct_256_sampled": {"mixed": rel(m["force"][idx], force_d),
+                                                    "fp64": rel(f["force"][idx], force_d)}}
+    acc["gate_1e-6_met"] = bool(acc["rel_energy_err_vs_fp64_gpu"] <= 1e-6 and
+                                acc["rel_rms_force_err_vs_fp64_gpu"] <= 1e-5)
+    for r in res.values():
+        for k in ("phi", "force", "energy"):
+            r.pop(k)
+    out = {"workload": wl.name, "n": wl.n, "leaf_max": wl.leaf_max, "depth_cap": wl.max_depth,
+           "p": wl.p, "seed": wl.seed, "metric": "particles/s per FMM evaluation (plan + evaluate)",
+           "value": m["value"], "ms_per_step": m["ms_per_step"], "tree": stats, "accuracy": acc,
+           "variants": res}
+    if not args.no_cpu_baseline:
+        sample = W.molecular_clusters(30_000, wl.seed)[:2]
+        t0 = time.perf_counter()
+        oracle.fmm_adaptive(sample[0], sample[1], wl.leaf_max, wl.max_depth, wl.p, side=0.0)
+        dt = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": len(sample[1]) / dt, "unit": "particles/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"CPU FP64 oracle adaptive FMM on 3e4 clusters (9e4 sites) of the "
+                                         f"same recipe, leaf_max {wl.leaf_max}, p {wl.p}; {dt:.1f} s wall"}
+    return out
+
+
 def cpu_baseline(pos, q, wl, nboxes):
     import numpy as np
     import oracle
@@ -228,6 +311,10 @@ def main():
     from paper_2209_13121_amd import binding as B
     from paper_2209_13121_amd import workloads as W
 
+    if args.adaptive_only:
+        B.load()
+        print(json.dumps(adaptive_bench(B, torch, args, torch.cuda.current_stream())), flush=True)
+        return
     wl = W.HEADLINE
     pos_np, q_np = wl.make()
     dev = torch.device("cuda:0")
@@ -337,6 +424,10 @@ def main():
     }
     print("[bench] p2p at depth 4", file=sys.stderr, flush=True)
     out["p2p_depth4"] = p2p_evidence(B, torch, pos, q, stream)
+    if not args.no_adaptive:
+        del pos, q
+        torch.cuda.empty_cache()
+        out["adaptive"] = adaptive_bench(B, torch, args, stream)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pos_np, q_np, wl, args.cpu_sample_boxes)

@@ -201,14 +201,15 @@ enum {
   FMM_PHASE_OPERATORS,  /* translation-operator tables */
   FMM_PHASE_P2M,
   FMM_PHASE_M2M,
-  FMM_PHASE_M2L,
-  FMM_PHASE_L2L,
-  FMM_PHASE_L2P,
+  FMM_PHASE_M2L,        /* the M2L kernel alone */
+  FMM_PHASE_L2L,        /* adaptive tree: P2L included */
+  FMM_PHASE_L2P,        /* adaptive tree: M2P included */
   FMM_PHASE_P2P,        /* near field, combination, unpermute, energy partials */
   FMM_PHASE_ENERGY,
+  FMM_PHASE_SPLIT,      /* split forms of M2L: multipoles into BF16 / FP16 pieces */
   FMM_PHASE_COUNT
 };
-#define FMM_PROFILE_ALL 0x1ff
+#define FMM_PROFILE_ALL 0x3ff
 fmm_status fmm_profile_enable(fmm_plan_t *plan, int phase_mask);
 fmm_status fmm_profile_read(fmm_plan_t *plan, double ms[FMM_PHASE_COUNT],
                             int32_t launches[FMM_PHASE_COUNT]);

@@ -21,7 +21,7 @@ FMM_M2L_AUTO, FMM_M2L_F64, FMM_M2L_F32, FMM_M2L_BF16X2, FMM_M2L_BF16X3, FMM_M2L_
 STATUS_NAMES = {0: "FMM_OK", 1: "FMM_E_INVALID_ARG", 2: "FMM_E_WORKSPACE", 3: "FMM_E_OUT_OF_CUBE",
                 4: "FMM_E_NONFINITE", 5: "FMM_E_COINCIDENT", 6: "FMM_E_UNSUPPORTED",
                 7: "FMM_E_DEVICE"}
-PHASES = ["tree", "operators", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "energy"]
+PHASES = ["tree", "operators", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "energy", "split"]
 
 # every symbol include/fmm.h declares
 EXPORTS = ["fmm_config_default", "fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_backward",
@@ -183,7 +183,7 @@ def fmm_hilbert_index(ix, iy, iz, bits):
     return int(load().fmm_hilbert_index(ix, iy, iz, bits))
 
 
-FMM_PROFILE_ALL = 0x1FF
+FMM_PROFILE_ALL = 0x3FF
 
 
 def fmm_profile_enable(plan, on=True, phases=None):

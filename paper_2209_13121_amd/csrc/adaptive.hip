@@ -1,6 +1,7 @@
 // adaptive.hip -- the adaptive octree: which boxes exist, their compact
 // numbering, the U, W and X lists, and the passes only the adaptive tree has
-// (P2M and L2P at leaves of any level, P2L over X, M2P over W).
+// (P2M at leaves of any level, P2L over X, M2P over W; L2P at leaves of any
+// level is the uniform kernel given each leaf's level, downward.hip).
 //
 // Tree (Cheng, Greengard & Rokhlin, J. Comput. Phys. 155:468 (1999), sec. 4):
 // a box holding more than leaf_max particles is divided into its 8 children
@@ -34,6 +35,7 @@
 #include <algorithm>
 
 #include "fmm_internal.h"
+#include "m2l_common.h"
 
 namespace fmm {
 namespace {
@@ -159,6 +161,52 @@ __global__ void k_gather_adaptive(ATree t, const double* __restrict__ pos,
   if (src64) src64[s] = Rec<double>{u[0], u[1], u[2], 0.0};
 }
 
+// ---- M2L work lists -------------------------------------------------------------
+
+struct VLevels {
+  int64_t ndiv[FMM_DEPTH_MAX + 2];     // divided parents of level l - 1 (targets per class)
+  int64_t tgt_off[FMM_DEPTH_MAX + 2];
+  int64_t vt_off[FMM_DEPTH_MAX + 2];
+};
+
+// Class pi of a box is the parity of its cell; the k-th divided parent of
+// level l - 1 owns rows 8k .. 8k+7 of level l, one of each class.
+__global__ void k_m2l_targets(ATree t, VLevels v, uint32_t* __restrict__ tgt) {
+  const int64_t r = t.ce_off[2] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= t.nbox) return;
+  const int l = t.level[r];
+  int x, y, z;
+  unpack_coord(t.coord[r], x, y, z);
+  const int pi = ((x & 1) << 2) | ((y & 1) << 1) | (z & 1);
+  const int64_t rel = r - t.ce_off[l];
+  tgt[v.tgt_off[l] + pi * v.ndiv[l] + rel / 8] = (uint32_t)rel;
+}
+
+// Source row of every (tile, class, offset, target) of level l: the existing
+// box of level l at target - d (d the class's offset), or kAbsent.
+__global__ void k_m2l_sources(ATree t, VLevels v, int l, int64_t nent, const uint32_t* __restrict__ tgt,
+                              uint32_t* __restrict__ vtab) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nent) return;
+  const int tix = (int)(e % m2l::kTargetsPerGroup);
+  int64_t rest = e / m2l::kTargetsPerGroup;
+  const int i = (int)(rest % kIL);
+  rest /= kIL;
+  const int pi = (int)(rest % 8);
+  const int64_t tile = rest / 8;
+  const int64_t ps = tile * m2l::kTargetsPerGroup + tix;
+  uint32_t out = m2l::kAbsent;
+  if (ps < v.ndiv[l]) {
+    const uint32_t trow = tgt[v.tgt_off[l] + pi * v.ndiv[l] + ps];
+    int x, y, z, dx, dy, dz;
+    unpack_coord(t.coord[t.ce_off[l] + trow], x, y, z);
+    m2l::il_offset(pi, i, dx, dy, dz);
+    const int64_t c = find_box(t, l, x - dx, y - dy, z - dz);
+    if (c >= 0) out = (uint32_t)(c - t.ce_off[l]);
+  }
+  vtab[v.vt_off[l] + e] = out;
+}
+
 // ---- lists -------------------------------------------------------------------
 
 constexpr int kStack = 80;  // depth-first stack: at most 7 per level below the leaf + 8
@@ -257,6 +305,17 @@ __global__ void k_lists(ATree t, uint32_t* __restrict__ cnt, const uint32_t* __r
     cnt[nb1 + b] = nw;
     cnt[2 * nb1 + b] = nx;
   }
+}
+
+__global__ void k_flag_nonzero(const uint32_t* __restrict__ cnt, int64_t n, uint32_t* __restrict__ flag) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n) flag[b] = cnt[b] ? 1u : 0u;
+}
+
+__global__ void k_compact_nonzero(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ pos,
+                                  int64_t n, uint32_t* __restrict__ list) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < n && cnt[b]) list[pos[b]] = (uint32_t)b;
 }
 
 // Tree statistics: [0] leaves, [1] V entries, [2] M2L pairs of non-empty
@@ -380,16 +439,19 @@ __global__ __launch_bounds__(64) void k_p2m_adaptive(ATree t, const Rec<double>*
 
 // P2L over X(b), added to the M2L result of b (units before the 1/h of L2L):
 // q conj(I_n^m(v)) with v the source's offset from b's centre in b's units.
+// One thread per box of the compact list xbox (the boxes whose X list is not
+// empty).
 template <int P, typename T>
-__global__ __launch_bounds__(64) void k_p2l(ATree t, const uint32_t* __restrict__ xoff,
+__global__ __launch_bounds__(64) void k_p2l(ATree t, const uint32_t* __restrict__ xbox, int64_t nxbox,
+                                            const uint32_t* __restrict__ xoff,
                                             const uint32_t* __restrict__ xidx,
                                             const Rec<T>* __restrict__ src, T* __restrict__ m2l) {
   constexpr int NC = (P + 1) * (P + 1);
   constexpr int NT = (P + 1) * (P + 2) / 2;
-  const int64_t b = t.ce_off[2] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= t.nbox) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nxbox) return;
+  const int64_t b = xbox[e];
   const uint32_t k0 = xoff[b], k1 = xoff[b + 1];
-  if (k0 == k1) return;
   const int l = t.level[b];
   int bc[3];
   unpack_coord(t.coord[b], bc[0], bc[1], bc[2]);
@@ -428,72 +490,31 @@ __global__ __launch_bounds__(64) void k_p2l(ATree t, const uint32_t* __restrict_
   for (int c = 0; c < NC; ++c) o[c] += acc[c];
 }
 
-// L2P at every particle from its leaf's FP64 local expansion (zero above
-// level 2), then M2P over the leaf's W list.
+// M2P over the W list of a leaf, added to the far field L2P wrote: one wave
+// per leaf of the compact list wbox (the leaves whose W list is not empty), a
+// lane per particle (64 at a time), the W entries in list order, so every
+// lane reads the same multipole at once.
 template <int P, typename T>
-__global__ __launch_bounds__(kBlock) void k_l2p_m2p(ATree t, const uint32_t* __restrict__ sorted_leaf,
-                                                    const Rec<T>* __restrict__ src, int64_t n,
-                                                    const DevParams* __restrict__ dp,
-                                                    const double* __restrict__ loc64,
-                                                    const double* __restrict__ mult64,
-                                                    const uint32_t* __restrict__ woff,
-                                                    const uint32_t* __restrict__ widx,
-                                                    double* __restrict__ far_phi,
-                                                    double* __restrict__ far_grad) {
+__global__ __launch_bounds__(64) void k_m2p(ATree t, const uint32_t* __restrict__ wbox,
+                                            const Rec<T>* __restrict__ src, int64_t n,
+                                            const DevParams* __restrict__ dp,
+                                            const T* __restrict__ mult,
+                                            const uint32_t* __restrict__ woff,
+                                            const uint32_t* __restrict__ widx,
+                                            double* __restrict__ far_phi,
+                                            double* __restrict__ far_grad) {
   constexpr int MS = mstride_of((P + 1) * (P + 1));
-  constexpr int NT = (P + 1) * (P + 2) / 2;
   constexpr int NT1 = (P + 2) * (P + 3) / 2;
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const uint32_t leaf = sorted_leaf[s];
-  const int l = t.level[leaf];
-  const Rec<T> r = src[s];
-  double phi = 0.0, g[3] = {0.0, 0.0, 0.0};
-  if (l >= 2) {
-    const double* Lc = loc64 + (int64_t)leaf * MS;
-    T re[NT], im[NT];
-    regular_harmonics<P, T>(r.x, r.y, r.z, re, im);
-    T f = T(0), gx = T(0), gy = T(0), gz = T(0);
-#pragma unroll
-    for (int nn = 0; nn <= P; ++nn) {
-      {
-        const T c = (T)Lc[cidx_re(nn, 0)];
-        f += c * re[tri(nn, 0)];
-        if (nn >= 1) {
-          gz += c * re[tri(nn - 1, 0)];
-          if (nn >= 2) {
-            gx += c * re[tri(nn - 1, 1)];
-            gy += c * im[tri(nn - 1, 1)];
-          }
-        }
-      }
-#pragma unroll
-      for (int m = 1; m <= nn; ++m) {
-        const T cr = T(2) * (T)Lc[cidx_re(nn, m)], ci = T(2) * (T)Lc[cidx_im(nn, m)];
-        f += cr * re[tri(nn, m)] - ci * im[tri(nn, m)];
-        const T ar = re[tri(nn - 1, m - 1)], ai = im[tri(nn - 1, m - 1)];
-        T br = T(0), bi = T(0), zr = T(0), zi = T(0);
-        if (m + 1 <= nn - 1) {
-          br = re[tri(nn - 1, m + 1)];
-          bi = im[tri(nn - 1, m + 1)];
-        }
-        if (m <= nn - 1) {
-          zr = re[tri(nn - 1, m)];
-          zi = im[tri(nn - 1, m)];
-        }
-        gx += T(0.5) * (cr * (br - ar) - ci * (bi - ai));
-        gy += T(0.5) * (cr * (ai + bi) + ci * (ar + br));
-        gz += cr * zr - ci * zi;
-      }
-    }
-    const double inv_h = (double)(1 << l) / dp->side;
-    phi = (double)f;
-    g[0] = inv_h * (double)gx;
-    g[1] = inv_h * (double)gy;
-    g[2] = inv_h * (double)gz;
-  }
+  const int64_t leaf = wbox[blockIdx.x];  // a leaf whose W list is not empty
   const uint32_t k0 = woff[leaf], k1 = woff[leaf + 1];
-  if (k0 < k1) {
+  const uint32_t s0 = t.range[2 * leaf], cnt = t.range[2 * leaf + 1];
+  const int l = t.level[leaf];
+  for (uint32_t base = 0; base < cnt; base += 64) {
+    const uint32_t j = base + threadIdx.x;
+    const bool active = j < cnt;
+    const int64_t s = s0 + (active ? j : 0);
+    const Rec<T> r = src[s];
+    double phi = 0.0, g[3] = {0.0, 0.0, 0.0};
     int lc[3];
     unpack_coord(t.coord[leaf], lc[0], lc[1], lc[2]);
     for (uint32_t k = k0; k < k1; ++k) {
@@ -501,25 +522,25 @@ __global__ __launch_bounds__(kBlock) void k_l2p_m2p(ATree t, const uint32_t* __r
       const int lw = t.level[w];  // > l
       int wc[3];
       unpack_coord(t.coord[w], wc[0], wc[1], wc[2]);
-      // the particle's offset from w's centre in w's units, from the leaf-unit offset u:
-      // (leaf centre - w centre)/h_w + u h_leaf/h_w, the centre part exact
+      // the particle's offset from w's centre in w's units, from the leaf-unit
+      // offset u: (leaf centre - w centre)/h_w + u h_leaf/h_w, the centre part exact
       const double sc = (double)(1 << (lw - l));
       const T vx = (T)(((double)lc[0] + 0.5) * sc - ((double)wc[0] + 0.5)) + (T)sc * r.x;
       const T vy = (T)(((double)lc[1] + 0.5) * sc - ((double)wc[1] + 0.5)) + (T)sc * r.y;
       const T vz = (T)(((double)lc[2] + 0.5) * sc - ((double)wc[2] + 0.5)) + (T)sc * r.z;
       T re[NT1], im[NT1];
       irregular_harmonics<P + 1, T>(vx, vy, vz, re, im);
-      const double* Mw = mult64 + (int64_t)w * MS;
+      const T* Mw = mult + (int64_t)w * MS;
       T f = T(0), gx = T(0), gy = T(0), gz = T(0);
       // I_{n+1}^{m-1} at m = 0 is I_{n+1}^{-1} = -conj(I_{n+1}^1)
       auto ir = [&](int nn, int m) { return m >= 0 ? re[tri(nn, m)] : -re[tri(nn, 1)]; };
       auto ii = [&](int nn, int m) { return m >= 0 ? im[tri(nn, m)] : im[tri(nn, 1)]; };
-#pragma unroll
+  #pragma unroll
       for (int nn = 0; nn <= P; ++nn) {
-#pragma unroll
+  #pragma unroll
         for (int m = 0; m <= nn; ++m) {
-          const T mr = (T)Mw[cidx_re(nn, m)];
-          const T mi = m ? (T)Mw[cidx_im(nn, m)] : T(0);
+          const T mr = Mw[cidx_re(nn, m)];
+          const T mi = m ? Mw[cidx_im(nn, m)] : T(0);
           const T wgt = m ? T(2) : T(1);  // the negative orders are the conjugates
           // Re(M I_n^m)
           f += wgt * (mr * re[tri(nn, m)] - mi * im[tri(nn, m)]);
@@ -541,11 +562,13 @@ __global__ __launch_bounds__(kBlock) void k_l2p_m2p(ATree t, const uint32_t* __r
       g[1] += inv_hw * inv_hw * (double)gy;
       g[2] += inv_hw * inv_hw * (double)gz;
     }
+    if (active) {
+      far_phi[s] += phi;
+      far_grad[s] += g[0];
+      far_grad[n + s] += g[1];
+      far_grad[2 * n + s] += g[2];
+    }
   }
-  far_phi[s] = phi;
-  far_grad[s] = g[0];
-  far_grad[n + s] = g[1];
-  far_grad[2 * n + s] = g[2];
 }
 
 ATree tree_view(fmm_plan_s* P) {
@@ -590,15 +613,16 @@ struct P2LRun {
   static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
     const Layout& lay = Pl->lay;
     const ATree t = tree_view(Pl);
-    const int64_t nb = t.nbox - t.ce_off[2];
     const uint32_t* xoff = wsp<uint32_t>(Pl, lay.a_off) + 2 * (lay.bmax + 1);
-    if (nb <= 0 || Pl->nlist[2] == 0) return hipGetLastError();
+    if (Pl->nxbox == 0) return hipGetLastError();
+    const int64_t nx = Pl->nxbox;  // one thread per box with an X list
+    const uint32_t* xbox = wsp<uint32_t>(Pl, lay.a_xbox);
     if (Pl->mixed)
-      k_p2l<P, float><<<grid_for(nb, 64), 64, 0, s>>>(t, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
+      k_p2l<P, float><<<grid_for(nx, 64), 64, 0, s>>>(t, xbox, nx, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
                                                       wsp<Rec<float>>(Pl, lay.src),
                                                       wsp<float>(Pl, lay.m2l_out));
     else
-      k_p2l<P, double><<<grid_for(nb, 64), 64, 0, s>>>(t, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
+      k_p2l<P, double><<<grid_for(nx, 64), 64, 0, s>>>(t, xbox, nx, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
                                                        wsp<Rec<double>>(Pl, lay.src),
                                                        wsp<double>(Pl, lay.m2l_out));
     return hipGetLastError();
@@ -606,23 +630,24 @@ struct P2LRun {
 };
 
 template <int P>
-struct L2PM2PRun {
+struct M2PRun {
   static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
     const Layout& lay = Pl->lay;
+    if (Pl->nlist[1] == 0) return hipGetLastError();
     const ATree t = tree_view(Pl);
     const uint32_t* woff = wsp<uint32_t>(Pl, lay.a_off) + (lay.bmax + 1);
     const int64_t n = Pl->n;
     const DevParams* dp = wsp<DevParams>(Pl, lay.params);
+    const unsigned nb = (unsigned)Pl->nwbox;  // one wave per leaf with a W list
+    const uint32_t* wbox = wsp<uint32_t>(Pl, lay.a_wbox);
     if (Pl->mixed)
-      k_l2p_m2p<P, float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
-          t, wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<float>>(Pl, lay.src), n, dp,
-          wsp<double>(Pl, lay.loc_exp64), wsp<double>(Pl, lay.mult64), woff,
-          wsp<uint32_t>(Pl, lay.a_widx), wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
+      k_m2p<P, float><<<nb, 64, 0, s>>>(t, wbox, wsp<Rec<float>>(Pl, lay.src), n, dp,
+                                        wsp<float>(Pl, lay.mult32), woff, wsp<uint32_t>(Pl, lay.a_widx),
+                                        wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
     else
-      k_l2p_m2p<P, double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
-          t, wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<double>>(Pl, lay.src), n, dp,
-          wsp<double>(Pl, lay.loc_exp64), wsp<double>(Pl, lay.mult64), woff,
-          wsp<uint32_t>(Pl, lay.a_widx), wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
+      k_m2p<P, double><<<nb, 64, 0, s>>>(t, wbox, wsp<Rec<double>>(Pl, lay.src), n, dp,
+                                         wsp<double>(Pl, lay.mult64), woff, wsp<uint32_t>(Pl, lay.a_widx),
+                                         wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
     return hipGetLastError();
   }
 };
@@ -660,6 +685,30 @@ hipError_t launch_adaptive_tree(fmm_plan_s* P, const double* d_pos, hipStream_t 
   k_compact<<<grid_for(nd, kBlock), kBlock, 0, s>>>(
       t, nd, wsp<uint32_t>(P, lay.a_slot), wsp<int32_t>(P, lay.a_level), wsp<uint32_t>(P, lay.a_coord),
       wsp<uint32_t>(P, lay.a_range), wsp<int32_t>(P, lay.a_child0), wsp<uint32_t>(P, lay.a_parent_of));
+  {  // M2L targets per class and their source rows, level by level
+    VLevels v = {};
+    int64_t to = 0, vo = 0;
+    for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) {
+      P->a_tgt_off[l] = v.tgt_off[l] = to;
+      P->a_vt_off[l] = v.vt_off[l] = vo;
+      v.ndiv[l] = l >= 1 ? P->nsplit[l - 1] : 0;  // l - 1 <= FMM_DEPTH_MAX
+      if (l >= 2 && l <= P->Ld) {
+        to += 8 * v.ndiv[l];
+        vo += ((v.ndiv[l] + m2l::kTargetsPerGroup - 1) / m2l::kTargetsPerGroup) * m2l::kTargetsPerGroup *
+              8 * kIL;
+      }
+    }
+    if (to > lay.bmax || vo > lay.vtcap) return hipErrorInvalidValue;  // cannot happen (bounds)
+    uint32_t* tgt = wsp<uint32_t>(P, lay.a_tgt);
+    const int64_t nb2 = t.nbox - t.ce_off[2];
+    if (nb2 > 0) k_m2l_targets<<<grid_for(nb2, kBlock), kBlock, 0, s>>>(t, v, tgt);
+    for (int l = 2; l <= P->Ld; ++l) {
+      const int64_t nent = P->a_vt_off[l + 1] - P->a_vt_off[l];
+      if (nent > 0)
+        k_m2l_sources<<<grid_for(nent, kBlock), kBlock, 0, s>>>(t, v, l, nent, tgt,
+                                                                 wsp<uint32_t>(P, lay.a_vtab));
+    }
+  }
   const DevParams* dp = wsp<DevParams>(P, lay.params);
   if (P->mixed)
     k_gather_adaptive<float><<<grid_for(P->n, kBlock), kBlock, 0, s>>>(
@@ -680,14 +729,27 @@ hipError_t launch_adaptive_tree(fmm_plan_s* P, const double* d_pos, hipStream_t 
     e = scan_exclusive(cnt + k * nb1, nbox, nbox + 1, off + k * nb1, tmp, s);
     if (e != hipSuccess) return e;
   }
-  uint32_t tot[3];
-  for (int k = 0; k < 3; ++k) {
-    e = hipMemcpyAsync(&tot[k], off + k * nb1 + nbox, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+  // compact lists of the boxes with a W (list 1) or X (list 2) list
+  uint32_t* flag = wsp<uint32_t>(P, lay.a_flag);
+  uint32_t* fscan = wsp<uint32_t>(P, lay.a_fscan);
+  for (int k = 1; k <= 2; ++k) {
+    k_flag_nonzero<<<grid_for(nbox, kBlock), kBlock, 0, s>>>(cnt + k * nb1, nbox, flag);
+    e = scan_exclusive(flag, nbox, nbox + 1, fscan + (k - 1) * nb1, tmp, s);
+    if (e != hipSuccess) return e;
+    k_compact_nonzero<<<grid_for(nbox, kBlock), kBlock, 0, s>>>(
+        cnt + k * nb1, fscan + (k - 1) * nb1, nbox, wsp<uint32_t>(P, k == 1 ? lay.a_wbox : lay.a_xbox));
+  }
+  uint32_t tot[5];
+  for (int k = 0; k < 5; ++k) {
+    const uint32_t* at = k < 3 ? off + k * nb1 + nbox : fscan + (k - 3) * nb1 + nbox;
+    e = hipMemcpyAsync(&tot[k], at, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
   }
   e = hipStreamSynchronize(s);
   if (e != hipSuccess) return e;
   for (int k = 0; k < 3; ++k) P->nlist[k] = tot[k];
+  P->nwbox = tot[3];
+  P->nxbox = tot[4];
   if (P->nlist[0] > lay.ucap || P->nlist[1] > lay.wcap || P->nlist[2] > lay.xcap) {
     prof_end(P, s);
     return hipSuccess;  // the caller reports FMM_E_WORKSPACE
@@ -725,7 +787,8 @@ hipError_t launch_adaptive_downward(fmm_plan_s* P, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   prof_begin(P, FMM_PHASE_L2P, s);
-  e = dispatch_p<L2PM2PRun>(P->p, P, s);
+  e = launch_l2p_adaptive(P, s);
+  if (e == hipSuccess) e = dispatch_p<M2PRun>(P->p, P, s);
   prof_end(P, s);
   return e;
 }

@@ -14,9 +14,12 @@
 namespace fmm {
 namespace {
 
+// level: adaptive tree, the level of each (compact) leaf row, whose local
+// expansion is zero above level 2; null: every leaf is of level L.
 template <int P, typename T>
 __global__ __launch_bounds__(kBlock) void k_l2p(const uint32_t* __restrict__ sorted_leaf,
                                                 const Rec<T>* __restrict__ src, int64_t n, int L,
+                                                const int32_t* __restrict__ level,
                                                 const DevParams* __restrict__ dp,
                                                 const T* __restrict__ leafloc,
                                                 double* __restrict__ far_phi,
@@ -25,7 +28,16 @@ __global__ __launch_bounds__(kBlock) void k_l2p(const uint32_t* __restrict__ sor
   constexpr int NT = (P + 1) * (P + 2) / 2;
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  const T* Lc = leafloc + (int64_t)sorted_leaf[s] * MS;
+  const uint32_t leaf = sorted_leaf[s];
+  if (level) {
+    L = level[leaf];
+    if (L < 2) {
+      far_phi[s] = 0.0;
+      far_grad[s] = far_grad[n + s] = far_grad[2 * n + s] = 0.0;
+      return;
+    }
+  }
+  const T* Lc = leafloc + (int64_t)leaf * MS;
   T re[NT], im[NT];
   const Rec<T> r = src[s];
   regular_harmonics<P, T>(r.x, r.y, r.z, re, im);
@@ -80,12 +92,12 @@ struct L2PRun {
     const DevParams* dp = wsp<DevParams>(Pl, lay.params);
     if (Pl->mixed)
       k_l2p<P, float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
-          wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<float>>(Pl, lay.src), n, Pl->L, dp,
+          wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<float>>(Pl, lay.src), n, Pl->L, nullptr, dp,
           wsp<float>(Pl, lay.leaf_loc32), wsp<double>(Pl, lay.far_phi),
           wsp<double>(Pl, lay.far_grad));
     else
       k_l2p<P, double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
-          wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<double>>(Pl, lay.src), n, Pl->L, dp,
+          wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<double>>(Pl, lay.src), n, Pl->L, nullptr, dp,
           wsp<double>(Pl, lay.loc_exp64) + lay.lvl_off[Pl->L] * mstride(Pl->p),
           wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
     return hipGetLastError();
@@ -93,6 +105,29 @@ struct L2PRun {
 };
 
 }  // namespace
+
+// Adaptive tree: L2P at every particle from its leaf's local expansion
+// (FP32 copy in the mixed mode), zero above level 2.
+template <int P>
+struct L2PAdaptiveRun {
+  static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {
+    const Layout& lay = Pl->lay;
+    const int64_t n = Pl->n;
+    const DevParams* dp = wsp<DevParams>(Pl, lay.params);
+    const int32_t* lev = wsp<int32_t>(Pl, lay.a_level);
+    if (Pl->mixed)
+      k_l2p<P, float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
+          wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<float>>(Pl, lay.src), n, Pl->L, lev, dp,
+          wsp<float>(Pl, lay.leaf_loc32), wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
+    else
+      k_l2p<P, double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
+          wsp<uint32_t>(Pl, lay.sorted_leaf), wsp<Rec<double>>(Pl, lay.src), n, Pl->L, lev, dp,
+          wsp<double>(Pl, lay.loc_exp64), wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
+    return hipGetLastError();
+  }
+};
+
+hipError_t launch_l2p_adaptive(fmm_plan_s* P, hipStream_t s) { return dispatch_p<L2PAdaptiveRun>(P->p, P, s); }
 
 hipError_t launch_downward(fmm_plan_s* P, hipStream_t s) {
   if (P->adaptive) return launch_adaptive_downward(P, s);

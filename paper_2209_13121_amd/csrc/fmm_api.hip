@@ -52,6 +52,9 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     lay->ucap = 40 * lay->bmax;
     lay->wcap = 16 * lay->bmax;
     lay->xcap = 16 * lay->bmax;
+    // M2L source table: 8 x 189 entries per divided parent, tiles of 128
+    // padded, at most L + 1 partly filled tiles per class
+    lay->vtcap = ((lay->bmax + 7) / 8 + 128 * (int64_t)(L + 1)) * 8 * kIL;
   }
   lay->nbox_exp = adaptive ? lay->bmax : lay->nbox;
   // scan scratch: block sums of every level of the recursive scan, for the
@@ -101,7 +104,8 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     lay->mult32 = mixed ? take(sizeof(float) * NB * ms) : 0;
     lay->m2l_out = take((mixed ? sizeof(float) : sizeof(double)) * NB * nce);
     lay->loc_exp64 = take(sizeof(double) * NB * ms);
-    lay->leaf_loc32 = (mixed && !adaptive) ? take(sizeof(float) * NL * ms) : 0;
+    // mixed: FP32 leaf locals for L2P (adaptive: a copy of every box's local)
+    lay->leaf_loc32 = mixed ? take(sizeof(float) * (adaptive ? NB : NL) * ms) : 0;
     const size_t tile = (size_t)shift_kpad(nc) * m2l_rows_pad(p);
     lay->op_m2m = take(sizeof(double) * 8 * tile);
     lay->op_l2l = take(sizeof(double) * 8 * tile);
@@ -139,6 +143,12 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     lay->a_uidx = take(sizeof(uint32_t) * (size_t)lay->ucap);
     lay->a_widx = take(sizeof(uint32_t) * (size_t)lay->wcap);
     lay->a_xidx = take(sizeof(uint32_t) * (size_t)lay->xcap);
+    lay->a_wbox = take(sizeof(uint32_t) * BM);
+    lay->a_xbox = take(sizeof(uint32_t) * BM);
+    lay->a_flag = take(sizeof(uint32_t) * (BM + 1));
+    lay->a_fscan = take(sizeof(uint32_t) * 2 * (BM + 1));
+    lay->a_tgt = take(sizeof(uint32_t) * BM);
+    lay->a_vtab = take(sizeof(uint32_t) * (size_t)lay->vtcap);
     lay->a_small = take(sizeof(uint32_t) * 64);
     lay->a_stats = take(sizeof(int64_t) * 8);
   }

@@ -116,9 +116,13 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t a_parent_of;      // at child0: the parent's index within its level
   size_t a_cnt, a_off;     // list sizes and offsets: 3 lists (U, W, X) x (bmax + 1)
   size_t a_uidx, a_widx, a_xidx;  // list entries (compact box indices)
+  size_t a_wbox, a_xbox;   // compact lists of the boxes whose W / X list is not empty
+  size_t a_flag, a_fscan;  // scratch of the compaction (bmax + 1 each)
+  size_t a_tgt;            // M2L targets per level and parity class (rows within the level)
+  size_t a_vtab;           // M2L source rows per (tile, class, offset, target); vtcap entries
   size_t a_small;          // per-level offsets and totals read back by the host
   size_t a_stats;          // 8 x int64 counters of the tree statistics
-  int64_t bmax, ucap, wcap, xcap, nbox_exp;  // bounds; nbox_exp = rows of the expansion arrays
+  int64_t bmax, ucap, wcap, xcap, vtcap, nbox_exp;  // bounds; nbox_exp = rows of the expansion arrays
   size_t total;
   int64_t n, nleaf, nbox, n_energy_part, scan_tmp_elems;
   int64_t lvl_off[FMM_DEPTH_MAX + 2];
@@ -150,6 +154,9 @@ struct fmm_plan_s {
   int64_t ce_off[FMM_DEPTH_MAX + 2];  // compact index of the first box of each level
   int64_t nsplit[FMM_DEPTH_MAX + 1];  // divided boxes per level
   int64_t nlist[3];                   // U, W, X entries
+  int64_t nwbox, nxbox;               // boxes with a non-empty W / X list
+  int64_t a_tgt_off[FMM_DEPTH_MAX + 2];  // M2L target lists per level (entries)
+  int64_t a_vt_off[FMM_DEPTH_MAX + 2];   // M2L source tables per level (entries)
   char* ws;
   hipStream_t last_stream;
   bool has_charges;  // fmm_evaluate has run: sorted charges are in the workspace
@@ -195,6 +202,7 @@ hipError_t launch_adaptive_upward(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_adaptive_p2l(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_adaptive_downward(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_adaptive_stats(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_l2p_adaptive(fmm_plan_s* P, hipStream_t s);  // downward.hip
 // M2M / L2L over the divided boxes of the adaptive tree (shift.hip)
 hipError_t launch_m2m_adaptive(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_l2l_adaptive(fmm_plan_s* P, hipStream_t s);

@@ -205,7 +205,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restri
     }
   };
   typedef m2l::Src Src;
-  auto lookup = [&](int dx, int dy, int dz) -> Src { return tl.lookup(sSlot, dx, dy, dz); };
+  auto lookup = [&](int k, int dx, int dy, int dz) -> Src { return tl.lookup(sSlot, k, dx, dy, dz); };
   // Source row of a lookup: the zero row outside the domain.
   auto row_of = [&](Src src) -> const T* {
     return src.ok ? mlev + (int64_t)src.slot * MS : zero_row;
@@ -262,8 +262,8 @@ __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restri
   int i = 0, dx, dy, dz, ndx, ndy, ndz;
   int op = offset_of(0, dx, dy, dz);
   int nop = offset_of(1, ndx, ndy, ndz);
-  Src s_cur = lookup(dx, dy, dz);
-  Src s_next = lookup(ndx, ndy, ndz);
+  Src s_cur = lookup(0, dx, dy, dz);
+  Src s_next = lookup(1, ndx, ndy, ndz);
   bool wave_any = false;
   if (PB) {
     load_b(row_of(s_cur), b0);
@@ -281,8 +281,9 @@ __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restri
   auto do_offset = [&](vec_t* bc, vec_t* bn) -> bool {
     const bool more = i + 1 < kIL;
     int fdx, fdy, fdz;
-    const int fop = offset_of(i + 2 < kIL ? i + 2 : kIL - 1, fdx, fdy, fdz);
-    const Src s_far = lookup(fdx, fdy, fdz);  // offset i + 2 (clamped at the end)
+    const int fi = i + 2 < kIL ? i + 2 : kIL - 1;
+    const int fop = offset_of(fi, fdx, fdy, fdz);
+    const Src s_far = lookup(fi, fdx, fdy, fdz);  // offset i + 2 (clamped at the end)
     if (!PB) {
       load_b(row_of(s_cur), bc);
       wave_any = __any(s_cur.ok);
@@ -374,8 +375,9 @@ struct M2LRun {
 }  // namespace
 
 hipError_t launch_m2l(fmm_plan_s* P, hipStream_t s) {
+  if (P->m2l_np) return launch_m2l_bf16(P, s);  // times its split and M2L kernels apart
   prof_begin(P, FMM_PHASE_M2L, s);
-  hipError_t e = P->m2l_np ? launch_m2l_bf16(P, s) : dispatch_p<M2LRun>(P->p, P, s);
+  hipError_t e = dispatch_p<M2LRun>(P->p, P, s);
   prof_end(P, s);
   return e;
 }

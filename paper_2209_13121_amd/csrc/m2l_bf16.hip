@@ -260,8 +260,8 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   int i = 0, dx, dy, dz, ndx, ndy, ndz;
   int op = m2l::il_offset(pi, 0, dx, dy, dz);
   int nop = m2l::il_offset(pi, 1, ndx, ndy, ndz);
-  m2l::Src s_cur = tl.lookup(sSlot, dx, dy, dz);
-  m2l::Src s_next = tl.lookup(sSlot, ndx, ndy, ndz);
+  m2l::Src s_cur = tl.lookup(sSlot, 0, dx, dy, dz);
+  m2l::Src s_next = tl.lookup(sSlot, 1, ndx, ndy, ndz);
   bool wave_any = false;
   float sc_cur = scale_of(s_cur), sc_next = 0.f;
   if (PB) {
@@ -276,8 +276,9 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   auto do_offset = [&](u32x4* bc, u32x4* bn) -> bool {
     const bool more = i + 1 < kIL;
     int fdx, fdy, fdz;
-    const int fop = m2l::il_offset(pi, i + 2 < kIL ? i + 2 : kIL - 1, fdx, fdy, fdz);
-    const m2l::Src s_far = tl.lookup(sSlot, fdx, fdy, fdz);
+    const int fi = i + 2 < kIL ? i + 2 : kIL - 1;
+    const int fop = m2l::il_offset(pi, fi, fdx, fdy, fdz);
+    const m2l::Src s_far = tl.lookup(sSlot, fi, fdx, fdy, fdz);
     if (!PB) {
       load_b(row_of(s_cur), bc);
       wave_any = __any(s_cur.ok);
@@ -373,13 +374,17 @@ struct M2LBfRun {
     const int64_t box0 = exp_box0(Pl), nbox = exp_nbox(Pl) - box0;
     u32x4* mq = wsp<u32x4>(Pl, lay.multb);
     const int qr = m2lb_row_quads(nc, NP);
+    prof_begin(Pl, FMM_PHASE_SPLIT, s);
     k_split_mult<NP><<<grid_for(nbox * kst * 4, kBlock), kBlock, 0, s>>>(
         wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox,
         mq + box0 * qr);
+    prof_end(Pl, s);
     const m2l::Args a = m2l::make_args(Pl);
+    prof_begin(Pl, FMM_PHASE_M2L, s);
     k_m2l_bf<P, NP, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
         a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
         nullptr, nullptr);
+    prof_end(Pl, s);
     return hipGetLastError();
   }
   static hipError_t go_f16(fmm_plan_s* Pl, hipStream_t s) {
@@ -390,13 +395,17 @@ struct M2LBfRun {
     const int qr = m2lb_row_quads(nc, 2);
     float* msc = wsp<float>(Pl, lay.f16_mscale);
     const int lpb = 4 * kst <= 16 ? 16 : 32;
+    prof_begin(Pl, FMM_PHASE_SPLIT, s);
     k_split_mult_h<<<grid_for(nbox * lpb, kBlock), kBlock, 0, s>>>(
         wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox, lpb,
         wsp<float>(Pl, lay.f16_colf), mq + box0 * qr, msc + box0);
+    prof_end(Pl, s);
     const m2l::Args a = m2l::make_args(Pl);
+    prof_begin(Pl, FMM_PHASE_M2L, s);
     k_m2l_bf<P, 2, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
         a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
         msc, wsp<float>(Pl, lay.f16_rowf));
+    prof_end(Pl, s);
     return hipGetLastError();
   }
   static hipError_t run(fmm_plan_s* Pl, hipStream_t s) {

@@ -63,10 +63,20 @@ struct Args {
   int64_t ngroups;
   const uint32_t* c2s;
   const uint32_t* s2c;
-  // Adaptive tree only (null for the uniform one): per dense box, whether it
-  // exists and its row in the expansion arrays.
+  // Adaptive tree only (null for the uniform one).  The targets of level l
+  // and class pi are the class-pi children of the level's divided parents,
+  // ndiv[l] of them, rows tgt[tgt_off[l] + pi ndiv[l] + k] of the level; a
+  // work-group owns 128 of them (tile t) and reads the row of each target's
+  // source at offset i of its class from
+  // vtab[vt_off[l] + ((t * 8 + pi) * kIL + i) * 128 + target] (kAbsent where
+  // the tree has no such box, and for the padding of the last tile).
   const uint32_t* present;
   const uint32_t* row;
+  const uint32_t* tgt;
+  const uint32_t* vtab;
+  int64_t ndiv[FMM_DEPTH_MAX + 2];
+  int64_t tgt_off[FMM_DEPTH_MAX + 2];
+  int64_t vt_off[FMM_DEPTH_MAX + 2];
 };
 
 inline Args make_args(fmm_plan_s* Pl) {
@@ -80,7 +90,7 @@ inline Args make_args(fmm_plan_s* Pl) {
   int64_t g = 0;
   for (int l = 2; l <= a.L; ++l) {
     a.group_off[l] = g;
-    const int64_t np = (int64_t)1 << (3 * (l - 1));
+    const int64_t np = Pl->adaptive ? Pl->nsplit[l - 1] : (int64_t)1 << (3 * (l - 1));
     g += 8 * ((np + kTargetsPerGroup - 1) / kTargetsPerGroup);
   }
   a.group_off[a.L + 1] = g;
@@ -89,6 +99,13 @@ inline Args make_args(fmm_plan_s* Pl) {
   a.s2c = wsp<uint32_t>(Pl, lay.slot2coord);
   a.present = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_present) : nullptr;
   a.row = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_scan) : nullptr;
+  a.tgt = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_tgt) : nullptr;
+  a.vtab = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_vtab) : nullptr;
+  for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) {
+    a.ndiv[l] = Pl->adaptive && l >= 1 ? Pl->nsplit[l - 1] : 0;
+    a.tgt_off[l] = Pl->a_tgt_off[l];
+    a.vt_off[l] = Pl->a_vt_off[l];
+  }
   return a;
 }
 inline unsigned grid_of(const Args& a) { return (unsigned)(((a.ngroups + 7) / 8) * 8); }
@@ -115,6 +132,8 @@ struct Tile {
   int hx0, hy0, hz0, hx1, hy1, hz1, hey, hez;  // halo box (clamped to the level)
   int64_t lvl_off;                             // first row of level l in the expansion arrays
   int64_t dense_off;                           // first box of level l in the dense tables
+  const uint32_t* vt;                          // adaptive: this lane's source-row column
+  int64_t trow;                                // adaptive: this lane's target row
 
   // Decode the group, find this lane's target (number tix of the tile's 128)
   // and stage the halo's rows in sSlot (kAbsent where the adaptive tree has no
@@ -128,6 +147,18 @@ struct Tile {
     if (lg >= a.ngroups) return false;
     l = 2;
     while (l < a.L && lg >= a.group_off[l + 1]) ++l;
+    vt = nullptr;
+    if (a.vtab) {  // adaptive: no halo, the source rows come from the table
+      const int64_t idx = lg - a.group_off[l];
+      pi = (int)(idx % 8);
+      const int64_t tile = idx / 8;
+      const int64_t ps = tile * kTargetsPerGroup + tix;
+      col_ok = ps < a.ndiv[l];
+      trow = col_ok ? (int64_t)a.tgt[a.tgt_off[l] + pi * a.ndiv[l] + ps] : 0;
+      lvl_off = a.exp_off[l];
+      vt = a.vtab + a.vt_off[l] + (tile * 8 + pi) * (int64_t)kIL * kTargetsPerGroup + tix;
+      return true;
+    }
     const int64_t np = (int64_t)1 << (3 * (l - 1));  // parents at level l-1
     // The 8 parity classes of a tile are consecutive groups, so they run close
     // together on one XCD and share its L2 for the tile's sources.
@@ -185,10 +216,15 @@ struct Tile {
     return true;
   }
 
-  // This lane's source for offset (dx, dy, dz): its slot, read from the
-  // staged halo at coordinates clamped into it (so the read is
-  // unconditional), and whether it lies in the domain.
-  __device__ __forceinline__ Src lookup(const uint32_t* sSlot, int dx, int dy, int dz) const {
+  // This lane's source for offset k = (dx, dy, dz) of its class: its row,
+  // read from the staged halo at coordinates clamped into it (so the read is
+  // unconditional) or, on the adaptive tree, from the source table; and
+  // whether the source exists.
+  __device__ __forceinline__ Src lookup(const uint32_t* sSlot, int k, int dx, int dy, int dz) const {
+    if (vt) {
+      const uint32_t v = vt[(int64_t)k * kTargetsPerGroup];
+      return Src{v & ~kAbsent, !(v & kAbsent)};
+    }
     int sx = tx - dx, sy = ty - dy, sz = tz - dz;
     const bool ok = col_ok && sx >= 0 && sy >= 0 && sz >= 0 && sx < nb && sy < nb && sz < nb;
     sx = sx < hx0 ? hx0 : (sx > hx1 ? hx1 : sx);
@@ -200,6 +236,7 @@ struct Tile {
 
   // Row of this lane's target within its level (col_ok only).
   __device__ __forceinline__ int64_t target_slot(const Args& a) const {
+    if (vt) return trow;
     const uint32_t slot = a.c2s[dense_off + lex_index(tx, ty, tz, l)];
     return a.present ? (int64_t)a.row[dense_off + slot] - lvl_off : (int64_t)slot;
   }

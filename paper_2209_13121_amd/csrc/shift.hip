@@ -213,13 +213,15 @@ __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
       if (rr + j < NC)
         v[j] += inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + rr + j]
                                  : static_cast<const double*>(a.m2l)[cs * NC + rr + j]);
-    if (a.leaf && a.mixed) {
-      *reinterpret_cast<f32x4*>(a.dst32 + cs * MS + rr) =
-          f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
-    } else {
+    // uniform leaf level (mixed): FP32 only; otherwise FP64, plus an FP32 copy
+    // where dst32 is given (adaptive, mixed: every level holds leaves)
+    if (!(a.leaf && a.mixed)) {
       *reinterpret_cast<f64x2*>(a.dst64 + cs * MS + rr) = f64x2{v[0], v[1]};
       *reinterpret_cast<f64x2*>(a.dst64 + cs * MS + rr + 2) = f64x2{v[2], v[3]};
     }
+    if (a.dst32)
+      *reinterpret_cast<f32x4*>(a.dst32 + cs * MS + rr) =
+          f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
   }
 }
 
@@ -238,7 +240,8 @@ struct ShiftRun {
   }
 };
 
-// Level 2 locals: L~ = (1/h) * M2L result (no parent contribution).
+// Level 2 locals: L~ = (1/h) * M2L result (no parent contribution), into
+// dst64 and / or dst32 (whichever is given).
 template <typename TM>
 __global__ void k_l2l_top(int nc, int ms, int l, int64_t nbox, const DevParams* __restrict__ dp,
                           const TM* __restrict__ m2l, double* __restrict__ dst64,
@@ -248,10 +251,8 @@ __global__ void k_l2l_top(int nc, int ms, int l, int64_t nbox, const DevParams* 
   const int64_t b = e / ms;
   const int row = (int)(e % ms);
   const double v = row < nc ? (double)(1 << l) / dp->side * (double)m2l[b * nc + row] : 0.0;
-  if (dst32)
-    dst32[e] = (float)v;
-  else
-    dst64[e] = v;
+  if (dst32) dst32[e] = (float)v;
+  if (dst64) dst64[e] = v;
 }
 
 }  // namespace
@@ -290,7 +291,7 @@ hipError_t launch_l2l(fmm_plan_s* P, hipStream_t s) {
     if (P->mixed)
       k_l2l_top<float><<<grid_for(nb * ms, kBlock), kBlock, 0, s>>>(
           nc, ms, 2, nb, dp, wsp<float>(P, lay.m2l_out) + lay.lvl_off[2] * nc,
-          l64 + lay.lvl_off[2] * ms, d32);
+          d32 ? nullptr : l64 + lay.lvl_off[2] * ms, d32);
     else
       k_l2l_top<double><<<grid_for(nb * ms, kBlock), kBlock, 0, s>>>(
           nc, ms, 2, nb, dp, wsp<double>(P, lay.m2l_out) + lay.lvl_off[2] * nc,
@@ -354,7 +355,7 @@ hipError_t launch_l2l_adaptive(fmm_plan_s* P, hipStream_t s) {
     if (P->mixed)
       k_l2l_top<float><<<grid_for(nb2 * ms, kBlock), kBlock, 0, s>>>(
           nc, ms, 2, nb2, dp, wsp<float>(P, lay.m2l_out) + P->ce_off[2] * nc,
-          l64 + P->ce_off[2] * ms, nullptr);
+          l64 + P->ce_off[2] * ms, wsp<float>(P, lay.leaf_loc32) + P->ce_off[2] * ms);
     else
       k_l2l_top<double><<<grid_for(nb2 * ms, kBlock), kBlock, 0, s>>>(
           nc, ms, 2, nb2, dp, wsp<double>(P, lay.m2l_out) + P->ce_off[2] * nc,
@@ -372,7 +373,7 @@ hipError_t launch_l2l_adaptive(fmm_plan_s* P, hipStream_t s) {
     a.ops = wsp<double>(P, lay.op_l2l);
     a.src = l64 + P->ce_off[l - 1] * ms;
     a.dst64 = l64 + P->ce_off[l] * ms;
-    a.dst32 = nullptr;
+    a.dst32 = P->mixed ? wsp<float>(P, lay.leaf_loc32) + P->ce_off[l] * ms : nullptr;
     a.m2l = P->mixed ? (const void*)(wsp<float>(P, lay.m2l_out) + P->ce_off[l] * nc)
                      : (const void*)(wsp<double>(P, lay.m2l_out) + P->ce_off[l] * nc);
     a.dp = dp;

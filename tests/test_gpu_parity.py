@@ -292,3 +292,22 @@ def test_work_counts():
             pd = np.abs(boxes // 2 - t // 2).max(axis=1)
             exp_m2l += int(((d > 1) & (pd <= 1)).sum())
     assert m2l == exp_m2l
+
+
+def test_profile_phases():
+    # The M2L phase times the M2L kernel alone (once per evaluation); the
+    # split forms record their multipole split as a phase of its own.
+    import torch
+    pos, q = W.uniform_gauss(20000, 41)
+    dev = torch.device("cuda:0")
+    tp, tq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
+    for prec, kind, split in ((B.FMM_PREC_MIXED, B.FMM_M2L_F16X2, 1), (B.FMM_PREC_MIXED, B.FMM_M2L_F32, 0),
+                              (B.FMM_PREC_FP64, B.FMM_M2L_AUTO, 0)):
+        f = B.FMM(tp, p=6, depth=4, precision=prec, m2l_kind=kind)
+        B.fmm_profile_enable(f.plan, True)
+        f.evaluate(tq)
+        rec = B.fmm_profile_read(f.plan)
+        assert rec["m2l"][1] == 1 and rec["m2l"][0] > 0
+        assert rec["split"][1] == split
+        assert rec["p2p"][1] == 1 and rec["p2m"][1] == 1
+        f.close()
