@@ -269,14 +269,14 @@ def adaptive_bench(B, torch, args, stream):
            "value": m["value"], "ms_per_step": m["ms_per_step"], "tree": stats, "accuracy": acc,
            "variants": res}
     if not args.no_cpu_baseline:
-        sample = W.molecular_clusters(30_000, wl.seed)[:2]
+        sample = W.molecular_clusters(300_000, wl.seed)[:2]
         t0 = time.perf_counter()
         oracle.fmm_adaptive(sample[0], sample[1], wl.leaf_max, wl.max_depth, wl.p, side=0.0)
         dt = time.perf_counter() - t0
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"] = {"value": len(sample[1]) / dt, "unit": "particles/s", "cores": threads,
                                "kind": "oracle",
-                               "sample": f"CPU FP64 oracle adaptive FMM on 3e4 clusters (9e4 sites) of the "
+                               "sample": f"CPU FP64 oracle adaptive FMM on 3e5 clusters (9e5 sites) of the "
                                          f"same recipe, leaf_max {wl.leaf_max}, p {wl.p}; {dt:.1f} s wall"}
     return out
 
