@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define FMM_ABI_VERSION 1
+#define FMM_ABI_VERSION 2
 #define FMM_P_MAX 12     /* largest expansion order */
 #define FMM_DEPTH_MAX 9  /* deepest uniform tree (8^9 leaves) */
 
@@ -115,6 +115,18 @@ typedef struct {
                            must contain every position (else FMM_E_OUT_OF_CUBE);
                            <= 0: derived on the device as lo_a = min_i x_ia,
                            side = max_a (max_i x_ia - lo_a), or 1 if that is 0 */
+  int32_t batch_level;  /* adaptive tree only: 0 for one system; b > 0: every box of
+                           level b is an independent system (a batch of systems,
+                           one per box of level b, e.g. each in its own cell of
+                           the root cube).  Boxes above level b that hold
+                           particles are always divided, and no pair of
+                           particles in different level-b boxes interacts: the
+                           result per system is that of a plan for the system
+                           alone with its level-b box as the root cube, and the
+                           energy is the sum over the systems.  0..depth, else
+                           FMM_E_INVALID_ARG; > 0 with leaf_max == 0:
+                           FMM_E_UNSUPPORTED. */
+  int32_t reserved;     /* must be 0 */
 } fmm_config;
 
 typedef struct fmm_plan_s fmm_plan_t; /* opaque */

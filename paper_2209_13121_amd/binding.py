@@ -33,7 +33,8 @@ class fmm_config(ctypes.Structure):
     _fields_ = [("abi_version", ctypes.c_uint32), ("p", ctypes.c_int32), ("depth", ctypes.c_int32),
                 ("leaf_max", ctypes.c_int32), ("ws", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("m2l_kind", ctypes.c_int32),
-                ("root_lo", ctypes.c_double * 3), ("root_side", ctypes.c_double)]
+                ("root_lo", ctypes.c_double * 3), ("root_side", ctypes.c_double),
+                ("batch_level", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class FMMError(RuntimeError):
@@ -98,12 +99,14 @@ def _check(st, what):
 
 
 def make_config(p=8, depth=3, precision=FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
-                m2l_kind=FMM_M2L_AUTO, leaf_max=0):
-    """leaf_max > 0 asks for the adaptive tree, depth then being its depth cap."""
+                m2l_kind=FMM_M2L_AUTO, leaf_max=0, batch_level=0):
+    """leaf_max > 0 asks for the adaptive tree, depth then being its depth cap;
+    batch_level > 0 makes every box of that level an independent system."""
     cfg = fmm_config()
     load().fmm_config_default(ctypes.byref(cfg))
     cfg.p, cfg.depth, cfg.precision, cfg.m2l_kind = p, depth, precision, m2l_kind
     cfg.leaf_max = leaf_max
+    cfg.batch_level = batch_level
     for a in range(3):
         cfg.root_lo[a] = float(lo[a])
     cfg.root_side = float(side)
@@ -221,10 +224,10 @@ class FMM:
     """Owns a workspace and a plan for one position set (torch device tensors)."""
 
     def __init__(self, pos, p=8, depth=3, precision=FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
-                 stream=None, workspace=None, m2l_kind=FMM_M2L_AUTO, leaf_max=0):
+                 stream=None, workspace=None, m2l_kind=FMM_M2L_AUTO, leaf_max=0, batch_level=0):
         import torch
         self.n = pos.shape[0]
-        self.cfg = make_config(p, depth, precision, lo, side, m2l_kind, leaf_max)
+        self.cfg = make_config(p, depth, precision, lo, side, m2l_kind, leaf_max, batch_level)
         nbytes = fmm_workspace_size(self.cfg, self.n)
         if workspace is None or workspace.numel() < nbytes:
             workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=pos.device)

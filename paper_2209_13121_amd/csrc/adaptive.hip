@@ -43,6 +43,7 @@ namespace {
 struct ATree {
   int L;         // depth cap
   int leaf_max;
+  int l0;        // batch level: boxes of level l0 are independent systems (0: one system)
   int64_t nbox;  // existing boxes
   int64_t ls;    // stride of the three lists' count and offset arrays
   int64_t lvl_off[FMM_DEPTH_MAX + 2];  // dense level offsets
@@ -71,6 +72,22 @@ __device__ __forceinline__ int64_t find_box(const ATree& t, int l, int x, int y,
   return t.present[g] ? (int64_t)t.scan[g] : -1;
 }
 
+// A box of level l holding cnt particles is divided (cnt > leaf_max, or it lies
+// above the batch level and is not empty) unless l is the cap.
+__device__ __forceinline__ bool divided(const ATree& t, int l, uint32_t cnt) {
+  return l < t.L && (cnt > (uint32_t)t.leaf_max || (l < t.l0 && cnt > 0));
+}
+
+// Boxes a (level la) and b (level lb) belong to one system: always for a single
+// system; for a batch, both at or below the batch level with one ancestor there.
+__device__ __forceinline__ bool same_system(const ATree& t, int la, int ax, int ay, int az, int lb,
+                                            int bx, int by, int bz) {
+  if (t.l0 == 0) return true;
+  if (la < t.l0 || lb < t.l0) return false;
+  const int sa = la - t.l0, sb = lb - t.l0;
+  return (ax >> sa) == (bx >> sb) && (ay >> sa) == (by >> sb) && (az >> sa) == (bz >> sb);
+}
+
 // Closed cubes of box a (level la) and box b (level lb >= la) touch.
 __device__ __forceinline__ bool touches(int la, int ax, int ay, int az, int lb, int bx, int by, int bz) {
   const int s = lb - la;
@@ -88,7 +105,7 @@ __global__ void k_present(ATree t, int64_t nd, uint32_t* __restrict__ present) {
   const uint32_t slot = (uint32_t)(g - t.lvl_off[l]);
   uint32_t ok = 1;
   for (int m = 0; m < l && ok; ++m)
-    if (count_of(t.start, t.L, m, slot >> (3 * (l - m))) <= (uint32_t)t.leaf_max) ok = 0;
+    if (!divided(t, m, count_of(t.start, t.L, m, slot >> (3 * (l - m))))) ok = 0;
   present[g] = ok;
 }
 
@@ -113,9 +130,8 @@ __global__ void k_compact(ATree t, int64_t nd, uint32_t* __restrict__ slot_of,
   coord[c] = t.s2c[g];
   range[2 * c] = t.start[(uint64_t)slot << (3 * (t.L - l))];
   range[2 * c + 1] = cnt;
-  const bool divided = cnt > (uint32_t)t.leaf_max && l < t.L;
   int32_t ch = -1;
-  if (divided) {
+  if (divided(t, l, cnt)) {
     ch = (int32_t)t.scan[t.lvl_off[l + 1] + 8 * (int64_t)slot];
     parent_of[ch] = (uint32_t)(c - t.ce_off[l]);
   }
@@ -138,7 +154,7 @@ __global__ void k_gather_adaptive(ATree t, const double* __restrict__ pos,
   uint32_t slot = 0;
   for (; l <= t.L; ++l) {
     slot = key >> (3 * (t.L - l));
-    if (l == t.L || count_of(t.start, t.L, l, slot) <= (uint32_t)t.leaf_max) break;
+    if (!divided(t, l, count_of(t.start, t.L, l, slot))) break;
   }
   if (l > t.L) l = t.L;
   const int64_t g = t.lvl_off[l] + slot;
@@ -201,8 +217,10 @@ __global__ void k_m2l_sources(ATree t, VLevels v, int l, int64_t nent, const uin
     int x, y, z, dx, dy, dz;
     unpack_coord(t.coord[t.ce_off[l] + trow], x, y, z);
     m2l::il_offset(pi, i, dx, dy, dz);
-    const int64_t c = find_box(t, l, x - dx, y - dy, z - dz);
-    if (c >= 0) out = (uint32_t)(c - t.ce_off[l]);
+    if (same_system(t, l, x - dx, y - dy, z - dz, l, x, y, z)) {
+      const int64_t c = find_box(t, l, x - dx, y - dy, z - dz);
+      if (c >= 0) out = (uint32_t)(c - t.ce_off[l]);
+    }
   }
   vtab[v.vt_off[l] + e] = out;
 }
@@ -241,6 +259,7 @@ __global__ void k_lists(ATree t, uint32_t* __restrict__ cnt, const uint32_t* __r
       for (int x = x0; x <= x1; ++x)
         for (int y = y0; y <= y1; ++y)
           for (int z = z0; z <= z1; ++z) {
+            if (!same_system(t, m, x, y, z, l, bx, by, bz)) continue;
             const int64_t c = find_box(t, m, x, y, z);
             if (c < 0 || t.child0[c] >= 0 || !touches(m, x, y, z, l, bx, by, bz)) continue;
             if (FILL) pu[nu] = (uint32_t)c;
@@ -251,6 +270,7 @@ __global__ void k_lists(ATree t, uint32_t* __restrict__ cnt, const uint32_t* __r
     for (int dx = -1; dx <= 1; ++dx)
       for (int dy = -1; dy <= 1; ++dy)
         for (int dz = -1; dz <= 1; ++dz) {
+          if (!same_system(t, l, bx + dx, by + dy, bz + dz, l, bx, by, bz)) continue;
           const int64_t c = find_box(t, l, bx + dx, by + dy, bz + dz);
           if (c < 0) continue;
           if (t.child0[c] < 0) {
@@ -293,6 +313,7 @@ __global__ void k_lists(ATree t, uint32_t* __restrict__ cnt, const uint32_t* __r
       for (int x = x0; x <= x1; ++x)
         for (int y = y0; y <= y1; ++y)
           for (int z = z0; z <= z1; ++z) {
+            if (!same_system(t, m, x, y, z, l, bx, by, bz)) continue;
             const int64_t c = find_box(t, m, x, y, z);
             if (c < 0 || t.child0[c] >= 0 || touches(m, x, y, z, l, bx, by, bz)) continue;
             if (FILL) px[nx] = (uint32_t)c;
@@ -338,6 +359,7 @@ __global__ void k_stats(ATree t, const uint32_t* __restrict__ off, const uint32_
           if (abs((sx >> 1) - (x >> 1)) > 1 || abs((sy >> 1) - (y >> 1)) > 1 ||
               abs((sz >> 1) - (z >> 1)) > 1)
             continue;
+          if (!same_system(t, l, sx, sy, sz, l, x, y, z)) continue;
           const int64_t c = find_box(t, l, sx, sy, sz);
           if (c < 0) continue;
           ++v;
@@ -576,6 +598,7 @@ ATree tree_view(fmm_plan_s* P) {
   ATree t;
   t.L = P->L;
   t.leaf_max = P->cfg.leaf_max;
+  t.l0 = P->cfg.batch_level;
   t.nbox = P->ce_off[P->L + 1];
   t.ls = lay.bmax + 1;
   for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) {

@@ -201,6 +201,9 @@ static fmm_status validate_config(const fmm_config* cfg) {
   if (cfg->depth < 0 || cfg->depth > FMM_DEPTH_MAX) return FMM_E_INVALID_ARG;
   if (cfg->ws != 1) return FMM_E_INVALID_ARG;
   if (cfg->leaf_max < 0) return FMM_E_INVALID_ARG;
+  if (cfg->batch_level < 0 || cfg->batch_level > cfg->depth || cfg->reserved != 0)
+    return FMM_E_INVALID_ARG;
+  if (cfg->batch_level > 0 && cfg->leaf_max == 0) return FMM_E_UNSUPPORTED;
   if (cfg->precision != FMM_PREC_FP64 && cfg->precision != FMM_PREC_MIXED) return FMM_E_INVALID_ARG;
   if (cfg->m2l_kind < FMM_M2L_AUTO || cfg->m2l_kind > FMM_M2L_F16X2) return FMM_E_INVALID_ARG;
   if (cfg->m2l_kind == FMM_M2L_F64 && cfg->precision != FMM_PREC_FP64) return FMM_E_UNSUPPORTED;

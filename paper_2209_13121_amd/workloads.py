@@ -130,3 +130,46 @@ class ClusterWorkload:
 # Adaptive case: 10^6 three-site clusters (3e6 sites), leaves of at most 64
 # sites, p = 10, mixed precision.
 CLUSTERS = ClusterWorkload("clusters-n3000000-leaf64-p10", 1_000_000, 64, 8, 10, 1003)
+
+
+def batched_systems(n_systems: int, seed: int, n_min: int = 1000, n_max: int = 65536,
+                    grid: int = 8):
+    """A batch of independent systems: N_k = round(exp(U[ln n_min, ln n_max]))
+    rounded up to even, positions uniform in the system's own unit cube, the
+    k-th cube at cell (k % g, (k // g) % g, k // g^2) of a g^3 grid (root cube
+    [0, g]^3, so the systems are the boxes of level log2(g)), +-1 charges
+    with exactly N_k / 2 of each sign, shuffled.  Returns (pos, q, counts)."""
+    assert n_systems <= grid ** 3
+    rng = np.random.default_rng(seed)
+    counts = np.round(np.exp(rng.uniform(np.log(n_min), np.log(n_max), n_systems))).astype(np.int64)
+    counts += counts % 2
+    pos, q = [], []
+    for k, nk in enumerate(counts):
+        cell = np.array([k % grid, (k // grid) % grid, k // (grid * grid)], dtype=float)
+        pos.append(cell + rng.random((nk, 3)))
+        qk = np.empty(nk)
+        qk[: nk // 2] = 1.0
+        qk[nk // 2:] = -1.0
+        rng.shuffle(qk)
+        q.append(qk)
+    return np.concatenate(pos), np.concatenate(q), counts
+
+
+@dataclass(frozen=True)
+class BatchWorkload:
+    name: str
+    n_systems: int
+    leaf_max: int
+    max_depth: int
+    batch_level: int
+    p: int
+    seed: int
+
+    def make(self):
+        return batched_systems(self.n_systems, self.seed, grid=1 << self.batch_level)
+
+
+# Batched case: 256 systems of 10^3 .. 2^16 +-1 charges (log-uniform, about
+# 4e6 in all), each in its own unit cell of an 8^3 grid, adaptive leaves of at
+# most 64, p = 6.
+BATCH = BatchWorkload("batch256-n1e3to65536-leaf64-p6", 256, 64, 8, 3, 6, 1005)

@@ -21,7 +21,7 @@ def device():
 
 
 def run_gpu(pos, q, depth, p, precision=B.FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), side=1.0,
-            check=True, m2l_kind=B.FMM_M2L_AUTO, leaf_max=0, stats=None):
+            check=True, m2l_kind=B.FMM_M2L_AUTO, leaf_max=0, stats=None, batch_level=0):
     """Plan + evaluate on the GPU; returns numpy (phi, force, energy, status).
     leaf_max > 0: adaptive tree (depth = its cap); a dict passed as stats
     receives the tree statistics."""
@@ -30,7 +30,7 @@ def run_gpu(pos, q, depth, p, precision=B.FMM_PREC_FP64, lo=(0.0, 0.0, 0.0), sid
     tp = torch.from_numpy(np.ascontiguousarray(pos, dtype=np.float64)).to(dev)
     tq = torch.from_numpy(np.ascontiguousarray(q, dtype=np.float64)).to(dev)
     f = B.FMM(tp, p=p, depth=depth, precision=precision, lo=lo, side=side, m2l_kind=m2l_kind,
-              leaf_max=leaf_max)
+              leaf_max=leaf_max, batch_level=batch_level)
     phi, force, energy = f.evaluate(tq)
     st = f.check()
     torch.cuda.synchronize()

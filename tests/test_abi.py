@@ -39,7 +39,7 @@ def test_config_validation(lib):
     n = 1000
     for field, bad, code in [("p", -1, 1), ("p", 13, 1), ("depth", -1, 1), ("depth", 10, 1),
                              ("ws", 2, 1), ("leaf_max", -1, 1), ("precision", 5, 1),
-                             ("m2l_kind", 9, 1), ("abi_version", 2, 1)]:
+                             ("m2l_kind", 9, 1), ("abi_version", 1, 1), ("reserved", 1, 1)]:
         cfg = B.make_config()
         setattr(cfg, field, bad)
         with pytest.raises(B.FMMError) as ei:
@@ -52,6 +52,13 @@ def test_config_validation(lib):
         with pytest.raises(B.FMMError) as ei:
             B.fmm_workspace_size(cfg, n)
         assert ei.value.status == 6, (prec, kind)
+    # batch level: within 0..depth, and only on the adaptive tree
+    for kw, code in ((dict(depth=5, leaf_max=16, batch_level=6), 1), (dict(depth=5, leaf_max=16, batch_level=-1), 1),
+                     (dict(depth=5, batch_level=2), 6)):
+        with pytest.raises(B.FMMError) as ei:
+            B.fmm_workspace_size(B.make_config(**kw), n)
+        assert ei.value.status == code, kw
+    assert B.fmm_workspace_size(B.make_config(depth=5, leaf_max=16, batch_level=2), n) > 0
     cfg = B.make_config(side=float("nan"))
     with pytest.raises(B.FMMError):
         B.fmm_workspace_size(cfg, n)
