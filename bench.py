@@ -62,6 +62,8 @@ def parse():
                     help="skip the adaptive-tree workload (10^6 three-site clusters)")
     ap.add_argument("--adaptive-only", action="store_true",
                     help="run only the adaptive-tree workload and print its JSON object")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the 256-system batch and print its JSON object")
     ap.add_argument("--cpu-sample-boxes", type=int, default=3,
                     help="level-1 boxes (1/8 of the domain each) whose particles the oracle evaluates")
     ap.add_argument("--only", choices=sorted(VARIANTS), default=None,
@@ -281,6 +283,118 @@ def adaptive_bench(B, torch, args, stream):
     return out
 
 
+def batch_bench(B, torch, args, stream):
+    """The batch of 256 independent systems (10^3 .. 2^16 +-1 charges each,
+    4.04e6 in all, p = 6): the autotuner picks the M2L form and the leaf
+    capacity under the gate; then plan + evaluate of the whole batch is timed
+    like the headline (one launch per pass for all systems), and the
+    evaluation alone as one hipGraph replay."""
+    import numpy as np
+    import oracle
+    from paper_2209_13121_amd import autotune as T
+    from paper_2209_13121_amd import workloads as W
+    wl = W.BATCH
+    pos_np, q_np, counts = wl.make()
+    n = len(q_np)
+    grid = 1 << wl.batch_level
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(pos_np).to(dev)
+    q = torch.from_numpy(q_np).to(dev)
+    common = dict(lo=(0.0, 0.0, 0.0), side=float(grid), batch_level=wl.batch_level)
+    print("[bench] batch: autotune", file=sys.stderr, flush=True)
+    trees = [{"depth": wl.max_depth, "leaf_max": lm} for lm in (32, 64, 128)]
+    best, table = T.tune(pos, q, wl.p, trees, reps=3, stream=stream, **common)
+    tuned = {"leaf_max": best.tree["leaf_max"], "m2l_kind": best.kind} if best else None
+    kind = best.kind if best else "F16X2"
+    leaf = best.tree["leaf_max"] if best else wl.leaf_max
+    res = {}
+    for name, prec, mk in (("mixed", "MIXED", kind), ("fp64", "FP64", "AUTO")):
+        cfg = B.make_config(p=wl.p, depth=wl.max_depth, precision=getattr(B, "FMM_PREC_" + prec),
+                            m2l_kind=getattr(B, "FMM_M2L_" + mk), leaf_max=leaf, **common)
+        ws = torch.empty(B.fmm_workspace_size(cfg, n), dtype=torch.uint8, device=dev)
+        ms, step_stats, phi, force, energy, m2l, phases, st, work = timed_steps(
+            B, torch, pos, q, cfg, ws, max(5, args.steps // 2), args.warmup, stream)
+        entry = {"value": n / (ms / 1e3), "ms_per_step": ms, "step_events_ms": step_stats, "status": st,
+                 "phases_ms_per_step": {k: v[0] for k, v in phases.items()},
+                 "m2l_avg_launch_ms": m2l[0] / m2l[1]}
+        if name == "mixed":
+            # the evaluation alone, captured once and replayed as one graph launch
+            plan = B.fmm_plan(cfg, n, pos, ws, stream)
+            ph = torch.empty(n, dtype=torch.float64, device=dev)
+            fo = torch.empty((n, 3), dtype=torch.float64, device=dev)
+            en = torch.empty(1, dtype=torch.float64, device=dev)
+            side_s = torch.cuda.Stream()
+            side_s.wait_stream(stream)
+            with torch.cuda.stream(side_s):
+                B.fmm_evaluate(plan, q, ph, fo, en)
+            stream.wait_stream(side_s)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                B.fmm_evaluate(plan, q, ph, fo, en)
+            g.replay()
+            torch.cuda.synchronize()
+            reps = max(5, args.steps // 2)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                g.replay()
+            e1.record()
+            torch.cuda.synchronize()
+            gms = e0.elapsed_time(e1) / reps
+            entry["graph_evaluate"] = {"ms": gms, "value": n / (gms / 1e3),
+                                       "equals_eager_bitwise": bool(torch.equal(ph, phi))}
+            B.fmm_destroy(plan)
+            del g
+        res[name] = dict(entry, phi=phi.cpu().numpy(), force=force.cpu().numpy(),
+                         energy=float(energy.cpu()[0]), work=work)
+        print(f"[bench] batch {name}: {ms:.3f} ms/step, status {st}", file=sys.stderr, flush=True)
+        del ws
+        torch.cuda.empty_cache()
+    m, f = res["mixed"], res["fp64"]
+    acc = {"rel_energy_err_vs_fp64_gpu": abs(m["energy"] - f["energy"]) / abs(f["energy"]),
+           "rel_rms_force_err_vs_fp64_gpu": float(np.linalg.norm(m["force"] - f["force"]) /
+                                                  np.linalg.norm(f["force"]))}
+    # FP64 against the oracle of three systems alone (smallest, middle, largest)
+    starts = np.concatenate([[0], np.cumsum(counts)])
+    errs = {}
+    for k in (int(np.argmin(counts)), len(counts) // 2, int(np.argmax(counts))):
+        sl = slice(starts[k], starts[k + 1])
+        cell = (k % grid, (k // grid) % grid, k // (grid * grid))
+        ph, fo, _, _ = oracle.fmm_adaptive(pos_np[sl], q_np[sl], leaf, wl.max_depth - wl.batch_level,
+                                           wl.p, lo=cell, side=1.0)
+        errs[str(k)] = float(np.linalg.norm(f["phi"][sl] - ph) / np.linalg.norm(ph))
+    acc["fp64_rel_phi_err_vs_oracle_systems"] = errs
+    acc["gate_1e-6_met"] = bool(acc["rel_energy_err_vs_fp64_gpu"] <= 1e-6 and
+                                acc["rel_rms_force_err_vs_fp64_gpu"] <= 1e-5)
+    for r in res.values():
+        for k in ("phi", "force", "energy"):
+            r.pop(k)
+    out = {"workload": wl.name, "n": n, "systems": wl.n_systems, "n_min": int(counts.min()),
+           "n_max": int(counts.max()), "p": wl.p, "depth_cap": wl.max_depth, "batch_level": wl.batch_level,
+           "seed": wl.seed, "metric": "aggregate particles/s per batch evaluation (plan + evaluate)",
+           "value": m["value"], "ms_per_step": m["ms_per_step"], "tuned": tuned,
+           "autotune": [{"leaf_max": r.tree["leaf_max"], "m2l_kind": r.kind, "ms": r.ms,
+                         "energy_err": r.energy_err, "force_err": r.force_err} for r in table],
+           "accuracy": acc, "variants": res}
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        done = 0
+        for k in range(160):  # the first 160 systems, each alone
+            sl = slice(starts[k], starts[k + 1])
+            cell = (k % grid, (k // grid) % grid, k // (grid * grid))
+            oracle.fmm_adaptive(pos_np[sl], q_np[sl], leaf, wl.max_depth - wl.batch_level, wl.p,
+                                lo=cell, side=1.0)
+            done += counts[k]
+        dt = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"] = {"value": done / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
+                               "sample": f"CPU FP64 oracle adaptive FMM of the first 160 systems "
+                                         f"({int(done)} charges), one after another; {dt:.1f} s wall"}
+    return out
+
+
 def cpu_baseline(pos, q, wl, nboxes):
     import numpy as np
     import oracle
@@ -314,6 +428,10 @@ def main():
     if args.adaptive_only:
         B.load()
         print(json.dumps(adaptive_bench(B, torch, args, torch.cuda.current_stream())), flush=True)
+        return
+    if args.batch_only:
+        B.load()
+        print(json.dumps(batch_bench(B, torch, args, torch.cuda.current_stream())), flush=True)
         return
     wl = W.HEADLINE
     pos_np, q_np = wl.make()
@@ -428,6 +546,8 @@ def main():
         del pos, q
         torch.cuda.empty_cache()
         out["adaptive"] = adaptive_bench(B, torch, args, stream)
+        torch.cuda.empty_cache()
+        out["batch"] = batch_bench(B, torch, args, stream)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pos_np, q_np, wl, args.cpu_sample_boxes)
