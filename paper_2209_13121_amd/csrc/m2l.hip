@@ -144,7 +144,7 @@ struct Shape {
   static_assert(MS % V == 0, "multipole rows must hold whole vectors");
 };
 
-template <int P, typename T>
+template <int P, typename T, bool AD>
 __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restrict__ mult,
                                                   const T* __restrict__ zero_row,
                                                   const T* __restrict__ ops,
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restri
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  m2l::Tile tl;
+  m2l::TileT<AD> tl;
   if (!tl.setup(a, wave * 16 + col, sSlot, sBox)) return;  // uniform over the work-group
   const int pi = tl.pi;
   const bool col_ok = tl.col_ok;
@@ -359,16 +359,20 @@ struct M2LRun {
     const m2l::Args a = m2l::make_args(Pl);
     const unsigned grid = m2l::grid_of(a);
     if (Pl->mixed)
-      k_m2l<P, float><<<grid, kThreads, 0, s>>>(a, wsp<float>(Pl, lay.mult32),
-                                               wsp<float>(Pl, lay.zero_row),
-                                               wsp<float>(Pl, lay.op_m2l32),
-                                               wsp<float>(Pl, lay.m2l_out));
+      go<float>(Pl, a, grid, wsp<float>(Pl, lay.mult32), wsp<float>(Pl, lay.zero_row),
+                wsp<float>(Pl, lay.op_m2l32), wsp<float>(Pl, lay.m2l_out), s);
     else
-      k_m2l<P, double><<<grid, kThreads, 0, s>>>(a, wsp<double>(Pl, lay.mult64),
-                                                wsp<double>(Pl, lay.zero_row),
-                                                wsp<double>(Pl, lay.op_m2l64),
-                                                wsp<double>(Pl, lay.m2l_out));
+      go<double>(Pl, a, grid, wsp<double>(Pl, lay.mult64), wsp<double>(Pl, lay.zero_row),
+                 wsp<double>(Pl, lay.op_m2l64), wsp<double>(Pl, lay.m2l_out), s);
     return hipGetLastError();
+  }
+  template <typename T>
+  static void go(fmm_plan_s* Pl, const m2l::Args& a, unsigned grid, const T* mult, const T* zero,
+                 const T* ops, T* out, hipStream_t s) {
+    if (Pl->adaptive)
+      k_m2l<P, T, true><<<grid, kThreads, 0, s>>>(a, mult, zero, ops, out);
+    else
+      k_m2l<P, T, false><<<grid, kThreads, 0, s>>>(a, mult, zero, ops, out);
   }
 };
 

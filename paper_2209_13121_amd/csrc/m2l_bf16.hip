@@ -157,7 +157,7 @@ struct Shape {
 // F16: FP16 pieces of scaled operands (FMM_M2L_F16X2): per-offset FP32 chains
 // times the source box's inverse scale, summed in two levels (partials of
 // kGroupF16 offsets), rows times rowf at the end.
-template <int P, int NP, bool F16>
+template <int P, int NP, bool F16, bool AD>
 __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* __restrict__ multq,
                                                      const u32x4* __restrict__ zero_q,
                                                      const u32x4* __restrict__ ops,
@@ -174,7 +174,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  m2l::Tile tl;
+  m2l::TileT<AD> tl;
   if (!tl.setup(a, wave * 16 + col, sSlot, sBox)) return;  // uniform over the work-group
   const int pi = tl.pi;
   const u32x4* mlev = multq + tl.lvl_off * QR;
@@ -381,9 +381,14 @@ struct M2LBfRun {
     prof_end(Pl, s);
     const m2l::Args a = m2l::make_args(Pl);
     prof_begin(Pl, FMM_PHASE_M2L, s);
-    k_m2l_bf<P, NP, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
-        a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-        nullptr, nullptr);
+    if (Pl->adaptive)
+      k_m2l_bf<P, NP, false, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
+          a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+          nullptr, nullptr);
+    else
+      k_m2l_bf<P, NP, false, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
+          a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+          nullptr, nullptr);
     prof_end(Pl, s);
     return hipGetLastError();
   }
@@ -402,9 +407,14 @@ struct M2LBfRun {
     prof_end(Pl, s);
     const m2l::Args a = m2l::make_args(Pl);
     prof_begin(Pl, FMM_PHASE_M2L, s);
-    k_m2l_bf<P, 2, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
-        a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-        msc, wsp<float>(Pl, lay.f16_rowf));
+    if (Pl->adaptive)
+      k_m2l_bf<P, 2, true, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
+          a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+          msc, wsp<float>(Pl, lay.f16_rowf));
+    else
+      k_m2l_bf<P, 2, true, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
+          a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+          msc, wsp<float>(Pl, lay.f16_rowf));
     prof_end(Pl, s);
     return hipGetLastError();
   }

@@ -63,15 +63,13 @@ struct Args {
   int64_t ngroups;
   const uint32_t* c2s;
   const uint32_t* s2c;
-  // Adaptive tree only (null for the uniform one).  The targets of level l
+  // Adaptive tree only.  The targets of level l
   // and class pi are the class-pi children of the level's divided parents,
   // ndiv[l] of them, rows tgt[tgt_off[l] + pi ndiv[l] + k] of the level; a
   // work-group owns 128 of them (tile t) and reads the row of each target's
   // source at offset i of its class from
   // vtab[vt_off[l] + ((t * 8 + pi) * kIL + i) * 128 + target] (kAbsent where
   // the tree has no such box, and for the padding of the last tile).
-  const uint32_t* present;
-  const uint32_t* row;
   const uint32_t* tgt;
   const uint32_t* vtab;
   int64_t ndiv[FMM_DEPTH_MAX + 2];
@@ -97,8 +95,6 @@ inline Args make_args(fmm_plan_s* Pl) {
   a.ngroups = g;
   a.c2s = wsp<uint32_t>(Pl, lay.coord2slot);
   a.s2c = wsp<uint32_t>(Pl, lay.slot2coord);
-  a.present = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_present) : nullptr;
-  a.row = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_scan) : nullptr;
   a.tgt = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_tgt) : nullptr;
   a.vtab = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_vtab) : nullptr;
   for (int l = 0; l <= FMM_DEPTH_MAX + 1; ++l) {
@@ -121,11 +117,14 @@ struct Src {
   bool ok;  // inside the domain (else the source is a zero row)
 };
 
-// Staged halo entries of the adaptive tree: a box that does not exist.
+// Source-table entry of the adaptive tree: no box there.
 constexpr uint32_t kAbsent = 0x80000000u;
 
-// A lane's view of its work-group's tile.
-struct Tile {
+// A lane's view of its work-group's tile.  AD: adaptive tree (targets from the
+// per-class lists, sources from the table; no halo), fixed at compile time so
+// that the uniform form carries none of it.
+template <bool AD>
+struct TileT {
   int l, pi, nb;
   int tx, ty, tz;  // this lane's target box (meaningful when col_ok)
   bool col_ok;
@@ -136,9 +135,9 @@ struct Tile {
   int64_t trow;                                // adaptive: this lane's target row
 
   // Decode the group, find this lane's target (number tix of the tile's 128)
-  // and stage the halo's rows in sSlot (kAbsent where the adaptive tree has no
-  // box).  Returns false, uniformly over the work-group, for a group past the
-  // end or one without any existing target.  Contains barriers.
+  // and (uniform tree) stage the halo's slots in sSlot.  Returns false,
+  // uniformly over the work-group, for a group past the end.  The uniform form
+  // contains barriers.
   __device__ bool setup(const Args& a, int tix, uint32_t* sSlot, int* sBox) {
     // XCD-aware order: hardware group b runs on XCD b % 8; each XCD gets a
     // contiguous range of logical groups.
@@ -147,8 +146,7 @@ struct Tile {
     if (lg >= a.ngroups) return false;
     l = 2;
     while (l < a.L && lg >= a.group_off[l + 1]) ++l;
-    vt = nullptr;
-    if (a.vtab) {  // adaptive: no halo, the source rows come from the table
+    if constexpr (AD) {  // no halo, the source rows come from the table
       const int64_t idx = lg - a.group_off[l];
       pi = (int)(idx % 8);
       const int64_t tile = idx / 8;
@@ -177,7 +175,6 @@ struct Tile {
       tx = 2 * tx + px;
       ty = 2 * ty + py;
       tz = 2 * tz + pz;
-      if (a.present) col_ok = a.present[dense_off + a.c2s[dense_off + lex_index(tx, ty, tz, l)]] != 0;
     }
     const int tid = threadIdx.x;
     if (tid < 6) sBox[tid] = tid < 3 ? nb : -1;
@@ -191,7 +188,6 @@ struct Tile {
       atomicMax(&sBox[5], tz - pz + 3);
     }
     __syncthreads();
-    if (sBox[3] == -1) return false;  // no existing target in this tile
     hx0 = sBox[0] < 0 ? 0 : sBox[0];
     hy0 = sBox[1] < 0 ? 0 : sBox[1];
     hz0 = sBox[2] < 0 ? 0 : sBox[2];
@@ -204,13 +200,7 @@ struct Tile {
     const uint32_t* c2s = a.c2s + dense_off;
     for (int e = tid; e < hn && e < kHalo; e += (int)blockDim.x) {
       const int x = hx0 + e / (hey * hez), y = hy0 + (e / hez) % hey, z = hz0 + e % hez;
-      const uint32_t slot = c2s[lex_index(x, y, z, l)];
-      uint32_t v = slot;
-      if (a.present) {
-        const int64_t g = dense_off + slot;
-        v = a.present[g] ? (uint32_t)(a.row[g] - lvl_off) : kAbsent;
-      }
-      sSlot[e] = v;
+      sSlot[e] = c2s[lex_index(x, y, z, l)];
     }
     __syncthreads();
     return true;
@@ -221,7 +211,7 @@ struct Tile {
   // unconditional) or, on the adaptive tree, from the source table; and
   // whether the source exists.
   __device__ __forceinline__ Src lookup(const uint32_t* sSlot, int k, int dx, int dy, int dz) const {
-    if (vt) {
+    if constexpr (AD) {
       const uint32_t v = vt[(int64_t)k * kTargetsPerGroup];
       return Src{v & ~kAbsent, !(v & kAbsent)};
     }
@@ -230,15 +220,13 @@ struct Tile {
     sx = sx < hx0 ? hx0 : (sx > hx1 ? hx1 : sx);
     sy = sy < hy0 ? hy0 : (sy > hy1 ? hy1 : sy);
     sz = sz < hz0 ? hz0 : (sz > hz1 ? hz1 : sz);
-    const uint32_t v = sSlot[((sx - hx0) * hey + (sy - hy0)) * hez + (sz - hz0)];
-    return Src{v & ~kAbsent, ok && !(v & kAbsent)};
+    return Src{sSlot[((sx - hx0) * hey + (sy - hy0)) * hez + (sz - hz0)], ok};
   }
 
   // Row of this lane's target within its level (col_ok only).
   __device__ __forceinline__ int64_t target_slot(const Args& a) const {
-    if (vt) return trow;
-    const uint32_t slot = a.c2s[dense_off + lex_index(tx, ty, tz, l)];
-    return a.present ? (int64_t)a.row[dense_off + slot] - lvl_off : (int64_t)slot;
+    if constexpr (AD) return trow;
+    return a.c2s[dense_off + lex_index(tx, ty, tz, l)];
   }
 };
 

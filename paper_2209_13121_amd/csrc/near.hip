@@ -38,28 +38,45 @@ struct NearAcc {
 // once to T, so a close pair keeps its relative accuracy; r^2, 1/r and the
 // sums run in T.
 template <bool SCALED, typename T>
+__device__ __forceinline__ void near_pair(NearAcc<T>& a, double ox, double oy, double oz, double sg,
+                                          const Rec<double>& rj, bool self) {
+  const T rx = (T)(SCALED ? fma(-sg, rj.x, ox) : ox - rj.x);
+  const T ry = (T)(SCALED ? fma(-sg, rj.y, oy) : oy - rj.y);
+  const T rz = (T)(SCALED ? fma(-sg, rj.z, oz) : oz - rj.z);
+  const T r2 = rx * rx + ry * ry + rz * rz;
+  // the target itself and coincident points contribute nothing (the latter
+  // are flagged); selects rather than branches keep the loop straight
+  const bool skip = self || r2 == T(0);
+  a.coincident |= !self && r2 == T(0);
+  const T rinv = inv_sqrt(skip ? T(1) : r2);
+  const T qr = (skip ? T(0) : (T)rj.q) * rinv;
+  const T qr3 = qr * rinv * rinv;
+  a.f += qr;
+  a.gx -= qr3 * rx;
+  a.gy -= qr3 * ry;
+  a.gz -= qr3 * rz;
+}
+
+// Sum over sources j in [b, e), j != i, with (ox, oy, oz) the target's offset
+// from the source box centre in the target's box units: pair offset
+// r = o - sg u_j.  SCALED: the sources' own offsets are in units sg times the
+// target's (an exact power of two; adaptive tree).  The box-unit offsets are
+// FP64 in both precision modes: the pair offset is formed in FP64 and rounded
+// once to T, so a close pair keeps its relative accuracy; r^2, 1/r and the
+// sums run in T.  Four source records are loaded ahead of their use.
+template <bool SCALED, typename T>
 __device__ __forceinline__ void near_pairs(NearAcc<T>& a, double ox, double oy, double oz, double sg,
                                            const Rec<double>* __restrict__ src, uint32_t b,
                                            uint32_t e, int64_t i) {
-  for (uint32_t j = b; j < e; ++j) {
-    if ((int64_t)j == i) continue;
-    const Rec<double> rj = src[j];
-    const T rx = (T)(SCALED ? fma(-sg, rj.x, ox) : ox - rj.x);
-    const T ry = (T)(SCALED ? fma(-sg, rj.y, oy) : oy - rj.y);
-    const T rz = (T)(SCALED ? fma(-sg, rj.z, oz) : oz - rj.z);
-    const T r2 = rx * rx + ry * ry + rz * rz;
-    if (r2 == T(0)) {
-      a.coincident = true;
-      continue;
-    }
-    const T rinv = inv_sqrt(r2);
-    const T qr = (T)rj.q * rinv;
-    const T qr3 = qr * rinv * rinv;
-    a.f += qr;
-    a.gx -= qr3 * rx;
-    a.gy -= qr3 * ry;
-    a.gz -= qr3 * rz;
+  uint32_t j = b;
+  for (; j + 4 <= e; j += 4) {
+    const Rec<double> r0 = src[j], r1 = src[j + 1], r2 = src[j + 2], r3 = src[j + 3];
+    near_pair<SCALED, T>(a, ox, oy, oz, sg, r0, (int64_t)j == i);
+    near_pair<SCALED, T>(a, ox, oy, oz, sg, r1, (int64_t)j + 1 == i);
+    near_pair<SCALED, T>(a, ox, oy, oz, sg, r2, (int64_t)j + 2 == i);
+    near_pair<SCALED, T>(a, ox, oy, oz, sg, r3, (int64_t)j + 3 == i);
   }
+  for (; j < e; ++j) near_pair<SCALED, T>(a, ox, oy, oz, sg, src[j], (int64_t)j == i);
 }
 
 struct FinishArgs {
