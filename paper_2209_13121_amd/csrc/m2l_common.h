@@ -131,6 +131,7 @@ struct TileT {
   int hx0, hy0, hz0, hx1, hy1, hz1, hey, hez;  // halo box (clamped to the level)
   int64_t lvl_off;                             // first row of level l in the expansion arrays
   int64_t dense_off;                           // first box of level l in the dense tables
+  int64_t tile;                                // tile number within the level and class
   const uint32_t* vt;                          // adaptive: this lane's source-row column
   int64_t trow;                                // adaptive: this lane's target row
 
@@ -138,7 +139,7 @@ struct TileT {
   // and (uniform tree) stage the halo's slots in sSlot.  Returns false,
   // uniformly over the work-group, for a group past the end.  The uniform form
   // contains barriers.
-  __device__ bool setup(const Args& a, int tix, uint32_t* sSlot, int* sBox) {
+  __device__ __forceinline__ bool setup(const Args& a, int tix, uint32_t* sSlot, int* sBox) {
     // XCD-aware order: hardware group b runs on XCD b % 8; each XCD gets a
     // contiguous range of logical groups.
     const int64_t per_xcd = (a.ngroups + 7) / 8;
@@ -149,33 +150,21 @@ struct TileT {
     if constexpr (AD) {  // no halo, the source rows come from the table
       const int64_t idx = lg - a.group_off[l];
       pi = (int)(idx % 8);
-      const int64_t tile = idx / 8;
-      const int64_t ps = tile * kTargetsPerGroup + tix;
-      col_ok = ps < a.ndiv[l];
-      trow = col_ok ? (int64_t)a.tgt[a.tgt_off[l] + pi * a.ndiv[l] + ps] : 0;
+      tile = idx / 8;
       lvl_off = a.exp_off[l];
-      vt = a.vtab + a.vt_off[l] + (tile * 8 + pi) * (int64_t)kIL * kTargetsPerGroup + tix;
+      retarget(a, tix);
       return true;
     }
-    const int64_t np = (int64_t)1 << (3 * (l - 1));  // parents at level l-1
     // The 8 parity classes of a tile are consecutive groups, so they run close
     // together on one XCD and share its L2 for the tile's sources.
     const int64_t idx = lg - a.group_off[l];
     pi = (int)(idx % 8);
-    const int64_t tile = idx / 8;
+    tile = idx / 8;
     const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
     nb = 1 << l;
     lvl_off = a.exp_off[l];
     dense_off = a.lvl_off[l];
-    const int64_t ps = tile * kTargetsPerGroup + tix;
-    col_ok = ps < np;
-    tx = ty = tz = 0;
-    if (col_ok) {
-      unpack_coord(a.s2c[a.lvl_off[l - 1] + ps], tx, ty, tz);
-      tx = 2 * tx + px;
-      ty = 2 * ty + py;
-      tz = 2 * tz + pz;
-    }
+    retarget(a, tix);
     const int tid = threadIdx.x;
     if (tid < 6) sBox[tid] = tid < 3 ? nb : -1;
     __syncthreads();
@@ -204,6 +193,25 @@ struct TileT {
     }
     __syncthreads();
     return true;
+  }
+
+  // This lane's target: number tix of the tile (no barriers).
+  __device__ __forceinline__ void retarget(const Args& a, int tix) {
+    const int64_t ps = tile * kTargetsPerGroup + tix;
+    if constexpr (AD) {
+      col_ok = ps < a.ndiv[l];
+      trow = col_ok ? (int64_t)a.tgt[a.tgt_off[l] + pi * a.ndiv[l] + ps] : 0;
+      vt = a.vtab + a.vt_off[l] + (tile * 8 + pi) * (int64_t)kIL * kTargetsPerGroup + tix;
+    } else {
+      col_ok = ps < ((int64_t)1 << (3 * (l - 1)));
+      tx = ty = tz = 0;
+      if (col_ok) {
+        unpack_coord(a.s2c[a.lvl_off[l - 1] + ps], tx, ty, tz);
+        tx = 2 * tx + ((pi >> 2) & 1);
+        ty = 2 * ty + ((pi >> 1) & 1);
+        tz = 2 * tz + (pi & 1);
+      }
+    }
   }
 
   // This lane's source for offset k = (dx, dy, dz) of its class: its row,
