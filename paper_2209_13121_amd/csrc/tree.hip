@@ -65,15 +65,35 @@ __global__ void k_bbox_partial(const double* __restrict__ pos, int64_t n, double
     }
 }
 
+// One block of kBlock threads: each folds a strided share of the partials,
+// then a tree reduction in LDS (min / max are exact in any order).
 __global__ void k_bbox_final(const double* __restrict__ part, int nparts, DevParams* dp,
                              int32_t* flags) {
-  if (threadIdx.x != 0) return;
+  __shared__ double smin[3][kBlock], smax[3][kBlock];
   double mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-  for (int b = 0; b < nparts; ++b)
+  for (int b = threadIdx.x; b < nparts; b += kBlock)
     for (int a = 0; a < 3; ++a) {
       mn[a] = fmin(mn[a], part[6 * b + a]);
       mx[a] = fmax(mx[a], part[6 * b + 3 + a]);
     }
+  for (int a = 0; a < 3; ++a) {
+    smin[a][threadIdx.x] = mn[a];
+    smax[a][threadIdx.x] = mx[a];
+  }
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w)
+      for (int a = 0; a < 3; ++a) {
+        smin[a][threadIdx.x] = fmin(smin[a][threadIdx.x], smin[a][threadIdx.x + w]);
+        smax[a][threadIdx.x] = fmax(smax[a][threadIdx.x], smax[a][threadIdx.x + w]);
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  for (int a = 0; a < 3; ++a) {
+    mn[a] = smin[a][0];
+    mx[a] = smax[a][0];
+  }
   double side = 0.0;
   for (int a = 0; a < 3; ++a) {
     if (!isfinite(mn[a])) mn[a] = 0.0, mx[a] = 0.0;  // no finite coordinate at all
@@ -332,7 +352,7 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
     double* part = wsp<double>(P, lay.bbox);
     const int nparts = (int)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock);
     k_bbox_partial<<<nparts, kBlock, 0, s>>>(d_pos, n, part);
-    k_bbox_final<<<1, 64, 0, s>>>(part, nparts, dp, flags);
+    k_bbox_final<<<1, kBlock, 0, s>>>(part, nparts, dp, flags);
   }
   k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(count, lay.nleaf, 0u);
   {  // the zero row M2L reads for sources outside the domain

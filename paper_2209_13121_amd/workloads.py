@@ -129,7 +129,7 @@ class ClusterWorkload:
 
 # Adaptive case: 10^6 three-site clusters (3e6 sites), leaves of at most 64
 # sites, p = 10, mixed precision.
-CLUSTERS = ClusterWorkload("clusters-n3000000-leaf64-p10", 1_000_000, 64, 8, 10, 1003)
+CLUSTERS = ClusterWorkload("clusters-n3000000-leaf64-p10", 1_000_000, 64, 7, 10, 1003)
 
 
 def batched_systems(n_systems: int, seed: int, n_min: int = 1000, n_max: int = 65536,
@@ -172,4 +172,4 @@ class BatchWorkload:
 # Batched case: 256 systems of 10^3 .. 2^16 +-1 charges (log-uniform, about
 # 4e6 in all), each in its own unit cell of an 8^3 grid, adaptive leaves of at
 # most 64, p = 6.
-BATCH = BatchWorkload("batch256-n1e3to65536-leaf64-p6", 256, 64, 8, 3, 6, 1005)
+BATCH = BatchWorkload("batch256-n1e3to65536-leaf64-p6", 256, 64, 7, 3, 6, 1005)
