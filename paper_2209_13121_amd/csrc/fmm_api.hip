@@ -116,7 +116,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     if (np) {
       const size_t rq = (size_t)m2lb_row_quads(nc, np);
       lay->multb = take(16 * NB * rq);
-      lay->op_m2lb = take(16 * (size_t)kNumM2LOps * m2lb_op_quads(nc, np));
+      lay->op_m2lb = take(16 * (size_t)kNumM2LOps * m2lb_op_quads(nc, np, adaptive));
     }
     if (m2l_is_f16(cfg)) {
       const size_t rp = (size_t)m2lb_rows(nc), kp = (size_t)32 * m2lb_ksteps(nc);

@@ -55,22 +55,28 @@ __host__ __device__ constexpr int m2l_kstride_of(int nc, int elem) {
 //    fill the even residues and the odd g offset the odd ones.
 __host__ __device__ constexpr int m2lb_ksteps(int nc) { return (nc + 31) / 32; }
 __host__ __device__ constexpr int m2lb_row_quads(int nc, int np) { return m2lb_ksteps(nc) * np * 4; }
-constexpr int kM2lbLdsBudget = 140 * 1024;  // two operator chunk buffers
+// LDS for the two operator chunk buffers: the uniform tree's kernels also hold
+// the halo's slot table (11.5 KB), the adaptive tree's (ad) do not.
+constexpr int kM2lbLdsBudget = 140 * 1024;
+constexpr int kM2lbLdsBudgetAd = 156 * 1024;
 __host__ __device__ constexpr int m2lb_gq(int kc, int np) { return (kc * np) | 1; }
 __host__ __device__ constexpr int m2lb_qcs(int kc, int np) { return 4 * m2lb_gq(kc, np) + 2; }
 __host__ __device__ constexpr int m2lb_rows(int nc) { return ((nc + 15) / 16) * 16; }
-__host__ __device__ constexpr int m2lb_kc_fit(int nc, int np, int n) {
+__host__ __device__ constexpr int m2lb_kc_fit(int nc, int np, int n, bool ad) {
   return n <= 1 ? 1
-                : (2 * m2lb_rows(nc) * m2lb_qcs(n, np) * 16 <= kM2lbLdsBudget ? n
-                                                                            : m2lb_kc_fit(nc, np, n - 1));
+                : (2 * m2lb_rows(nc) * m2lb_qcs(n, np) * 16 <= (ad ? kM2lbLdsBudgetAd : kM2lbLdsBudget)
+                       ? n
+                       : m2lb_kc_fit(nc, np, n - 1, ad));
 }
-__host__ __device__ constexpr int m2lb_kc(int nc, int np) { return m2lb_kc_fit(nc, np, m2lb_ksteps(nc)); }
-__host__ __device__ constexpr int m2lb_nch(int nc, int np) {
-  return (m2lb_ksteps(nc) + m2lb_kc(nc, np) - 1) / m2lb_kc(nc, np);
+__host__ __device__ constexpr int m2lb_kc(int nc, int np, bool ad = false) {
+  return m2lb_kc_fit(nc, np, m2lb_ksteps(nc), ad);
+}
+__host__ __device__ constexpr int m2lb_nch(int nc, int np, bool ad = false) {
+  return (m2lb_ksteps(nc) + m2lb_kc(nc, np, ad) - 1) / m2lb_kc(nc, np, ad);
 }
 // Quads of one operator (all chunks).
-__host__ __device__ constexpr int m2lb_op_quads(int nc, int np) {
-  return m2lb_nch(nc, np) * m2lb_rows(nc) * m2lb_qcs(m2lb_kc(nc, np), np);
+__host__ __device__ constexpr int m2lb_op_quads(int nc, int np, bool ad = false) {
+  return m2lb_nch(nc, np, ad) * m2lb_rows(nc) * m2lb_qcs(m2lb_kc(nc, np, ad), np);
 }
 
 // Bytes of the all-zero source row that M2L reads outside the domain (large

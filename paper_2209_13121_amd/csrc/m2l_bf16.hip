@@ -129,15 +129,15 @@ __global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, in
 }
 
 // Shape of the kernel for order P and NP pieces.
-template <int P, int NP, bool F16 = false>
+template <int P, int NP, bool F16 = false, bool AD = false>
 struct Shape {
   static constexpr int NC = (P + 1) * (P + 1);
   static constexpr int RB = (NC + 15) / 16;  // 16-row blocks
   static constexpr int RP = RB * 16;
   static constexpr int KST = m2lb_ksteps(NC);       // 32-wide k steps
   static constexpr int QR = m2lb_row_quads(NC, NP);  // quads per source box
-  static constexpr int KC = m2lb_kc(NC, NP);         // k steps per staged chunk
-  static constexpr int NCH = m2lb_nch(NC, NP);       // chunks per operator
+  static constexpr int KC = m2lb_kc(NC, NP, AD);     // k steps per staged chunk
+  static constexpr int NCH = m2lb_nch(NC, NP, AD);   // chunks per operator
   static constexpr int GQ = m2lb_gq(KC, NP);         // quads between lane groups g
   static constexpr int QCS = m2lb_qcs(KC, NP);       // quads between rows
   static constexpr int CQ = RP * QCS;                // quads per stored chunk
@@ -164,12 +164,12 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
                                                      float* __restrict__ out,
                                                      const float* __restrict__ mscale,
                                                      const float* __restrict__ rowf) {
-  typedef Shape<P, NP, F16> S;
+  typedef Shape<P, NP, F16, AD> S;
   typedef Prod<NP> PR;
   constexpr int NC = S::NC, RB = S::RB, RP = S::RP, KST = S::KST, QR = S::QR;
   constexpr int KC = S::KC, NCH = S::NCH, GQ = S::GQ, QCS = S::QCS, RG = S::RG;
   __shared__ u32x4 sT[2][RP * QCS];
-  __shared__ uint32_t sSlot[m2l::kHalo];
+  __shared__ uint32_t sSlot[AD ? 1 : m2l::kHalo];  // the adaptive form has no halo
   __shared__ int sBox[6];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;

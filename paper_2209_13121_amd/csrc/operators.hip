@@ -234,7 +234,7 @@ __global__ void k_gen_m2l(int p, int rp, int ks, T* __restrict__ ops) {
 // thread per (operator row, k step, lane group) computes its 8 FP64 entries
 // and writes their NP quads.  Pad quads are zeroed beforehand.
 template <int NP>
-__global__ void k_gen_m2l_bf(int p, u32x4* __restrict__ ops) {
+__global__ void k_gen_m2l_bf(int p, bool ad, u32x4* __restrict__ ops) {
   __shared__ double tre[kTabMax], tim[kTabMax];
   const int op = blockIdx.x;
   if ((int)threadIdx.x <= 2 * p) {
@@ -245,9 +245,9 @@ __global__ void k_gen_m2l_bf(int p, u32x4* __restrict__ ops) {
   }
   __syncthreads();
   const int nc = (p + 1) * (p + 1);
-  const int kst = m2lb_ksteps(nc), rp = m2lb_rows(nc), kc = m2lb_kc(nc, NP);
+  const int kst = m2lb_ksteps(nc), rp = m2lb_rows(nc), kc = m2lb_kc(nc, NP, ad);
   const int gq = m2lb_gq(kc, NP), qcs = m2lb_qcs(kc, NP);
-  u32x4* out = ops + (size_t)op * m2lb_op_quads(nc, NP);
+  u32x4* out = ops + (size_t)op * m2lb_op_quads(nc, NP, ad);
   for (int e = threadIdx.x; e < rp * kst * 4; e += blockDim.x) {
     const int row = e / (kst * 4), ks = e / 4 % kst, g = e % 4;
     uint32_t pc[8][NP];
@@ -333,13 +333,13 @@ __global__ void k_f16_fit(int rp, int kp, const float* __restrict__ tbl, float* 
 
 // Pass 4: scaled entries split into 2 FP16 pieces, in the split-M2L operator
 // layout (m2lb_* with np = 2); one thread per (op, row, k step, lane group).
-__global__ void k_f16_split_ops(int p, int64_t nitems, const double* __restrict__ scratch,
+__global__ void k_f16_split_ops(int p, bool ad, int64_t nitems, const double* __restrict__ scratch,
                                 const float* __restrict__ rowf, const float* __restrict__ colf,
                                 u32x4* __restrict__ ops) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= nitems) return;
   const int nc = (p + 1) * (p + 1);
-  const int kst = m2lb_ksteps(nc), rp = m2lb_rows(nc), kp = 32 * kst, kc = m2lb_kc(nc, 2);
+  const int kst = m2lb_ksteps(nc), rp = m2lb_rows(nc), kp = 32 * kst, kc = m2lb_kc(nc, 2, ad);
   const int gq = m2lb_gq(kc, 2), qcs = m2lb_qcs(kc, 2);
   const int g = (int)(t % 4), ks = (int)(t / 4 % kst), row = (int)(t / (4 * kst) % rp);
   const int op = (int)(t / (4 * kst * rp));
@@ -353,7 +353,7 @@ __global__ void k_f16_split_ops(int p, int64_t nitems, const double* __restrict_
   }
   u32x4 q[2];
   pack_quads<2>(pc, q);
-  u32x4* o = ops + (size_t)op * m2lb_op_quads(nc, 2) + ((size_t)(ks / kc) * rp + row) * qcs + g * gq +
+  u32x4* o = ops + (size_t)op * m2lb_op_quads(nc, 2, ad) + ((size_t)(ks / kc) * rp + row) * qcs + g * gq +
              (ks % kc) * 2;
   o[0] = q[0];
   o[1] = q[1];
@@ -369,7 +369,7 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
                                     wsp<double>(P, lay.op_l2l));
   if (P->m2l_f16) {
     const int nc = P->nc, rpp = m2lb_rows(nc), kp = 32 * m2lb_ksteps(nc);
-    const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(nc, 2) * 4;
+    const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(nc, 2, P->adaptive) * 4;
     fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads
     double* scratch = wsp<double>(P, lay.op_m2l_scratch);
     float* tbl = wsp<float>(P, lay.f16_tbl);
@@ -379,17 +379,17 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
     k_f16_table<<<grid_for(rpp * kp, kBlock), kBlock, 0, s>>>(rpp * kp, scratch, tbl);
     k_f16_fit<<<1, kBlock, 0, s>>>(rpp, kp, tbl, rowf, colf);
     const int64_t items = (int64_t)kNumM2LOps * rpp * m2lb_ksteps(nc) * 4;
-    k_f16_split_ops<<<grid_for(items, kBlock), kBlock, 0, s>>>(P->p, items, scratch, rowf, colf,
-                                                               wsp<u32x4>(P, lay.op_m2lb));
+    k_f16_split_ops<<<grid_for(items, kBlock), kBlock, 0, s>>>(P->p, P->adaptive, items, scratch, rowf,
+                                                               colf, wsp<u32x4>(P, lay.op_m2lb));
   } else if (P->m2l_np) {
     const int np = P->m2l_np;
-    const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(P->nc, np) * 4;
+    const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(P->nc, np, P->adaptive) * 4;
     fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads
     u32x4* ob = wsp<u32x4>(P, lay.op_m2lb);
     if (np == 2)
-      k_gen_m2l_bf<2><<<kNumM2LOps, kBlock, 0, s>>>(P->p, ob);
+      k_gen_m2l_bf<2><<<kNumM2LOps, kBlock, 0, s>>>(P->p, P->adaptive, ob);
     else
-      k_gen_m2l_bf<3><<<kNumM2LOps, kBlock, 0, s>>>(P->p, ob);
+      k_gen_m2l_bf<3><<<kNumM2LOps, kBlock, 0, s>>>(P->p, P->adaptive, ob);
   } else if (P->mixed)
     k_gen_m2l<float><<<kNumM2LOps, kBlock, 0, s>>>(P->p, rp, m2l_kstride_of(P->nc, 4),
                                                    wsp<float>(P, lay.op_m2l32));
