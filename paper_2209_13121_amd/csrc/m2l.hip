@@ -140,7 +140,7 @@ struct Shape {
   static constexpr int PER_THREAD = (NV + kThreads - 1) / kThreads;
   // Prefetch the next offset's B vectors (a second register set) only where
   // the registers allow it without spills.
-  static constexpr bool PREFETCH_B = sizeof(T) == 4 ? P <= 10 : P <= 7;
+  static constexpr bool PREFETCH_B = P <= (sizeof(T) == 4 ? 8 : 7);
   static_assert(MS % V == 0, "multipole rows must hold whole vectors");
 };
 

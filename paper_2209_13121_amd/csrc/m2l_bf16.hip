@@ -145,13 +145,17 @@ struct Shape {
   static constexpr int NV = NC * QD;                 // quads staged per chunk
   static constexpr int PER_THREAD = (NV + kThreads - 1) / kThreads;
   // row blocks whose MFMA chains are interleaved (per group of A loads):
-  // all of them in the FP16 form (measured: -7 % time at p = 8), fewer in the
-  // BF16 forms, whose extra piece would not fit the registers
-  static constexpr int RGW = F16 ? 6 : M2LB_RG;
+  // up to 6 in the FP16 form (measured: -7 % time at p = 8), fewer in the
+  // BF16 forms, whose extra piece would not fit the registers, and one from
+  // 5 (BF16) or 6 (FP16) k steps on, where the accumulators alone take half
+  // the registers (p >= 11 still spills a little)
+  static constexpr int RGW = F16 ? (KST >= 6 ? 1 : 6) : (KST >= 5 ? 1 : M2LB_RG);
   static constexpr int RG = RB < RGW ? RB : RGW;
-  // Prefetch the next offset's B quads (a second register set) where the
-  // registers allow it.
-  static constexpr bool PREFETCH_B = KST * NP <= 9;
+  // Prefetch the next offset's B quads (a second register set) up to 3 k
+  // steps (p <= 8).  From 4 on (p = 9, 10) the second set made the compiler
+  // spill (84-112 bytes per lane), and the adaptive p = 10 M2L took 10.3 ms
+  // instead of 6.3 ms without it.
+  static constexpr bool PREFETCH_B = KST <= 3;
 };
 
 // F16: FP16 pieces of scaled operands (FMM_M2L_F16X2): per-offset FP32 chains
