@@ -417,6 +417,43 @@ __device__ __forceinline__ void irregular_harmonics(T x, T y, T z, T* re, T* im)
   }
 }
 
+// The same values, in the same order and arithmetic, handed to f(n, m, re, im)
+// as the recurrence produces them, so that only its last two terms stay live.
+template <int Q, typename T, typename F>
+__device__ __forceinline__ void irregular_harmonics_each(T x, T y, T z, F&& f) {
+  const T r2 = x * x + y * y + z * z;
+  const T ir2 = T(1) / r2;
+  T dre = T(1) / sqrt(r2), dim = T(0);  // I_m^m
+  f(0, 0, dre, dim);
+#pragma unroll
+  for (int m = 0; m <= Q; ++m) {
+    if (m > 0) {
+      const T s = T(-(2.0 * m - 1.0)) * ir2;
+      const T nre = s * (x * dre - y * dim);
+      const T nim = s * (x * dim + y * dre);
+      dre = nre;
+      dim = nim;
+      f(m, m, dre, dim);
+    }
+    if (m + 1 <= Q) {
+      const T s = T(2.0 * m + 1.0) * z * ir2;
+      T p1re = s * dre, p1im = s * dim, p0re = dre, p0im = dim;
+      f(m + 1, m, p1re, p1im);
+#pragma unroll
+      for (int n = m + 2; n <= Q; ++n) {
+        const T a = T(2.0 * n - 1.0) * z, b = T((double)(n + m - 1) * (double)(n - m - 1));
+        const T cre = (a * p1re - b * p0re) * ir2;
+        const T cim = (a * p1im - b * p0im) * ir2;
+        f(n, m, cre, cim);
+        p0re = p1re;
+        p0im = p1im;
+        p1re = cre;
+        p1im = cim;
+      }
+    }
+  }
+}
+
 // ---- passes ------------------------------------------------------------------
 
 // P2M at the leaves of levels >= 2, accumulated in FP64 from the FP64
@@ -459,65 +496,102 @@ __global__ __launch_bounds__(64) void k_p2m_adaptive(ATree t, const Rec<double>*
   }
 }
 
+// Sum over the 64 lanes of a wave of N values per lane (N a power of two,
+// >= 64), by halving: at each step the lanes exchange half of what they still
+// hold with the partner lane w apart, the lanes with bit w set keeping the
+// upper half.  Afterwards lane L holds in v[0 .. N/64) the sums of the values
+// N/64 L .. N/64 L + N/64 - 1.  N - 2 shuffles instead of 6 N, in a fixed order.
+template <int H, int W, typename T>
+__device__ __forceinline__ void halve_exchange(T* v) {
+  const bool up = (threadIdx.x & W) != 0;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const T send = up ? v[i] : v[i + H];
+    const T keep = up ? v[i + H] : v[i];
+    v[i] = keep + __shfl_xor(send, W);
+  }
+}
+template <int N, typename T>
+__device__ __forceinline__ void wave_sum_split(T* v) {
+  static_assert(N >= 64 && (N & (N - 1)) == 0, "N must be a power of two >= 64");
+  halve_exchange<N / 2, 32>(v);
+  halve_exchange<N / 4, 16>(v);
+  halve_exchange<N / 8, 8>(v);
+  halve_exchange<N / 16, 4>(v);
+  halve_exchange<N / 32, 2>(v);
+  halve_exchange<N / 64, 1>(v);
+}
+
 // P2L over X(b), added to the M2L result of b (units before the 1/h of L2L):
 // q conj(I_n^m(v)) with v the source's offset from b's centre in b's units.
-// One thread per box of the compact list xbox (the boxes whose X list is not
-// empty).
+// One wave per box of the compact list xbox (the boxes whose X list is not
+// empty).  The lanes take the (X entry, particle) pairs of the list in order,
+// 64 at a time, so a short leaf does not leave lanes idle; each lane keeps its
+// own partial expansion, and the wave sums them at the end (wave_sum_split).
 template <int P, typename T>
-__global__ __launch_bounds__(64) void k_p2l(ATree t, const uint32_t* __restrict__ xbox, int64_t nxbox,
+__global__ __launch_bounds__(64) void k_p2l(ATree t, const uint32_t* __restrict__ xbox,
                                             const uint32_t* __restrict__ xoff,
                                             const uint32_t* __restrict__ xidx,
                                             const Rec<T>* __restrict__ src, T* __restrict__ m2l) {
   constexpr int NC = (P + 1) * (P + 1);
-  constexpr int NT = (P + 1) * (P + 2) / 2;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nxbox) return;
-  const int64_t b = xbox[e];
+  constexpr int N = NC <= 64 ? 64 : (NC <= 128 ? 128 : 256);
+  constexpr int R = N / 64;
+  const int lane = threadIdx.x;
+  const int64_t b = xbox[blockIdx.x];
   const uint32_t k0 = xoff[b], k1 = xoff[b + 1];
   const int l = t.level[b];
   int bc[3];
   unpack_coord(t.coord[b], bc[0], bc[1], bc[2]);
-  T acc[NC];
+  T acc[N];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = T(0);
-  for (uint32_t k = k0; k < k1; ++k) {
-    const uint32_t c = xidx[k];
-    const int lc = t.level[c];  // < l
-    int cc[3];
-    unpack_coord(t.coord[c], cc[0], cc[1], cc[2]);
-    // centre offset in b's units: ((cc + 1/2) 2^(l - lc) - (bc + 1/2)), exact
-    const double sc = (double)(1 << (l - lc));
-    const T ox = (T)(((double)cc[0] + 0.5) * sc - ((double)bc[0] + 0.5));
-    const T oy = (T)(((double)cc[1] + 0.5) * sc - ((double)bc[1] + 0.5));
-    const T oz = (T)(((double)cc[2] + 0.5) * sc - ((double)bc[2] + 0.5));
-    const T sg = (T)sc;
-    const uint32_t s0 = t.range[2 * c], s1 = s0 + t.range[2 * c + 1];
-    for (uint32_t s = s0; s < s1; ++s) {
-      const Rec<T> r = src[s];
-      T re[NT], im[NT];
-      irregular_harmonics<P, T>(ox + sg * r.x, oy + sg * r.y, oz + sg * r.z, re, im);
-#pragma unroll
-      for (int nn = 0; nn <= P; ++nn) {
-        acc[cidx_re(nn, 0)] += r.q * re[tri(nn, 0)];
-#pragma unroll
-        for (int m = 1; m <= nn; ++m) {
-          acc[cidx_re(nn, m)] += r.q * re[tri(nn, m)];
-          acc[cidx_im(nn, m)] -= r.q * im[tri(nn, m)];
-        }
-      }
+  for (int c = 0; c < N; ++c) acc[c] = T(0);
+  // lane state: the X entry k of its current pair and the pairs before entry k
+  uint32_t k = k0, before = 0;
+  uint32_t cnt = k < k1 ? t.range[2 * xidx[k] + 1] : 0;
+  for (uint32_t base = 0;; base += 64) {
+    const uint32_t j = base + lane;
+    while (k < k1 && j >= before + cnt) {
+      before += cnt;
+      ++k;
+      cnt = k < k1 ? t.range[2 * xidx[k] + 1] : 0;
+    }
+    const bool active = k < k1;
+    if (!__any(active)) break;
+    if (active) {
+      const uint32_t c = xidx[k];
+      const int lc = t.level[c];  // < l
+      int cc[3];
+      unpack_coord(t.coord[c], cc[0], cc[1], cc[2]);
+      // centre offset in b's units: ((cc + 1/2) 2^(l - lc) - (bc + 1/2)), exact
+      const double sc = (double)(1 << (l - lc));
+      const T ox = (T)(((double)cc[0] + 0.5) * sc - ((double)bc[0] + 0.5));
+      const T oy = (T)(((double)cc[1] + 0.5) * sc - ((double)bc[1] + 0.5));
+      const T oz = (T)(((double)cc[2] + 0.5) * sc - ((double)bc[2] + 0.5));
+      const T sg = (T)sc;
+      const Rec<T> r = src[t.range[2 * c] + (j - before)];
+      irregular_harmonics_each<P, T>(ox + sg * r.x, oy + sg * r.y, oz + sg * r.z,
+                                     [&](int nn, int m, T re, T im) {
+                                       acc[cidx_re(nn, m)] += r.q * re;
+                                       if (m) acc[cidx_im(nn, m)] -= r.q * im;
+                                     });
     }
   }
+  wave_sum_split<N>(acc);
   T* o = m2l + b * NC;
 #pragma unroll
-  for (int c = 0; c < NC; ++c) o[c] += acc[c];
+  for (int i = 0; i < R; ++i)
+    if (R * lane + i < NC) o[R * lane + i] += acc[i];
 }
 
-// M2P over the W list of a leaf, added to the far field L2P wrote: one wave
-// per leaf of the compact list wbox (the leaves whose W list is not empty), a
-// lane per particle (64 at a time), the W entries in list order, so every
-// lane reads the same multipole at once.
+// M2P over the W list of a leaf, added to the far field L2P wrote: one
+// work-group of kM2pWaves waves per leaf of the compact list wbox (the leaves
+// whose W list is not empty), a lane per particle (64 at a time).  Wave v
+// takes the W entries v, v + kM2pWaves, ... in list order, so all lanes of a
+// wave read the same multipole at once; the waves' sums are added in wave
+// order through LDS.
+constexpr int kM2pWaves = 4;
 template <int P, typename T>
-__global__ __launch_bounds__(64) void k_m2p(ATree t, const uint32_t* __restrict__ wbox,
+__global__ __launch_bounds__(64 * kM2pWaves, sizeof(T) == 4 && P <= 10 ? 2 : 1) void k_m2p(ATree t, const uint32_t* __restrict__ wbox,
                                             const Rec<T>* __restrict__ src, int64_t n,
                                             const DevParams* __restrict__ dp,
                                             const T* __restrict__ mult,
@@ -527,19 +601,22 @@ __global__ __launch_bounds__(64) void k_m2p(ATree t, const uint32_t* __restrict_
                                             double* __restrict__ far_grad) {
   constexpr int MS = mstride_of((P + 1) * (P + 1));
   constexpr int NT1 = (P + 2) * (P + 3) / 2;
+  __shared__ double red[kM2pWaves][4][64];
+  // the wave index, uniform over the wave (so the multipole reads stay scalar)
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t leaf = wbox[blockIdx.x];  // a leaf whose W list is not empty
   const uint32_t k0 = woff[leaf], k1 = woff[leaf + 1];
   const uint32_t s0 = t.range[2 * leaf], cnt = t.range[2 * leaf + 1];
   const int l = t.level[leaf];
   for (uint32_t base = 0; base < cnt; base += 64) {
-    const uint32_t j = base + threadIdx.x;
+    const uint32_t j = base + lane;
     const bool active = j < cnt;
     const int64_t s = s0 + (active ? j : 0);
     const Rec<T> r = src[s];
     double phi = 0.0, g[3] = {0.0, 0.0, 0.0};
     int lc[3];
     unpack_coord(t.coord[leaf], lc[0], lc[1], lc[2]);
-    for (uint32_t k = k0; k < k1; ++k) {
+    for (uint32_t k = k0 + wv; k < k1; k += kM2pWaves) {
       const uint32_t w = widx[k];
       const int lw = t.level[w];  // > l
       int wc[3];
@@ -584,12 +661,25 @@ __global__ __launch_bounds__(64) void k_m2p(ATree t, const uint32_t* __restrict_
       g[1] += inv_hw * inv_hw * (double)gy;
       g[2] += inv_hw * inv_hw * (double)gz;
     }
-    if (active) {
-      far_phi[s] += phi;
-      far_grad[s] += g[0];
-      far_grad[n + s] += g[1];
-      far_grad[2 * n + s] += g[2];
+    red[wv][0][lane] = phi;
+    red[wv][1][lane] = g[0];
+    red[wv][2][lane] = g[1];
+    red[wv][3][lane] = g[2];
+    __syncthreads();
+    if (wv == 0 && active) {
+      double v[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        v[q] = red[0][q][lane];
+#pragma unroll
+        for (int w = 1; w < kM2pWaves; ++w) v[q] += red[w][q][lane];
+      }
+      far_phi[s] += v[0];
+      far_grad[s] += v[1];
+      far_grad[n + s] += v[2];
+      far_grad[2 * n + s] += v[3];
     }
+    __syncthreads();
   }
 }
 
@@ -638,16 +728,14 @@ struct P2LRun {
     const ATree t = tree_view(Pl);
     const uint32_t* xoff = wsp<uint32_t>(Pl, lay.a_off) + 2 * (lay.bmax + 1);
     if (Pl->nxbox == 0) return hipGetLastError();
-    const int64_t nx = Pl->nxbox;  // one thread per box with an X list
+    const unsigned nx = (unsigned)Pl->nxbox;  // one wave per box with an X list
     const uint32_t* xbox = wsp<uint32_t>(Pl, lay.a_xbox);
     if (Pl->mixed)
-      k_p2l<P, float><<<grid_for(nx, 64), 64, 0, s>>>(t, xbox, nx, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
-                                                      wsp<Rec<float>>(Pl, lay.src),
-                                                      wsp<float>(Pl, lay.m2l_out));
+      k_p2l<P, float><<<nx, 64, 0, s>>>(t, xbox, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
+                                        wsp<Rec<float>>(Pl, lay.src), wsp<float>(Pl, lay.m2l_out));
     else
-      k_p2l<P, double><<<grid_for(nx, 64), 64, 0, s>>>(t, xbox, nx, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
-                                                       wsp<Rec<double>>(Pl, lay.src),
-                                                       wsp<double>(Pl, lay.m2l_out));
+      k_p2l<P, double><<<nx, 64, 0, s>>>(t, xbox, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
+                                         wsp<Rec<double>>(Pl, lay.src), wsp<double>(Pl, lay.m2l_out));
     return hipGetLastError();
   }
 };
@@ -661,14 +749,14 @@ struct M2PRun {
     const uint32_t* woff = wsp<uint32_t>(Pl, lay.a_off) + (lay.bmax + 1);
     const int64_t n = Pl->n;
     const DevParams* dp = wsp<DevParams>(Pl, lay.params);
-    const unsigned nb = (unsigned)Pl->nwbox;  // one wave per leaf with a W list
+    const unsigned nb = (unsigned)Pl->nwbox;  // one work-group per leaf with a W list
     const uint32_t* wbox = wsp<uint32_t>(Pl, lay.a_wbox);
     if (Pl->mixed)
-      k_m2p<P, float><<<nb, 64, 0, s>>>(t, wbox, wsp<Rec<float>>(Pl, lay.src), n, dp,
+      k_m2p<P, float><<<nb, 64 * kM2pWaves, 0, s>>>(t, wbox, wsp<Rec<float>>(Pl, lay.src), n, dp,
                                         wsp<float>(Pl, lay.mult32), woff, wsp<uint32_t>(Pl, lay.a_widx),
                                         wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
     else
-      k_m2p<P, double><<<nb, 64, 0, s>>>(t, wbox, wsp<Rec<double>>(Pl, lay.src), n, dp,
+      k_m2p<P, double><<<nb, 64 * kM2pWaves, 0, s>>>(t, wbox, wsp<Rec<double>>(Pl, lay.src), n, dp,
                                          wsp<double>(Pl, lay.mult64), woff, wsp<uint32_t>(Pl, lay.a_widx),
                                          wsp<double>(Pl, lay.far_phi), wsp<double>(Pl, lay.far_grad));
     return hipGetLastError();
