@@ -522,19 +522,50 @@ __device__ __forceinline__ void wave_sum_split(T* v) {
   halve_exchange<N / 64, 1>(v);
 }
 
+// Coefficients of degree <= p whose order m lies in [m0, m1), in the order of
+// the global index (cidx_re / cidx_im): their number, and the position of one
+// of them in that list.
+__host__ __device__ constexpr int orders_count(int p, int m0, int m1) {
+  int c = 0;
+  for (int n = 0; n <= p; ++n)
+    for (int m = m0; m < m1 && m <= n; ++m) c += m ? 2 : 1;
+  return c;
+}
+__host__ __device__ constexpr int orders_pos(int m0, int m1, int n, int m, bool im) {
+  int c = 0;
+  for (int nn = 0; nn < n; ++nn)
+    for (int mm = m0; mm < m1 && mm <= nn; ++mm) c += mm ? 2 : 1;
+  for (int mm = m0; mm < m; ++mm) c += mm ? 2 : 1;
+  return c + (im ? 1 : 0);
+}
+// Split of the orders 0..p into [0, m) and [m, p]: the m that halves the
+// coefficients most evenly.
+__host__ __device__ constexpr int orders_split(int p) {
+  int best = 1;
+  for (int m = 1; m <= p; ++m) {
+    const int a = 2 * orders_count(p, 0, m) - (p + 1) * (p + 1);
+    const int b = 2 * orders_count(p, 0, best) - (p + 1) * (p + 1);
+    if ((a < 0 ? -a : a) < (b < 0 ? -b : b)) best = m;
+  }
+  return best;
+}
+
 // P2L over X(b), added to the M2L result of b (units before the 1/h of L2L):
-// q conj(I_n^m(v)) with v the source's offset from b's centre in b's units.
+// q conj(I_n^m(v)) with v the source's offset from b's centre in b's units,
+// for the orders m in [M0, M1) (the coefficients are split over two launches
+// by order, so that a lane holds fewer sums and more waves fit a SIMD).
 // One wave per box of the compact list xbox (the boxes whose X list is not
 // empty).  The lanes take the (X entry, particle) pairs of the list in order,
 // 64 at a time, so a short leaf does not leave lanes idle; each lane keeps its
 // own partial expansion, and the wave sums them at the end (wave_sum_split).
-template <int P, typename T>
+template <int P, typename T, int M0, int M1>
 __global__ __launch_bounds__(64) void k_p2l(ATree t, const uint32_t* __restrict__ xbox,
                                             const uint32_t* __restrict__ xoff,
                                             const uint32_t* __restrict__ xidx,
                                             const Rec<T>* __restrict__ src, T* __restrict__ m2l) {
   constexpr int NC = (P + 1) * (P + 1);
-  constexpr int N = NC <= 64 ? 64 : (NC <= 128 ? 128 : 256);
+  constexpr int NA = orders_count(P, M0, M1);
+  constexpr int N = NA <= 64 ? 64 : (NA <= 128 ? 128 : 256);
   constexpr int R = N / 64;
   const int lane = threadIdx.x;
   const int64_t b = xbox[blockIdx.x];
@@ -569,18 +600,35 @@ __global__ __launch_bounds__(64) void k_p2l(ATree t, const uint32_t* __restrict_
       const T oz = (T)(((double)cc[2] + 0.5) * sc - ((double)bc[2] + 0.5));
       const T sg = (T)sc;
       const Rec<T> r = src[t.range[2 * c] + (j - before)];
-      irregular_harmonics_each<P, T>(ox + sg * r.x, oy + sg * r.y, oz + sg * r.z,
-                                     [&](int nn, int m, T re, T im) {
-                                       acc[cidx_re(nn, m)] += r.q * re;
-                                       if (m) acc[cidx_im(nn, m)] -= r.q * im;
-                                     });
+      irregular_harmonics_each<P, T>(
+          ox + sg * r.x, oy + sg * r.y, oz + sg * r.z, [&](int nn, int m, T re, T im) {
+            if (m < M0 || m >= M1) return;
+            acc[orders_pos(M0, M1, nn, m, false)] += r.q * re;
+            if (m) acc[orders_pos(M0, M1, nn, m, true)] -= r.q * im;
+          });
     }
   }
   wave_sum_split<N>(acc);
+  // local index u -> global coefficient index
   T* o = m2l + b * NC;
 #pragma unroll
-  for (int i = 0; i < R; ++i)
-    if (R * lane + i < NC) o[R * lane + i] += acc[i];
+  for (int i = 0; i < R; ++i) {
+    const int u = R * lane + i;
+    if (u >= NA) continue;
+    int c = 0, seen = 0;
+    for (int nn = 0; nn <= P; ++nn) {
+      const int here = orders_count(nn, M0, M1) - orders_count(nn - 1, M0, M1);
+      if (u < seen + here) {
+        const int v = u - seen;  // position within degree nn: m0 (re[, im]), m0 + 1 ...
+        const int m = M0 == 0 ? (v + 1) / 2 : M0 + v / 2;
+        const bool im = M0 == 0 ? (v > 0 && v % 2 == 0) : (v % 2 == 1);
+        c = im ? cidx_im(nn, m) : cidx_re(nn, m);
+        break;
+      }
+      seen += here;
+    }
+    o[c] += acc[i];
+  }
 }
 
 // M2P over the W list of a leaf, added to the far field L2P wrote: one
@@ -730,12 +778,21 @@ struct P2LRun {
     if (Pl->nxbox == 0) return hipGetLastError();
     const unsigned nx = (unsigned)Pl->nxbox;  // one wave per box with an X list
     const uint32_t* xbox = wsp<uint32_t>(Pl, lay.a_xbox);
-    if (Pl->mixed)
-      k_p2l<P, float><<<nx, 64, 0, s>>>(t, xbox, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
-                                        wsp<Rec<float>>(Pl, lay.src), wsp<float>(Pl, lay.m2l_out));
-    else
-      k_p2l<P, double><<<nx, 64, 0, s>>>(t, xbox, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
-                                         wsp<Rec<double>>(Pl, lay.src), wsp<double>(Pl, lay.m2l_out));
+    // FP32: two launches, over the orders below and from the split (p >= 6),
+    // which took the clusters P2L at p = 10 from 1 to 3 waves per SIMD and
+    // 1.6 to 1.4 ms; FP64 stays at one wave per SIMD either way, and there the
+    // second pass over the pairs made it slower (2.3 -> 4.4 ms), so one launch
+    constexpr int MS = P >= 6 ? orders_split(P) : P + 1;
+    if (Pl->mixed) {
+      k_p2l<P, float, 0, MS><<<nx, 64, 0, s>>>(t, xbox, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
+                                               wsp<Rec<float>>(Pl, lay.src), wsp<float>(Pl, lay.m2l_out));
+      if (MS <= P)
+        k_p2l<P, float, MS, P + 1><<<nx, 64, 0, s>>>(t, xbox, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
+                                                     wsp<Rec<float>>(Pl, lay.src), wsp<float>(Pl, lay.m2l_out));
+    } else {
+      k_p2l<P, double, 0, P + 1><<<nx, 64, 0, s>>>(t, xbox, xoff, wsp<uint32_t>(Pl, lay.a_xidx),
+                                                   wsp<Rec<double>>(Pl, lay.src), wsp<double>(Pl, lay.m2l_out));
+    }
     return hipGetLastError();
   }
 };
