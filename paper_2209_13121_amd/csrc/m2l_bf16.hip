@@ -167,7 +167,8 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
                                                      const u32x4* __restrict__ ops,
                                                      float* __restrict__ out,
                                                      const float* __restrict__ mscale,
-                                                     const float* __restrict__ rowf) {
+                                                     const float* __restrict__ rowf,
+                                                     float* __restrict__ half_out) {
   typedef Shape<P, NP, F16, AD> S;
   typedef Prod<NP> PR;
   constexpr int NC = S::NC, RB = S::RB, RP = S::RP, KST = S::KST, QR = S::QR;
@@ -181,6 +182,11 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   m2l::TileT<AD> tl;
   if (!tl.setup(a, wave * 16 + col, sSlot, sBox)) return;  // uniform over the work-group
   const int pi = tl.pi;
+  // offsets [i0, i1): all of them, or one part of a split group (the
+  // adaptive tree splits none)
+  const bool whole = AD || tl.part < 0;
+  const int i0 = whole ? 0 : tl.part * kIL / kM2lParts;
+  const int i1 = whole ? kIL : (tl.part + 1) * kIL / kM2lParts;
   const u32x4* mlev = multq + tl.lvl_off * QR;
 
   f32x4 sum[RB], comp[RB], acc[RB];
@@ -261,11 +267,11 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   // Pipeline over the class's offsets: offset i is computed while the
   // operator of the next stage and the B quads of offset i + 1 are loaded and
   // the source slot of offset i + 2 is looked up.
-  int i = 0, dx, dy, dz, ndx, ndy, ndz;
-  int op = m2l::il_offset(pi, 0, dx, dy, dz);
-  int nop = m2l::il_offset(pi, 1, ndx, ndy, ndz);
-  m2l::Src s_cur = tl.lookup(sSlot, 0, dx, dy, dz);
-  m2l::Src s_next = tl.lookup(sSlot, 1, ndx, ndy, ndz);
+  int i = i0, dx, dy, dz, ndx, ndy, ndz;
+  int op = m2l::il_offset(pi, i0, dx, dy, dz);
+  int nop = m2l::il_offset(pi, i0 + 1, ndx, ndy, ndz);
+  m2l::Src s_cur = tl.lookup(sSlot, i0, dx, dy, dz);
+  m2l::Src s_next = tl.lookup(sSlot, i0 + 1, ndx, ndy, ndz);
   bool wave_any = false;
   float sc_cur = scale_of(s_cur), sc_next = 0.f;
   if (PB) {
@@ -278,9 +284,9 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   int cur = 0;
 
   auto do_offset = [&](u32x4* bc, u32x4* bn) -> bool {
-    const bool more = i + 1 < kIL;
+    const bool more = i + 1 < i1;
     int fdx, fdy, fdz;
-    const int fi = i + 2 < kIL ? i + 2 : kIL - 1;
+    const int fi = i + 2 < i1 ? i + 2 : i1 - 1;
     const int fop = m2l::il_offset(pi, fi, fdx, fdy, fdz);
     const m2l::Src s_far = tl.lookup(sSlot, fi, fdx, fdy, fdz);
     if (!PB) {
@@ -309,7 +315,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
             acc[r] = f32x4{0, 0, 0, 0};
           }
         }
-        if ((i + 1) % kGroupF16 == 0 || !more) {
+        if ((i + 1 - i0) % kGroupF16 == 0 || !more) {
 #pragma unroll
           for (int r = 0; r < RB; ++r) {
             sum[r] += comp[r];
@@ -356,7 +362,11 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   }
 
   if (!tl.col_ok) return;
-  float* o = out + (tl.lvl_off + tl.target_slot(a)) * NC;
+  // parts 1.. of a split group: into their slots of half_out, added to part
+  // 0's result by k_m2l_add_half after the launch
+  float* o = !whole && tl.part > 0
+                 ? half_out + ((tl.sidx * (kM2lParts - 1) + tl.part - 1) * m2l::kTargetsPerGroup + wave * 16 + col) * NC
+                 : out + (tl.lvl_off + tl.target_slot(a)) * NC;
   // Accumulator layout of the 16x16 FP32-output MFMAs: lane l holds column
   // l % 16, rows 4 (l / 16) + i.
 #pragma unroll
@@ -366,6 +376,45 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
       const int row = 16 * r + 4 * kg + e;
       if (row < NC) o[row] = F16 ? sum[r][e] * rowf[row] : sum[r][e];
     }
+}
+
+// Parts 1.. of the split groups into the M2L result: one wave per (split
+// group, target of its tile), the lanes along the target's row (the same
+// decoding as the M2L kernel); each sum is part 0 + part 1 + ..., in that
+// order.
+__global__ __launch_bounds__(64) void k_m2l_add_half(m2l::Args a, int nc, const float* __restrict__ half_out,
+                                                     float* __restrict__ out) {
+  const int64_t per_xcd = (a.ngroups + 7) / 8;
+  const int64_t sidx = blockIdx.x / m2l::kTargetsPerGroup;
+  const int tix = (int)(blockIdx.x % m2l::kTargetsPerGroup);
+  const int64_t xcd = sidx / a.ksplit, j = sidx % a.ksplit;
+  m2l::TileT<false> tl;
+  if (!tl.locate(a, xcd * per_xcd + per_xcd - a.ksplit + j, tix) || !tl.col_ok) return;
+  float* o = out + (tl.lvl_off + tl.target_slot(a)) * nc;
+  for (int r = threadIdx.x; r < nc; r += 64) {
+    float v = o[r];
+    for (int q = 1; q < kM2lParts; ++q)
+      v += half_out[((sidx * (kM2lParts - 1) + q - 1) * m2l::kTargetsPerGroup + tix) * nc + r];
+    o[r] = v;
+  }
+}
+
+// Work decomposition of the split M2L: on the uniform tree the last
+// kM2lSplitPerXcd groups of every XCD (fewer when an XCD has fewer) run in
+// kM2lParts parts.  Measured at 2^20 charges, depth 6, p 8 (2,352 groups,
+// about 9.2 rounds of the 256 CUs): the nearly empty last round cost 0.36 ms
+// of 4.0; two halves took the pass to 3.80 ms.
+m2l::Args split_args(fmm_plan_s* Pl) {
+  m2l::Args a = m2l::make_args(Pl);
+  const int64_t per_xcd = (a.ngroups + 7) / 8;
+  a.ksplit = Pl->adaptive ? 0 : (per_xcd < kM2lSplitPerXcd ? per_xcd : kM2lSplitPerXcd);
+  return a;
+}
+
+void add_halves(fmm_plan_s* Pl, const m2l::Args& a, hipStream_t s) {
+  if (a.ksplit == 0) return;
+  k_m2l_add_half<<<(unsigned)(8 * a.ksplit * m2l::kTargetsPerGroup), 64, 0, s>>>(
+      a, Pl->nc, wsp<float>(Pl, Pl->lay.m2l_half), wsp<float>(Pl, Pl->lay.m2l_out));
 }
 
 template <int P>
@@ -383,16 +432,17 @@ struct M2LBfRun {
         wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox,
         mq + box0 * qr);
     prof_end(Pl, s);
-    const m2l::Args a = m2l::make_args(Pl);
+    const m2l::Args a = split_args(Pl);
     prof_begin(Pl, FMM_PHASE_M2L, s);
     if (Pl->adaptive)
       k_m2l_bf<P, NP, false, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-          nullptr, nullptr);
+          nullptr, nullptr, nullptr);
     else
       k_m2l_bf<P, NP, false, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-          nullptr, nullptr);
+          nullptr, nullptr, wsp<float>(Pl, lay.m2l_half));
+    add_halves(Pl, a, s);
     prof_end(Pl, s);
     return hipGetLastError();
   }
@@ -409,16 +459,17 @@ struct M2LBfRun {
         wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox, lpb,
         wsp<float>(Pl, lay.f16_colf), mq + box0 * qr, msc + box0);
     prof_end(Pl, s);
-    const m2l::Args a = m2l::make_args(Pl);
+    const m2l::Args a = split_args(Pl);
     prof_begin(Pl, FMM_PHASE_M2L, s);
     if (Pl->adaptive)
       k_m2l_bf<P, 2, true, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-          msc, wsp<float>(Pl, lay.f16_rowf));
+          msc, wsp<float>(Pl, lay.f16_rowf), nullptr);
     else
       k_m2l_bf<P, 2, true, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-          msc, wsp<float>(Pl, lay.f16_rowf));
+          msc, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
+    add_halves(Pl, a, s);
     prof_end(Pl, s);
     return hipGetLastError();
   }

@@ -61,6 +61,7 @@ struct Args {
   int64_t exp_off[FMM_DEPTH_MAX + 2];    // first row of each level in the expansion arrays
   int64_t group_off[FMM_DEPTH_MAX + 2];  // first work-group of each level (levels 2..L)
   int64_t ngroups;
+  int64_t ksplit;  // work-groups per XCD run as two halves (0: none)
   const uint32_t* c2s;
   const uint32_t* s2c;
   // Adaptive tree only.  The targets of level l
@@ -93,6 +94,7 @@ inline Args make_args(fmm_plan_s* Pl) {
   }
   a.group_off[a.L + 1] = g;
   a.ngroups = g;
+  a.ksplit = 0;
   a.c2s = wsp<uint32_t>(Pl, lay.coord2slot);
   a.s2c = wsp<uint32_t>(Pl, lay.slot2coord);
   a.tgt = Pl->adaptive ? wsp<uint32_t>(Pl, lay.a_tgt) : nullptr;
@@ -104,7 +106,29 @@ inline Args make_args(fmm_plan_s* Pl) {
   }
   return a;
 }
-inline unsigned grid_of(const Args& a) { return (unsigned)(((a.ngroups + 7) / 8) * 8); }
+inline unsigned grid_of(const Args& a) {
+  return (unsigned)(((a.ngroups + 7) / 8 + (kM2lParts - 1) * a.ksplit) * 8);
+}
+
+// Hardware group b -> logical group lg.  XCD-aware order: group b runs on XCD
+// b % 8, and each XCD gets a contiguous range of per_xcd logical groups.  With
+// ksplit > 0 the last ksplit of them are each run by kM2lParts consecutive
+// hardware groups, parts 0 .. kM2lParts - 1 (split index sidx = xcd * ksplit
+// + j for the j-th); part = -1 for a whole group.
+__host__ __device__ inline void decode_group(const Args& a, int64_t b, int64_t& lg, int& part,
+                                             int64_t& sidx) {
+  const int64_t per_xcd = (a.ngroups + 7) / 8, xcd = b % 8, r = b / 8, full = per_xcd - a.ksplit;
+  if (r < full) {
+    lg = xcd * per_xcd + r;
+    part = -1;
+    sidx = 0;
+  } else {
+    const int64_t h = r - full;
+    lg = xcd * per_xcd + full + h / kM2lParts;
+    part = (int)(h % kM2lParts);
+    sidx = xcd * a.ksplit + h / kM2lParts;
+  }
+}
 
 // Slots of every source box a work-group can touch: 128 consecutive aligned
 // Hilbert slots of the parent level are two face-adjacent 4^3 blocks, so the
@@ -134,37 +158,19 @@ struct TileT {
   int64_t tile;                                // tile number within the level and class
   const uint32_t* vt;                          // adaptive: this lane's source-row column
   int64_t trow;                                // adaptive: this lane's target row
+  int part;                                    // -1 whole group, else its part (split M2L)
+  int64_t sidx;                                // split index of a part group
 
   // Decode the group, find this lane's target (number tix of the tile's 128)
   // and (uniform tree) stage the halo's slots in sSlot.  Returns false,
   // uniformly over the work-group, for a group past the end.  The uniform form
   // contains barriers.
   __device__ __forceinline__ bool setup(const Args& a, int tix, uint32_t* sSlot, int* sBox) {
-    // XCD-aware order: hardware group b runs on XCD b % 8; each XCD gets a
-    // contiguous range of logical groups.
-    const int64_t per_xcd = (a.ngroups + 7) / 8;
-    const int64_t lg = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (lg >= a.ngroups) return false;
-    l = 2;
-    while (l < a.L && lg >= a.group_off[l + 1]) ++l;
-    if constexpr (AD) {  // no halo, the source rows come from the table
-      const int64_t idx = lg - a.group_off[l];
-      pi = (int)(idx % 8);
-      tile = idx / 8;
-      lvl_off = a.exp_off[l];
-      retarget(a, tix);
-      return true;
-    }
-    // The 8 parity classes of a tile are consecutive groups, so they run close
-    // together on one XCD and share its L2 for the tile's sources.
-    const int64_t idx = lg - a.group_off[l];
-    pi = (int)(idx % 8);
-    tile = idx / 8;
+    int64_t lg;
+    decode_group(a, blockIdx.x, lg, part, sidx);
+    if (!locate(a, lg, tix)) return false;
+    if constexpr (AD) return true;  // no halo, the source rows come from the table
     const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
-    nb = 1 << l;
-    lvl_off = a.exp_off[l];
-    dense_off = a.lvl_off[l];
-    retarget(a, tix);
     const int tid = threadIdx.x;
     if (tid < 6) sBox[tid] = tid < 3 ? nb : -1;
     __syncthreads();
@@ -192,6 +198,24 @@ struct TileT {
       sSlot[e] = c2s[lex_index(x, y, z, l)];
     }
     __syncthreads();
+    return true;
+  }
+
+  // Level, class and tile of logical group lg, and this lane's target (number
+  // tix of the tile); false past the last group.  No barriers, no halo.
+  // The 8 parity classes of a tile are consecutive groups, so they run close
+  // together on one XCD and share its L2 for the tile's sources.
+  __device__ __forceinline__ bool locate(const Args& a, int64_t lg, int tix) {
+    if (lg >= a.ngroups) return false;
+    l = 2;
+    while (l < a.L && lg >= a.group_off[l + 1]) ++l;
+    const int64_t idx = lg - a.group_off[l];
+    pi = (int)(idx % 8);
+    tile = idx / 8;
+    nb = 1 << l;
+    lvl_off = a.exp_off[l];
+    dense_off = a.lvl_off[l];
+    retarget(a, tix);
     return true;
   }
 
