@@ -179,7 +179,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  m2l::TileT<AD> tl;
+  m2l::TileT<AD, !AD> tl;  // the uniform tree splits the tail groups
   if (!tl.setup(a, wave * 16 + col, sSlot, sBox)) return;  // uniform over the work-group
   const int pi = tl.pi;
   // offsets [i0, i1): all of them, or one part of a split group (the
@@ -388,7 +388,7 @@ __global__ __launch_bounds__(64) void k_m2l_add_half(m2l::Args a, int nc, const 
   const int64_t sidx = blockIdx.x / m2l::kTargetsPerGroup;
   const int tix = (int)(blockIdx.x % m2l::kTargetsPerGroup);
   const int64_t xcd = sidx / a.ksplit, j = sidx % a.ksplit;
-  m2l::TileT<false> tl;
+  m2l::TileT<false, true> tl;
   if (!tl.locate(a, xcd * per_xcd + per_xcd - a.ksplit + j, tix) || !tl.col_ok) return;
   float* o = out + (tl.lvl_off + tl.target_slot(a)) * nc;
   for (int r = threadIdx.x; r < nc; r += 64) {

@@ -147,7 +147,9 @@ constexpr uint32_t kAbsent = 0x80000000u;
 // A lane's view of its work-group's tile.  AD: adaptive tree (targets from the
 // per-class lists, sources from the table; no halo), fixed at compile time so
 // that the uniform form carries none of it.
-template <bool AD>
+// SPLIT: the work-group may be one part of a split group (decode_group);
+// otherwise the plain XCD-aware mapping.
+template <bool AD, bool SPLIT = false>
 struct TileT {
   int l, pi, nb;
   int tx, ty, tz;  // this lane's target box (meaningful when col_ok)
@@ -167,10 +169,39 @@ struct TileT {
   // contains barriers.
   __device__ __forceinline__ bool setup(const Args& a, int tix, uint32_t* sSlot, int* sBox) {
     int64_t lg;
-    decode_group(a, blockIdx.x, lg, part, sidx);
-    if (!locate(a, lg, tix)) return false;
+    if constexpr (SPLIT) {
+      decode_group(a, blockIdx.x, lg, part, sidx);
+      if (!locate(a, lg, tix)) return false;
+    } else {
+      // (the same steps as locate, written out: the FP32 / FP64 kernel's main
+      // loop was measured 7 % slower when they were shared)
+      part = -1;
+      sidx = 0;
+      const int64_t per_xcd = (a.ngroups + 7) / 8;
+      lg = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+      if (lg >= a.ngroups) return false;
+      l = 2;
+      while (l < a.L && lg >= a.group_off[l + 1]) ++l;
+      if constexpr (AD) {
+        const int64_t idx = lg - a.group_off[l];
+        pi = (int)(idx % 8);
+        tile = idx / 8;
+        lvl_off = a.exp_off[l];
+        retarget(a, tix);
+        return true;
+      }
+      const int64_t idx = lg - a.group_off[l];
+      pi = (int)(idx % 8);
+      tile = idx / 8;
+    }
     if constexpr (AD) return true;  // no halo, the source rows come from the table
     const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
+    if constexpr (!SPLIT) {
+      nb = 1 << l;
+      lvl_off = a.exp_off[l];
+      dense_off = a.lvl_off[l];
+      retarget(a, tix);
+    }
     const int tid = threadIdx.x;
     if (tid < 6) sBox[tid] = tid < 3 ? nb : -1;
     __syncthreads();
