@@ -117,8 +117,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
       const size_t rq = (size_t)m2lb_row_quads(nc, np);
       lay->multb = take(16 * NB * rq);
       lay->op_m2lb = take(16 * (size_t)kNumM2LOps * m2lb_op_quads(nc, np, adaptive));
-      if (!adaptive)
-        lay->m2l_half = take(sizeof(float) * 8 * kM2lSplitPerXcd * (kM2lParts - 1) * 128 * (size_t)nc);
+      lay->m2l_half = take(sizeof(float) * 8 * kM2lSplitPerXcd * (kM2lParts - 1) * 128 * (size_t)nc);
     }
     if (m2l_is_f16(cfg)) {
       const size_t rp = (size_t)m2lb_rows(nc), kp = (size_t)32 * m2lb_ksteps(nc);

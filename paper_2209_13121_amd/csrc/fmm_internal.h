@@ -12,7 +12,7 @@ namespace fmm {
 constexpr int kBlock = 256;          // default work-group size (4 wave64)
 constexpr int kNumM2LOps = 316;      // offsets in [-3,3]^3 \ [-1,1]^3
 constexpr int kIL = 189;             // interaction-list offsets per parity class
-// Split M2L on the uniform tree: at most this many work-groups per XCD, the
+// Split M2L (split forms): at most this many work-groups per XCD, the
 // last ones dispatched, each run as kM2lParts part work-groups over offsets
 // [q kIL / kM2lParts, (q + 1) kIL / kM2lParts) (the launch's last round then
 // ends nearly full instead of nearly empty).
@@ -110,7 +110,7 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t op_m2l64, op_m2l32;
   size_t multb;            // split M2L: multipoles as BF16 / FP16 pieces, all boxes
   size_t op_m2lb;          // split M2L: operators as BF16 / FP16 pieces
-  size_t m2l_half;         // split M2L, uniform tree: parts 1.. of the split tail groups
+  size_t m2l_half;         // split M2L: parts 1.. of the split tail groups
   size_t f16_mscale;       // FP16 M2L: per box, the inverse of its power-of-two scale
   size_t f16_rowf;         // FP16 M2L: per operator row, the inverse row scale
   size_t f16_colf;         // FP16 M2L: per k, the inverse column scale (applied to multipoles)

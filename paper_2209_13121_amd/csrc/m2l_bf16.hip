@@ -179,12 +179,11 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
-  m2l::TileT<AD, !AD> tl;  // the uniform tree splits the tail groups
+  m2l::TileT<AD, true> tl;  // the tail groups may be split
   if (!tl.setup(a, wave * 16 + col, sSlot, sBox)) return;  // uniform over the work-group
   const int pi = tl.pi;
-  // offsets [i0, i1): all of them, or one part of a split group (the
-  // adaptive tree splits none)
-  const bool whole = AD || tl.part < 0;
+  // offsets [i0, i1): all of them, or one part of a split group
+  const bool whole = tl.part < 0;
   const int i0 = whole ? 0 : tl.part * kIL / kM2lParts;
   const int i1 = whole ? kIL : (tl.part + 1) * kIL / kM2lParts;
   const u32x4* mlev = multq + tl.lvl_off * QR;
@@ -382,13 +381,14 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
 // group, target of its tile), the lanes along the target's row (the same
 // decoding as the M2L kernel); each sum is part 0 + part 1 + ..., in that
 // order.
+template <bool AD>
 __global__ __launch_bounds__(64) void k_m2l_add_half(m2l::Args a, int nc, const float* __restrict__ half_out,
                                                      float* __restrict__ out) {
   const int64_t per_xcd = (a.ngroups + 7) / 8;
   const int64_t sidx = blockIdx.x / m2l::kTargetsPerGroup;
   const int tix = (int)(blockIdx.x % m2l::kTargetsPerGroup);
   const int64_t xcd = sidx / a.ksplit, j = sidx % a.ksplit;
-  m2l::TileT<false, true> tl;
+  m2l::TileT<AD, true> tl;
   if (!tl.locate(a, xcd * per_xcd + per_xcd - a.ksplit + j, tix) || !tl.col_ok) return;
   float* o = out + (tl.lvl_off + tl.target_slot(a)) * nc;
   for (int r = threadIdx.x; r < nc; r += 64) {
@@ -399,22 +399,26 @@ __global__ __launch_bounds__(64) void k_m2l_add_half(m2l::Args a, int nc, const 
   }
 }
 
-// Work decomposition of the split M2L: on the uniform tree the last
-// kM2lSplitPerXcd groups of every XCD (fewer when an XCD has fewer) run in
-// kM2lParts parts.  Measured at 2^20 charges, depth 6, p 8 (2,352 groups,
+// Work decomposition of the split M2L: the last kM2lSplitPerXcd groups of
+// every XCD (fewer when an XCD has fewer) run in kM2lParts parts.  Measured at 2^20 charges, depth 6, p 8 (2,352 groups,
 // about 9.2 rounds of the 256 CUs): the nearly empty last round cost 0.36 ms
 // of 4.0; two halves took the pass to 3.80 ms.
 m2l::Args split_args(fmm_plan_s* Pl) {
   m2l::Args a = m2l::make_args(Pl);
   const int64_t per_xcd = (a.ngroups + 7) / 8;
-  a.ksplit = Pl->adaptive ? 0 : (per_xcd < kM2lSplitPerXcd ? per_xcd : kM2lSplitPerXcd);
+  a.ksplit = per_xcd < kM2lSplitPerXcd ? per_xcd : kM2lSplitPerXcd;
   return a;
 }
 
 void add_halves(fmm_plan_s* Pl, const m2l::Args& a, hipStream_t s) {
   if (a.ksplit == 0) return;
-  k_m2l_add_half<<<(unsigned)(8 * a.ksplit * m2l::kTargetsPerGroup), 64, 0, s>>>(
-      a, Pl->nc, wsp<float>(Pl, Pl->lay.m2l_half), wsp<float>(Pl, Pl->lay.m2l_out));
+  const unsigned grid = (unsigned)(8 * a.ksplit * m2l::kTargetsPerGroup);
+  if (Pl->adaptive)
+    k_m2l_add_half<true><<<grid, 64, 0, s>>>(a, Pl->nc, wsp<float>(Pl, Pl->lay.m2l_half),
+                                             wsp<float>(Pl, Pl->lay.m2l_out));
+  else
+    k_m2l_add_half<false><<<grid, 64, 0, s>>>(a, Pl->nc, wsp<float>(Pl, Pl->lay.m2l_half),
+                                              wsp<float>(Pl, Pl->lay.m2l_out));
 }
 
 template <int P>
@@ -437,7 +441,7 @@ struct M2LBfRun {
     if (Pl->adaptive)
       k_m2l_bf<P, NP, false, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-          nullptr, nullptr, nullptr);
+          nullptr, nullptr, wsp<float>(Pl, lay.m2l_half));
     else
       k_m2l_bf<P, NP, false, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
@@ -464,7 +468,7 @@ struct M2LBfRun {
     if (Pl->adaptive)
       k_m2l_bf<P, 2, true, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-          msc, wsp<float>(Pl, lay.f16_rowf), nullptr);
+          msc, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
     else
       k_m2l_bf<P, 2, true, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
