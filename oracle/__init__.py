@@ -36,10 +36,12 @@ def load_library(path):
                                       ctypes.POINTER(ctypes.c_int32), d, d]
     lib.oracle_chain.argtypes = [ctypes.c_int, ctypes.c_int, i64, d, d, d, d, d, i64, d, d,
                                  ctypes.c_void_p]
+    lib.oracle_fmm_probe.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, d, ctypes.c_double,
+                                     i64, ctypes.c_void_p, d, d]
     lib.oracle_fmm_adaptive.argtypes = [i64, d, d, ctypes.c_int, ctypes.c_int, ctypes.c_int, d,
                                         ctypes.c_double, d, d, d, ctypes.POINTER(i64)]
     for f in (lib.oracle_direct, lib.oracle_fmm, lib.oracle_leaf_cells, lib.oracle_chain,
-              lib.oracle_fmm_adaptive):
+              lib.oracle_fmm_adaptive, lib.oracle_fmm_probe):
         f.restype = ctypes.c_int
     return lib
 
@@ -107,6 +109,26 @@ def fmm(pos, q, depth, p, lo=(0.0, 0.0, 0.0), side=1.0, targets=None, lib=None):
     if st:
         raise OracleError(st)
     return phi, force, (float(e[0]) if t is None else None)
+
+
+def fmm_probe(pos, q, depth, p, idx, y, lo=(0.0, 0.0, 0.0), side=1.0):
+    """FMM potential phi'(y_k) felt by particle idx[k] if it sat at y_k (same
+    leaf), from every other particle, with the tree and expansions of the
+    unmoved system.  Central differences of the FMM energy in x_i are then
+    q_i (phi'(x_i + h e) - phi'(x_i - h e)) / 2h (see fmm_oracle.c)."""
+    pos = _f64(pos, (-1, 3))
+    q = _f64(q)
+    lo = _f64(lo)
+    t, tp = _targets(idx)
+    y = _f64(y, (-1, 3))
+    if len(y) != len(t):
+        raise ValueError("one displaced position per index")
+    out = np.zeros(len(t))
+    st = _lib().oracle_fmm_probe(len(q), _dp(pos), _dp(q), int(depth), int(p), _dp(lo),
+                                 float(side), len(t), tp, _dp(y), _dp(out))
+    if st:
+        raise OracleError(st)
+    return out
 
 
 def leaf_cells(pos, depth, lo=(0.0, 0.0, 0.0), side=1.0):

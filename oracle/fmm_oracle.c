@@ -463,12 +463,11 @@ static void m2l_box(otree *T, int l, int ix, int iy, int iz) {
       }
 }
 
-/* Near field of particle i (in leaf (cx,cy,cz)): sum over the 27 neighbour
- * leaves, j != i. */
-static int p2p_particle(const otree *T, const double *pos, const double *q, int64_t i,
-                        double *phi, double grad[3]) {
+/* Near field at point x of leaf (cx,cy,cz) from the 27 neighbour leaves,
+ * skipping particle `skip' (the target itself; -1 for none). */
+static int p2p_point(const otree *T, const double *pos, const double *q, int cx, int cy, int cz,
+                     const double x[3], int64_t skip, double *phi, double grad[3]) {
   const int L = T->L, nb = 1 << L;
-  const int cx = T->cell[3 * i], cy = T->cell[3 * i + 1], cz = T->cell[3 * i + 2];
   ksum f = {0, 0}, gx = {0, 0}, gy = {0, 0}, gz = {0, 0};
   int status = ORACLE_OK;
   for (int ax = cx - 1; ax <= cx + 1; ++ax)
@@ -478,9 +477,8 @@ static int p2p_particle(const otree *T, const double *pos, const double *q, int6
         const int64_t b = box_lin(L, ax, ay, az);
         for (int64_t k = T->start[b]; k < T->start[b + 1]; ++k) {
           const int64_t j = T->order[k];
-          if (j == i) continue;
-          const double dx = pos[3 * i] - pos[3 * j], dy = pos[3 * i + 1] - pos[3 * j + 1],
-                       dz = pos[3 * i + 2] - pos[3 * j + 2];
+          if (j == skip) continue;
+          const double dx = x[0] - pos[3 * j], dy = x[1] - pos[3 * j + 1], dz = x[2] - pos[3 * j + 2];
           const double r2 = dx * dx + dy * dy + dz * dz;
           if (r2 == 0.0) {
             status = ORACLE_E_COINCIDENT;
@@ -500,6 +498,60 @@ static int p2p_particle(const otree *T, const double *pos, const double *q, int6
   return status;
 }
 
+/* Near field of particle i: the sum over its leaf's 27 neighbours, j != i. */
+static int p2p_particle(const otree *T, const double *pos, const double *q, int64_t i,
+                        double *phi, double grad[3]) {
+  return p2p_point(T, pos, q, T->cell[3 * i], T->cell[3 * i + 1], T->cell[3 * i + 2], pos + 3 * i,
+                   i, phi, grad);
+}
+
+/* Which boxes need a local expansion: the ancestors (levels 2..L) of the
+ * leaves of the listed particles (all particles when list is NULL). */
+static unsigned char *need_of(const otree *T, int64_t nt, const int64_t *list) {
+  const int L = T->L;
+  unsigned char *need = calloc(T->lvl_off[L + 1] ? T->lvl_off[L + 1] : 1, 1);
+  if (!need) return NULL;
+  for (int64_t t = 0; t < nt; ++t) {
+    const int64_t i = list ? list[t] : t;
+    for (int l = 2; l <= L; ++l) {
+      const int s = L - l;
+      need[T->lvl_off[l] + box_lin(l, T->cell[3 * i] >> s, T->cell[3 * i + 1] >> s,
+                                   T->cell[3 * i + 2] >> s)] = 1;
+    }
+  }
+  return need;
+}
+
+/* Upward pass, then M2L (levels 2..L) and L2L into every needed box. */
+static void expansions(otree *T, const double *pos, const double *q, const unsigned char *need) {
+  const int L = T->L, p = T->p;
+  if (L < 2) return;
+  upward_pass(T, pos, q);
+  /* M2L, every level 2..L */
+  for (int l = 2; l <= L; ++l) {
+    const int nl = 1 << l;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t b = 0; b < (int64_t)nl * nl * nl; ++b) {
+      if (!need[T->lvl_off[l] + b]) continue;
+      m2l_box(T, l, (int)(b / ((int64_t)nl * nl)), (int)((b / nl) % nl), (int)(b % nl));
+    }
+  }
+  /* L2L, level 2 down to L-1 into their children */
+  for (int l = 2; l < L; ++l) {
+    const int nl = 1 << (l + 1);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t b = 0; b < (int64_t)nl * nl * nl; ++b) {
+      if (!need[T->lvl_off[l + 1] + b]) continue;
+      const int cx = (int)(b / ((int64_t)nl * nl)), cy = (int)((b / nl) % nl), cz = (int)(b % nl);
+      double cp[3], cc[3];
+      box_centre(T, l, cx >> 1, cy >> 1, cz >> 1, cp);
+      box_centre(T, l + 1, cx, cy, cz, cc);
+      op_l2l(p, exp_at(T, T->Lc, l, box_lin(l, cx >> 1, cy >> 1, cz >> 1)), cp, cc,
+             exp_at(T, T->Lc, l + 1, b));
+    }
+  }
+}
+
 /* Full FMM (targets == NULL) or the FMM result at the listed targets only.
  * In the second form the upward pass is done in full and the downward pass
  * only along the ancestors of the targets' leaves; the values are the same as
@@ -517,45 +569,9 @@ int oracle_fmm(int64_t n, const double *pos, const double *q, int depth, int p,
   if (st) { otree_free(&T); return st; }
   const int L = depth;
 
-  /* Which boxes need a local expansion: ancestors (levels 2..L) of a target's leaf. */
-  const int64_t nbox = T.lvl_off[L + 1];
-  unsigned char *need = calloc(nbox ? nbox : 1, 1);
+  unsigned char *need = need_of(&T, nt, targets);
   if (!need) { otree_free(&T); return ORACLE_E_NOMEM; }
-  for (int64_t t = 0; t < nt; ++t) {
-    const int64_t i = targets ? targets[t] : t;
-    for (int l = 2; l <= L; ++l) {
-      const int s = L - l;
-      need[T.lvl_off[l] + box_lin(l, T.cell[3 * i] >> s, T.cell[3 * i + 1] >> s,
-                                  T.cell[3 * i + 2] >> s)] = 1;
-    }
-  }
-
-  if (L >= 2) {
-    upward_pass(&T, pos, q);
-    /* M2L, every level 2..L */
-    for (int l = 2; l <= L; ++l) {
-      const int nl = 1 << l;
-#pragma omp parallel for schedule(dynamic, 4)
-      for (int64_t b = 0; b < (int64_t)nl * nl * nl; ++b) {
-        if (!need[T.lvl_off[l] + b]) continue;
-        m2l_box(&T, l, (int)(b / ((int64_t)nl * nl)), (int)((b / nl) % nl), (int)(b % nl));
-      }
-    }
-    /* L2L, level 2 down to L-1 into their children */
-    for (int l = 2; l < L; ++l) {
-      const int nl = 1 << (l + 1);
-#pragma omp parallel for schedule(dynamic, 16)
-      for (int64_t b = 0; b < (int64_t)nl * nl * nl; ++b) {
-        if (!need[T.lvl_off[l + 1] + b]) continue;
-        const int cx = (int)(b / ((int64_t)nl * nl)), cy = (int)((b / nl) % nl), cz = (int)(b % nl);
-        double cp[3], cc[3];
-        box_centre(&T, l, cx >> 1, cy >> 1, cz >> 1, cp);
-        box_centre(&T, l + 1, cx, cy, cz, cc);
-        op_l2l(p, exp_at(&T, T.Lc, l, box_lin(l, cx >> 1, cy >> 1, cz >> 1)), cp, cc,
-               exp_at(&T, T.Lc, l + 1, b));
-      }
-    }
-  }
+  expansions(&T, pos, q, need);
 
   int status = ORACLE_OK;
   double *phi_all = phi;
@@ -589,6 +605,59 @@ int oracle_fmm(int64_t n, const double *pos, const double *q, int depth, int p,
     *energy = 0.5 * ksum_val(&e);
   }
   free(phi_tmp);
+  free(need);
+  otree_free(&T);
+  return status;
+}
+
+/* Potential of the FMM at displaced target positions.  For probe k the
+ * particle i = idx[k] is taken to sit at y_k (3 values), which must lie in the
+ * same leaf as x_i: phi_k = sum over the 27 neighbour leaves of q_j / |y_k -
+ * x_j| (j != i) plus the leaf's local expansion evaluated at y_k.  The tree,
+ * every multipole and every local expansion are those of the unmoved system:
+ * with every (local <= p, multipole <= p) pair kept, the FMM energy is the
+ * symmetric form E = 1/2 sum_{j,k} q_j q_k K_jk, and the only entries that move
+ * with x_i are K_ij = K_ji, so E(x_i -> y) - E(x_i -> y') = q_i (phi(y) -
+ * phi(y')) exactly (central differences of the energy in x_i).
+ * Errors: ORACLE_E_INVALID_ARG (an index out of range, or y_k outside x_i's
+ * leaf). */
+int oracle_fmm_probe(int64_t n, const double *pos, const double *q, int depth, int p,
+                     const double lo[3], double side, int64_t m, const int64_t *idx,
+                     const double *y, double *phi) {
+  if (n < 0 || !pos || !q || !idx || !y || !phi || depth < 0 || depth > ORACLE_LMAX || p < 0 ||
+      p > ORACLE_PMAX)
+    return ORACLE_E_INVALID_ARG;
+  for (int64_t k = 0; k < m; ++k)
+    if (idx[k] < 0 || idx[k] >= n) return ORACLE_E_INVALID_ARG;
+  otree T;
+  int st = otree_build(&T, n, pos, depth, p, lo, side);
+  if (st) { otree_free(&T); return st; }
+  for (int64_t k = 0; k < m && st == ORACLE_OK; ++k)
+    for (int a = 0; a < 3; ++a)
+      if (leaf_cell_axis(y[3 * k + a], T.lo[a], T.side, depth) != T.cell[3 * idx[k] + a])
+        st = ORACLE_E_INVALID_ARG;
+  unsigned char *need = st ? NULL : need_of(&T, m, idx);
+  if (!st && !need) st = ORACLE_E_NOMEM;
+  if (st) { free(need); otree_free(&T); return st; }
+  expansions(&T, pos, q, need);
+  int status = ORACLE_OK;
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t k = 0; k < m; ++k) {
+    const int64_t i = idx[k];
+    const int cx = T.cell[3 * i], cy = T.cell[3 * i + 1], cz = T.cell[3 * i + 2];
+    double fn, gn[3], ff = 0.0, gf[3] = {0.0, 0.0, 0.0};
+    int s = p2p_point(&T, pos, q, cx, cy, cz, y + 3 * k, i, &fn, gn);
+    if (s) {
+#pragma omp atomic write
+      status = s;
+    }
+    if (depth >= 2) {
+      double c[3];
+      box_centre(&T, depth, cx, cy, cz, c);
+      op_l2p(p, exp_at(&T, T.Lc, depth, box_lin(depth, cx, cy, cz)), c, y + 3 * k, &ff, gf);
+    }
+    phi[k] = fn + ff;
+  }
   free(need);
   otree_free(&T);
   return status;

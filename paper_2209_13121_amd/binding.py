@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfmm.so")
 
-FMM_ABI_VERSION = 1
+FMM_ABI_VERSION = 2
 FMM_P_MAX = 12
 FMM_DEPTH_MAX = 9
 FMM_PREC_FP64, FMM_PREC_MIXED = 0, 1
@@ -137,23 +137,68 @@ def _require(t, name, dtype, numel):
         raise ValueError(f"{name} must be a contiguous {dtype} device tensor with {numel} elements")
 
 
+class Plan:
+    """Handle of a plan (passed to ctypes as its pointer) with its particle
+    count and device, so that the buffers given with it can be checked."""
+
+    def __init__(self, ptr, n, device):
+        self._as_parameter_ = ptr
+        self.n = int(n)
+        self.device = device
+
+    @property
+    def value(self):
+        return self._as_parameter_.value
+
+
 def fmm_plan(cfg, n, pos, workspace, stream=None):
-    """pos: (n, 3) float64 device tensor; workspace: uint8 device tensor."""
+    """pos: (n, 3) float64 device tensor; workspace: uint8 device tensor on
+    the same device."""
     import torch
     _require(pos, "pos", torch.float64, 3 * n)
+    if not (isinstance(workspace, torch.Tensor) and workspace.device == pos.device):
+        raise ValueError("workspace must be a device tensor on the device of pos")
     plan = ctypes.c_void_p()
     _check(load().fmm_plan(ctypes.byref(cfg), int(n), _ptr(pos), _ptr(workspace),
-                           workspace.numel(), _stream_handle(stream), ctypes.byref(plan)),
-           "fmm_plan")
-    return plan
+                           workspace.numel() * workspace.element_size(), _stream_handle(stream),
+                           ctypes.byref(plan)), "fmm_plan")
+    return Plan(plan, n, pos.device)
+
+
+def _require_on(t, name, dtype, numel, plan):
+    _require(t, name, dtype, numel)
+    if isinstance(plan, Plan) and t.device != plan.device:
+        raise ValueError(f"{name} must be on {plan.device}")
+
+
+def _count(plan, t):
+    """Particle count of a plan (Plan) or, for a bare pointer, of tensor t."""
+    return plan.n if isinstance(plan, Plan) else t.numel()
 
 
 def fmm_evaluate(plan, q, phi=None, force=None, energy=None, stream=None):
+    """q: n float64 charges; phi (n), force (n, 3), energy (1): float64 outputs
+    or None; all contiguous tensors on the plan's device."""
+    import torch
+    n = _count(plan, q)
+    _require_on(q, "q", torch.float64, n, plan)
+    for t, name, k in ((phi, "phi", n), (force, "force", 3 * n), (energy, "energy", 1)):
+        if t is not None:
+            _require_on(t, name, torch.float64, k, plan)
     _check(load().fmm_evaluate(plan, _ptr(q), _ptr(phi), _ptr(force), _ptr(energy),
                                _stream_handle(stream)), "fmm_evaluate")
 
 
 def fmm_backward(plan, grad_energy, dE_dx=None, dE_dq=None, stream=None):
+    """grad_energy: one float64 on the device; dE_dx (n, 3), dE_dq (n): float64
+    outputs or None."""
+    import torch
+    _require_on(grad_energy, "grad_energy", torch.float64, 1, plan)
+    n = plan.n if isinstance(plan, Plan) else (dE_dq.numel() if dE_dq is not None else
+                                               (dE_dx.numel() // 3 if dE_dx is not None else 0))
+    for t, name, k in ((dE_dx, "dE_dx", 3 * n), (dE_dq, "dE_dq", n)):
+        if t is not None:
+            _require_on(t, name, torch.float64, k, plan)
     _check(load().fmm_backward(plan, _ptr(grad_energy), _ptr(dE_dx), _ptr(dE_dq),
                                _stream_handle(stream)), "fmm_backward")
 
@@ -271,11 +316,19 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, pos, q, p, depth, precision, lo, side):
-            f = FMM(pos.detach().contiguous(), p=p, depth=depth, precision=precision, lo=lo,
-                    side=side)
-            _, _, e = f.evaluate(q.detach().contiguous(), want_phi=False, want_force=False)
+            # the library takes FP64 positions and charges whatever the compute
+            # precision (FP32 inputs are widened here, exactly)
+            f = FMM(pos.detach().to(torch.float64).contiguous(), p=p, depth=depth,
+                    precision=precision, lo=lo, side=side)
+            _, _, e = f.evaluate(q.detach().to(torch.float64).contiguous(), want_phi=False,
+                                 want_force=False)
+            st = f.check()
+            if st != 0:
+                f.close()
+                raise FMMError(st, "fmm_evaluate (device check)")
             ctx.fmm = f
-            return e.reshape(())
+            ctx.dtypes = (pos.dtype, q.dtype)
+            return e.reshape(()).to(q.dtype)
 
         @staticmethod
         def backward(ctx, grad_e):
@@ -287,6 +340,13 @@ def _autograd_function():
                 if ctx.needs_input_grad[1] else None
             if dx is not None or dq is not None:
                 fmm_backward(f.plan, g, dx, dq)
+                st = f.check()
+                if st != 0:
+                    raise FMMError(st, "fmm_backward (device check)")
+            if dx is not None:
+                dx = dx.to(ctx.dtypes[0])
+            if dq is not None:
+                dq = dq.to(ctx.dtypes[1])
             return dx, dq, None, None, None, None, None
 
     return FMMEnergy

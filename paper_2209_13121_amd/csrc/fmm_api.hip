@@ -42,12 +42,14 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   lay->n_energy_part = (n + kBlock - 1) / kBlock;
   const bool adaptive = cfg.leaf_max > 0;
   if (adaptive) {
-    // Every existing box but the root is one of 8 children of a divided box;
-    // a divided box holds more than leaf_max particles, so a level has at
-    // most min(8^l, n / (leaf_max + 1)) of them.
+    // Every existing box but the root is one of 8 children of a divided box.
+    // Below the batch level a divided box holds more than leaf_max particles,
+    // so such a level has at most min(8^l, n / (leaf_max + 1)) of them; above
+    // it (batch_level > 0) every non-empty box is divided: min(8^l, n).
     int64_t div = 0;
     for (int l = 0; l < L; ++l)
-      div += std::min<int64_t>((int64_t)1 << (3 * l), n / ((int64_t)cfg.leaf_max + 1));
+      div += std::min<int64_t>((int64_t)1 << (3 * l),
+                               l < cfg.batch_level ? n : n / ((int64_t)cfg.leaf_max + 1));
     lay->bmax = 1 + 8 * div;
     lay->ucap = 40 * lay->bmax;
     lay->wcap = 16 * lay->bmax;

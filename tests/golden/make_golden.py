@@ -1,9 +1,14 @@
-"""Write the stored oracle values the GPU tests compare against at full size.
+"""Write the stored oracle values the GPU tests and the benchmark compare
+against at full size.
 
 Calls only the CPU oracle (oracle/) on the seeded workloads; nothing here
-comes from the GPU library.  Output: headline_oracle.json with the FP64 FMM
-energy of the 2^20-particle headline workload (uniform positions, Gaussian
-charges, depth 6, p = 8), the ~1 minute an 8-core host needs for it.
+comes from the GPU library.  Outputs:
+  * headline_oracle.json: the FP64 oracle FMM energy of the 2^20-particle
+    headline workload (uniform positions, Gaussian charges, depth 6, p = 8) and
+    the oracle FMM potentials and forces at 512 seeded sample particles;
+  * headline_direct_32k.npz: the exact O(N^2) sums (potential, force) at
+    32,768 seeded sample particles of the same workload.
+An 8-core host needs about two minutes.
 
     python tests/golden/make_golden.py
 """
@@ -20,6 +25,13 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 from paper_2209_13121_amd import workloads as W  # noqa: E402
 
+SAMPLE_SEED = 6
+DIRECT_SEED = 32768
+
+
+def sample(n, k, seed):
+    return np.sort(np.random.default_rng(seed).choice(n, k, replace=False))
+
 
 def main():
     out = {}
@@ -28,15 +40,24 @@ def main():
         t = time.time()
         phi, force, energy = oracle.fmm(pos, q, wl.depth, wl.p)
         dt = time.time() - t
+        s = sample(wl.n, 512, SAMPLE_SEED)
         out[wl.name] = {
             "n": wl.n, "depth": wl.depth, "p": wl.p, "seed": wl.seed, "charges": wl.charges,
             "energy": energy,
             "sum_q_phi_abs": float(np.abs(q * phi).sum()),
             "force_rms": float(np.sqrt((force**2).sum(axis=1).mean())),
             "phi_rms": float(np.sqrt((phi**2).mean())),
+            "sample_seed": SAMPLE_SEED, "sample_index": s.tolist(),
+            "sample_phi": phi[s].tolist(), "sample_force": force[s].tolist(),
             "oracle_seconds": dt, "oracle_threads": os.cpu_count(),
         }
-        print(wl.name, out[wl.name], flush=True)
+        print(wl.name, "energy", energy, f"{dt:.1f} s", flush=True)
+        t = time.time()
+        d = sample(wl.n, 32768, DIRECT_SEED)
+        phi_d, force_d, _ = oracle.direct(pos, q, targets=d)
+        np.savez_compressed(os.path.join(HERE, "headline_direct_32k.npz"), index=d, phi=phi_d,
+                            force=force_d)
+        print(wl.name, f"direct sums at 32768 particles in {time.time() - t:.1f} s", flush=True)
     with open(os.path.join(HERE, "headline_oracle.json"), "w") as f:
         json.dump(out, f, indent=1)
 

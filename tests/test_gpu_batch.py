@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_util import B, log, rel, run_gpu
+from gpu_util import assert_close, B, log, rel, run_gpu
 from paper_2209_13121_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -61,9 +61,36 @@ def test_batch_matches_per_system_oracle(prec):
     assert st["p2p_pairs"] == pairs["p2p_pairs"]
     assert st["m2l_pairs"] == pairs["m2l_pairs"]
     tol_phi, tol_f, tol_e = (1e-12, 1e-12, 1e-12) if prec == B.FMM_PREC_FP64 else (1e-5, 1e-5, 1e-6)
-    assert rel(phi, phi_o) < tol_phi
-    assert rel(force, f_o) < tol_f
+    assert_close(phi, phi_o, tol_phi, what="phi")
+    assert_close(force, f_o, tol_f, what="force")
     assert abs(e - e_o) <= tol_e * abs(e_o)
+
+
+def test_many_tiny_systems_depth_at_batch_level():
+    # 512 systems of 2 charges, one per cell of level 3, depth cap = batch
+    # level = 3: every box above level 3 holding a charge is divided although
+    # it holds fewer than leaf_max charges, so the workspace bound on the
+    # number of boxes must count such boxes (min(8^l, n) per level).  Each
+    # system is then its own leaf: the result is the direct sum per system.
+    rng = np.random.default_rng(53)
+    grid = 8
+    cells = np.array([(k % grid, (k // grid) % grid, k // (grid * grid)) for k in range(512)],
+                     dtype=np.float64)
+    pos = np.repeat(cells, 2, axis=0) + rng.random((1024, 3))
+    q = np.tile([1.0, -1.0], 512)
+    st = {}
+    phi, force, e, _ = run_batch(pos, q, 3, 4, B.FMM_PREC_FP64, 64, 3, grid, stats=st)
+    assert st["boxes"] == 1 + 8 + 64 + 512 and st["leaves"] == 512
+    d = pos[0::2] - pos[1::2]
+    r = np.sqrt((d * d).sum(axis=1))
+    phi_d = np.empty(1024)
+    phi_d[0::2], phi_d[1::2] = -1.0 / r, 1.0 / r
+    f_d = np.empty((1024, 3))
+    f_d[0::2] = -(d / r[:, None] ** 3)  # F_i = q_i q_j (x_i - x_j) / r^3, q_i q_j = -1
+    f_d[1::2] = d / r[:, None] ** 3
+    assert_close(phi, phi_d, 1e-13, what="phi")
+    assert_close(force, f_d, 1e-13, what="force")
+    assert abs(e - (-1.0 / r).sum()) <= 1e-13 * abs((1.0 / r).sum())
 
 
 def test_graph_replay_equals_eager():
@@ -115,7 +142,7 @@ def test_batch_full_size(batch_full):
     phim, fm, em, _ = run_batch(pos, q, wl.max_depth, wl.p, B.FMM_PREC_MIXED, wl.leaf_max,
                                 wl.batch_level, grid)
     assert abs(em - e64) <= 1e-6 * abs(e64)
-    assert rel(fm, f64) <= 1e-5
+    assert_close(fm, f64, 1e-5, what="fm")
     # three systems (the smallest, a middle one, the largest) against the oracle
     starts = np.concatenate([[0], np.cumsum(counts)])
     for k in (int(np.argmin(counts)), len(counts) // 2, int(np.argmax(counts))):
@@ -124,5 +151,5 @@ def test_batch_full_size(batch_full):
         ph, f, ek, _ = oracle.fmm_adaptive(pos[sl], q[sl], wl.leaf_max, wl.max_depth - wl.batch_level,
                                            wl.p, lo=cell, side=1.0)
         log(f"[batch full] system {k} ({counts[k]} charges)")
-        assert rel(phi64[sl], ph) < 1e-12
-        assert rel(f64[sl], f) < 1e-12
+        assert_close(phi64[sl], ph, 1e-12, what="phi64")
+        assert_close(f64[sl], f, 1e-12, what="f64")
