@@ -184,6 +184,34 @@ fmm_status fmm_destroy(fmm_plan_t *plan);
 /* Static text for a status code. */
 const char *fmm_status_string(fmm_status status);
 
+/* ---- a variant that allocates nothing ------------------------------------ */
+
+/* Bytes of the device scratch array fmm_evaluate_static works in (one array
+ * per GPU the library runs on, held until the process ends). */
+#define FMM_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): fmm_plan followed
+ * by fmm_evaluate, with the workspace taken from a device scratch array of
+ * FMM_STATIC_SCRATCH_BYTES that the library holds on the current device, and
+ * the plan object a static of the library's too.  The call allocates no device
+ * or host memory.  Arguments as for fmm_plan and fmm_evaluate; the caller
+ * still passes d_pos, d_q and the outputs (device, user order).
+ * *out_plan (if out_plan is not NULL) receives the library's plan for this
+ * device, usable with fmm_check, fmm_backward, fmm_plan_work and
+ * fmm_plan_tree_stats until the next fmm_evaluate_static call on the device;
+ * fmm_destroy on it only waits for its stream; fmm_profile_enable on it
+ * returns FMM_E_UNSUPPORTED.
+ * Every call on one GPU shares that GPU's array and plan: calls that overlap
+ * on one GPU (different streams, or host threads) race.  The array keeps the
+ * last call's contents; every pass clears what it needs.
+ * Errors: FMM_E_INVALID_ARG, FMM_E_UNSUPPORTED (as fmm_plan),
+ * FMM_E_WORKSPACE (the plan needs more than FMM_STATIC_SCRATCH_BYTES, see
+ * fmm_workspace_size; or adaptive lists over capacity), FMM_E_DEVICE. */
+fmm_status fmm_evaluate_static(const fmm_config *cfg, int64_t n, const double *d_pos,
+                               const double *d_q, double *d_phi, double *d_force,
+                               double *d_energy, fmm_stream_t stream, fmm_plan_t **out_plan);
+
 /* ---- introspection (tests and measurement) ------------------------------- */
 
 /* Leaf cell (ix, iy, iz) of every particle in user order (d_cells: device,

@@ -26,7 +26,9 @@ PHASES = ["tree", "operators", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "energy
 # every symbol include/fmm.h declares
 EXPORTS = ["fmm_config_default", "fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_backward",
            "fmm_check", "fmm_destroy", "fmm_status_string", "fmm_plan_leaves", "fmm_plan_cube",
-           "fmm_hilbert_index", "fmm_profile_enable", "fmm_profile_read", "fmm_plan_work", "fmm_plan_tree_stats"]
+           "fmm_hilbert_index", "fmm_profile_enable", "fmm_profile_read", "fmm_plan_work", "fmm_plan_tree_stats",
+           "fmm_evaluate_static"]
+FMM_STATIC_SCRATCH_BYTES = 128 << 20
 
 
 class fmm_config(ctypes.Structure):
@@ -80,13 +82,15 @@ def load(path=LIB_PATH):
     lib.fmm_profile_read.argtypes = [vp, dp, ctypes.POINTER(i32)]
     lib.fmm_plan_work.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.fmm_plan_tree_stats.argtypes = [vp, ctypes.POINTER(i64)]
+    lib.fmm_evaluate_static.argtypes = [cfgp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int or name in ("fmm_workspace_size", "fmm_plan", "fmm_evaluate",
                                                  "fmm_backward", "fmm_check", "fmm_destroy",
                                                  "fmm_plan_leaves", "fmm_plan_cube",
                                                  "fmm_profile_enable", "fmm_profile_read",
-                                                 "fmm_plan_work", "fmm_plan_tree_stats"):
+                                                 "fmm_plan_work", "fmm_plan_tree_stats",
+                                                 "fmm_evaluate_static"):
             f.restype = ctypes.c_int
     if path == LIB_PATH:
         _LIB = lib
@@ -201,6 +205,24 @@ def fmm_backward(plan, grad_energy, dE_dx=None, dE_dq=None, stream=None):
             _require_on(t, name, torch.float64, k, plan)
     _check(load().fmm_backward(plan, _ptr(grad_energy), _ptr(dE_dx), _ptr(dE_dq),
                                _stream_handle(stream)), "fmm_backward")
+
+
+def fmm_evaluate_static(cfg, n, pos, q, phi=None, force=None, energy=None, stream=None):
+    """Plan + evaluate in the library's own device scratch array (no
+    allocation by the library; the outputs are the caller's).  Returns the
+    library's plan for this device (valid until the next such call on it)."""
+    import torch
+    _require(pos, "pos", torch.float64, 3 * n)
+    for t, name, k in ((q, "q", n), (phi, "phi", n), (force, "force", 3 * n), (energy, "energy", 1)):
+        if t is not None:
+            _require(t, name, torch.float64, k)
+            if t.device != pos.device:
+                raise ValueError(f"{name} must be on {pos.device}")
+    plan = ctypes.c_void_p()
+    _check(load().fmm_evaluate_static(ctypes.byref(cfg), int(n), _ptr(pos), _ptr(q), _ptr(phi),
+                                      _ptr(force), _ptr(energy), _stream_handle(stream),
+                                      ctypes.byref(plan)), "fmm_evaluate_static")
+    return Plan(plan, n, pos.device)
 
 
 def fmm_check(plan):

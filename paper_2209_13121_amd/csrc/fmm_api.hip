@@ -163,7 +163,7 @@ static inline fmm_status from_hip(hipError_t e) { return e == hipSuccess ? FMM_O
 
 void prof_begin(fmm_plan_s* P, int phase, hipStream_t s) {
   P->prof_open = false;
-  if (!((P->profile_mask >> phase) & 1u) || P->nrec >= kMaxProfile) return;
+  if (!P->rec || !((P->profile_mask >> phase) & 1u) || P->nrec >= kMaxProfile) return;
   ProfileRec& r = P->rec[P->nrec];
   if (P->nrec >= P->nevents_created) {
     if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) return;
@@ -219,6 +219,49 @@ static fmm_status validate_config(const fmm_config* cfg) {
   return FMM_OK;
 }
 
+// Fill plan P (host object owned by the caller) for n particles at d_pos with
+// workspace ws laid out as lay, and enqueue the tree build and the operator
+// tables on s.  rec: kMaxProfile profile records, or NULL (no profiling).
+fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, int64_t n,
+                     const double* d_pos, char* ws, hipStream_t s, ProfileRec* rec) {
+  memset(P, 0, sizeof(*P));
+  P->cfg = cfg;
+  P->lay = lay;
+  P->n = n;
+  P->L = cfg.depth;
+  P->p = cfg.p;
+  P->nc = ncoef(cfg.p);
+  P->mixed = cfg.precision == FMM_PREC_MIXED;
+  P->m2l_np = m2l_pieces(cfg);
+  P->m2l_f16 = m2l_is_f16(cfg);
+  P->adaptive = cfg.leaf_max > 0;
+  P->Ld = P->L;
+  P->ws = ws;
+  P->last_stream = s;
+  P->rec = rec;
+  hipError_t e = launch_tree(P, d_pos, s);
+  if (e == hipSuccess && P->adaptive) e = launch_adaptive_tree(P, d_pos, s);
+  if (e != hipSuccess) return FMM_E_DEVICE;
+  if (P->adaptive && (P->nlist[0] > lay.ucap || P->nlist[1] > lay.wcap || P->nlist[2] > lay.xcap))
+    return FMM_E_WORKSPACE;  // the tree's lists do not fit the workspace's list capacity
+  if (P->Ld >= 2 && launch_operators(P, s) != hipSuccess) return FMM_E_DEVICE;
+  return FMM_OK;
+}
+
+// Every pass of an evaluation of charges d_q (NULL: the stored sorted charges)
+// and the outputs.
+fmm_status evaluate_into(fmm_plan_s* P, const double* d_q, double* d_phi, double* d_force,
+                         double* d_energy, hipStream_t s) {
+  P->last_stream = s;
+  hipError_t e = run_passes(P, d_q, s);
+  if (e == hipSuccess)
+    e = launch_near_and_finish(P, d_phi, d_force, d_energy, nullptr, nullptr, nullptr, s);
+  if (e == hipSuccess) P->has_charges = true;
+  return from_hip(e);
+}
+
+fmm_status validate_config_for(const fmm_config* cfg) { return validate_config(cfg); }
+
 }  // namespace fmm
 
 using namespace fmm;
@@ -260,37 +303,17 @@ fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void*
 
   fmm_plan_s* P = new (std::nothrow) fmm_plan_s;
   if (!P) return FMM_E_DEVICE;
-  memset(P, 0, sizeof(*P));
-  P->cfg = *cfg;
-  P->lay = lay;
-  P->n = n;
-  P->L = cfg->depth;
-  P->p = cfg->p;
-  P->nc = ncoef(cfg->p);
-  P->mixed = cfg->precision == FMM_PREC_MIXED;
-  P->m2l_np = m2l_pieces(*cfg);
-  P->m2l_f16 = m2l_is_f16(*cfg);
-  P->adaptive = cfg->leaf_max > 0;
-  P->Ld = P->L;
-  P->ws = static_cast<char*>(d_workspace);
-  P->last_stream = reinterpret_cast<hipStream_t>(stream);
-  P->rec = static_cast<ProfileRec*>(calloc(kMaxProfile, sizeof(ProfileRec)));
-  if (!P->rec) {
+  ProfileRec* rec = static_cast<ProfileRec*>(calloc(kMaxProfile, sizeof(ProfileRec)));
+  if (!rec) {
     delete P;
     return FMM_E_DEVICE;
   }
-  hipStream_t s = P->last_stream;
-  hipError_t e = launch_tree(P, d_pos, s);
-  if (e == hipSuccess && P->adaptive) e = launch_adaptive_tree(P, d_pos, s);
-  fmm_status st2 = FMM_OK;
-  if (e == hipSuccess && P->adaptive &&
-      (P->nlist[0] > lay.ucap || P->nlist[1] > lay.wcap || P->nlist[2] > lay.xcap))
-    st2 = FMM_E_WORKSPACE;  // the tree's lists do not fit the workspace's list capacity
-  if (e == hipSuccess && st2 == FMM_OK && P->Ld >= 2) e = launch_operators(P, s);
-  if (e != hipSuccess || st2 != FMM_OK) {
-    free(P->rec);
+  st = plan_into(P, *cfg, lay, n, d_pos, static_cast<char*>(d_workspace),
+                 reinterpret_cast<hipStream_t>(stream), rec);
+  if (st != FMM_OK) {
+    free(rec);
     delete P;
-    return e != hipSuccess ? FMM_E_DEVICE : st2;
+    return st;
   }
   *out = P;
   return FMM_OK;
@@ -299,13 +322,7 @@ fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void*
 fmm_status fmm_evaluate(fmm_plan_t* P, const double* d_q, double* d_phi, double* d_force,
                         double* d_energy, fmm_stream_t stream) {
   if (!P || !d_q) return FMM_E_INVALID_ARG;
-  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  P->last_stream = s;
-  hipError_t e = run_passes(P, d_q, s);
-  if (e == hipSuccess)
-    e = launch_near_and_finish(P, d_phi, d_force, d_energy, nullptr, nullptr, nullptr, s);
-  if (e == hipSuccess) P->has_charges = true;
-  return from_hip(e);
+  return evaluate_into(P, d_q, d_phi, d_force, d_energy, reinterpret_cast<hipStream_t>(stream));
 }
 
 fmm_status fmm_backward(fmm_plan_t* P, const double* d_grad_energy, double* d_dE_dx,
@@ -340,6 +357,7 @@ fmm_status fmm_destroy(fmm_plan_t* P) {
   if (!P) return FMM_OK;
   fmm_status st = FMM_OK;
   if (hipStreamSynchronize(P->last_stream) != hipSuccess) st = FMM_E_DEVICE;
+  if (P->is_static) return st;  // the library's own plan of fmm_evaluate_static: kept
   for (int i = 0; i < P->nevents_created; ++i) {
     hipEventDestroy(P->rec[i].start);
     hipEventDestroy(P->rec[i].stop);
@@ -389,6 +407,7 @@ uint64_t fmm_hilbert_index(uint32_t ix, uint32_t iy, uint32_t iz, int32_t bits) 
 
 fmm_status fmm_profile_enable(fmm_plan_t* P, int phase_mask) {
   if (!P) return FMM_E_INVALID_ARG;
+  if (!P->rec) return FMM_E_UNSUPPORTED;  // the plan of fmm_evaluate_static records nothing
   P->profile_mask = (uint32_t)phase_mask & ((1u << FMM_PHASE_COUNT) - 1u);
   P->prof_open = false;
   return FMM_OK;

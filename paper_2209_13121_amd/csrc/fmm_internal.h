@@ -179,6 +179,7 @@ struct fmm_plan_s {
   int nrec;
   fmm::ProfileRec* rec;  // kMaxProfile entries, events created lazily
   int nevents_created;
+  bool is_static;  // the per-device plan of fmm_evaluate_static (not freed by fmm_destroy)
 };
 
 namespace fmm {
@@ -187,6 +188,13 @@ template <typename T>
 inline T* wsp(fmm_plan_s* P, size_t off) {
   return reinterpret_cast<T*>(P->ws + off);
 }
+
+// ---- plan set-up and evaluation (defined in fmm_api.hip) ------------------
+fmm_status validate_config_for(const fmm_config* cfg);
+fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, int64_t n,
+                     const double* d_pos, char* ws, hipStream_t s, ProfileRec* rec);
+fmm_status evaluate_into(fmm_plan_s* P, const double* d_q, double* d_phi, double* d_force,
+                         double* d_energy, hipStream_t s);
 
 // ---- launch helpers (defined in fmm_api.hip) -------------------------------
 void prof_begin(fmm_plan_s* P, int phase, hipStream_t s);
