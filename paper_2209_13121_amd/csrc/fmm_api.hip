@@ -123,7 +123,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     }
     if (m2l_is_f16(cfg)) {
       const size_t rp = (size_t)m2lb_rows(nc), kp = (size_t)32 * m2lb_ksteps(nc);
-      lay->f16_mscale = take(sizeof(float) * NB);
+      lay->f16_lmax = take(sizeof(uint32_t) * (FMM_DEPTH_MAX + 2));
       lay->f16_rowf = take(sizeof(float) * rp);
       lay->f16_colf = take(sizeof(float) * kp);
       lay->f16_tbl = take(sizeof(uint32_t) * rp * kp);

@@ -111,7 +111,7 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t multb;            // split M2L: multipoles as BF16 / FP16 pieces, all boxes
   size_t op_m2lb;          // split M2L: operators as BF16 / FP16 pieces
   size_t m2l_half;         // split M2L: parts 1.. of the split tail groups
-  size_t f16_mscale;       // FP16 M2L: per box, the inverse of its power-of-two scale
+  size_t f16_lmax;         // FP16 M2L: per level, max |M_k colf_k| (float bits; the level's scale)
   size_t f16_rowf;         // FP16 M2L: per operator row, the inverse row scale
   size_t f16_colf;         // FP16 M2L: per k, the inverse column scale (applied to multipoles)
   size_t f16_tbl;          // FP16 M2L: per (row, k), max |entry| over the operators (float bits)

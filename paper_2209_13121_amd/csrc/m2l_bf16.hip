@@ -24,6 +24,13 @@
 //    into BF16 pieces (k_split_mult) so the M2L loop only loads quads.
 //  * Accumulation: FP32 chains over kFlush consecutive offsets (smallest
 //    piece products first), summed with Kahan compensation.
+//  * FP16 form (FMM_M2L_F16X2): operators scaled per row and column, source
+//    multipoles per level, by powers of two into the FP16 range, split into 2
+//    FP16 pieces (h + l); blocks of low degree take h h + h l + l h, blocks of
+//    high degree h h alone (f16_cross); FP32 chains of kGroupF16 offsets
+//    summed into the total, unscaled once at the end.
+#include <algorithm>
+
 #include "bf16_split.h"
 #include "m2l_common.h"
 
@@ -42,6 +49,18 @@ using m2l::kThreads;
 #endif
 #ifndef M2LB_FLUSH
 #define M2LB_FLUSH 4
+#endif
+#ifndef M2LB_RG_F16
+#define M2LB_RG_F16 6
+#endif
+#ifndef M2LB_PB_KST
+#define M2LB_PB_KST 3
+#endif
+#ifndef M2LB_PB2_KST
+#define M2LB_PB2_KST 0
+#endif
+#ifndef M2LB_OP2
+#define M2LB_OP2 1
 #endif
 constexpr int kFlush = M2LB_FLUSH;
 // FP16 form: offsets per FP32 partial sum.
@@ -90,43 +109,110 @@ __global__ void k_split_mult(const float* __restrict__ m32, int ms, int nc, int 
   for (int i = 0; i < NP; ++i) o[(ks * NP + i) * 4 + g] = q[i];
 }
 
-// FP16 form: every box's FP32 multipole row times the column factors colf_k,
-// scaled by a power of two 2^s_b so that its largest entry lies in
-// [2^13, 2^14), split into 2 FP16 pieces; mscale_b = 2^-s_b.  lpb (16 or 32)
-// lanes per box, lane u holding k = 8 u .. 8 u + 7 (quad (ks * 2 + piece) * 4 + g,
-// u = 4 ks + g).
-__global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, int kst, int64_t nbox,
-                               int lpb, const float* __restrict__ colf, u32x4* __restrict__ out,
-                               float* __restrict__ mscale) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t box = t / lpb;
-  const int u = (int)(t % lpb);
-  const bool live = box < nbox && u < 4 * kst;
-  float v[8];
+// FP16 form: boxes of levels 2..L in level order; the work-groups of the
+// level-max pass, per level.
+struct LevelBlocks {
+  int64_t box_off[FMM_DEPTH_MAX + 2];  // first box (row of the expansion arrays) of level l
+  int64_t blk_off[FMM_DEPTH_MAX + 2];  // first work-group of level l
+  int l0, l1;                          // levels l0..l1
+};
+
+__device__ __forceinline__ int level_of_block(const LevelBlocks& lb, int64_t b) {
+  int l = lb.l0;
+  while (l < lb.l1 && b >= lb.blk_off[l + 1]) ++l;
+  return l;
+}
+
+// FP16 form, pass 1: per level, the largest |M_k colf_k| over its boxes (the
+// FP32 multipoles times the column factors), into lmax[l] as float bits.  The
+// work-groups of a level stride over its boxes (at most kLevelMaxGroups per
+// level); each group's maximum joins lmax[l] by one atomicMax on the bits
+// (non-negative floats order as their bits; a maximum is exact in any order).
+// lpb lanes per box, lane u holding k = 8u .. 8u+7.
+constexpr int64_t kLevelMaxGroups = 256;
+__global__ void k_f16_level_max(const float* __restrict__ m32, int ms, int nc, int lpb,
+                                const float* __restrict__ colf, LevelBlocks lb,
+                                uint32_t* __restrict__ lmax) {
+  __shared__ float sm[kBlock / 64];
+  const int l = level_of_block(lb, blockIdx.x);
+  const int64_t ngrp = lb.blk_off[l + 1] - lb.blk_off[l], per = kBlock / lpb;
+  const int u = (int)(threadIdx.x % lpb);
   float m = 0.f;
+  for (int64_t box = lb.box_off[l] + (blockIdx.x - lb.blk_off[l]) * per + threadIdx.x / lpb;
+       box < lb.box_off[l + 1]; box += ngrp * per) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int k = 8 * u + j;
+      if (k < nc) m = fmaxf(m, fabsf(m32[box * ms + k] * colf[k]));
+    }
+  }
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) m = fmaxf(m, __shfl_xor(m, w, 64));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float b = 0.f;
+    for (int w = 0; w < kBlock / 64; ++w) b = fmaxf(b, sm[w]);
+    atomicMax(&lmax[l], __float_as_uint(b));
+  }
+}
+
+// The power of two 2^(14 - e) that puts a level's largest |M_k colf_k| (float
+// bits lmax) into [2^13, 2^14); 2^e is returned as the inverse scale.
+__device__ __forceinline__ int f16_level_exp(uint32_t lmax_bits) {
+  const float m = __uint_as_float(lmax_bits);
+  int e = 0;
+  if (m > 0.f) frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+  return e;
+}
+
+// FP16 form, pass 2: every box's FP32 multipole row times the column factors
+// colf_k, scaled by its level's power of two so that the level's largest
+// entry lies in [2^13, 2^14), split into 2 FP16 pieces.  lpb (16 or 32)
+// lanes per box, lane u holding k = 8 u .. 8 u + 7 (quad (ks * 2 + piece) * 4
+// + g, u = 4 ks + g).
+__global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, int kst, int lpb,
+                               const float* __restrict__ colf, LevelBlocks lb,
+                               const uint32_t* __restrict__ lmax, u32x4* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t box = lb.box_off[lb.l0] + t / lpb;
+  const int u = (int)(t % lpb);
+  if (box >= lb.box_off[lb.l1 + 1] || u >= 4 * kst) return;
+  int l = lb.l0;
+  while (l < lb.l1 && box >= lb.box_off[l + 1]) ++l;
+  const int e = f16_level_exp(lmax[l]);
+  uint32_t pc[8][2];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int k = 8 * u + j;
-    v[j] = (live && k < nc) ? m32[box * ms + k] * colf[k] : 0.f;
-    m = fmaxf(m, fabsf(v[j]));
+    split_f16_f32(ldexpf(k < nc ? m32[box * ms + k] * colf[k] : 0.f, 14 - e), pc[j]);
   }
-#pragma unroll
-  for (int w = 16; w >= 1; w >>= 1)
-    if (w < lpb) m = fmaxf(m, __shfl_xor(m, w, lpb));  // box max
-  int e = 0;
-  if (m > 0.f) frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
-  if (!live) return;
-  uint32_t pc[8][2];
-#pragma unroll
-  for (int j = 0; j < 8; ++j) split_f16_f32(ldexpf(v[j], 14 - e), pc[j]);
   u32x4 q[2];
   pack_quads<2>(pc, q);
   u32x4* o = out + box * (kst * 2 * 4);
   const int ks = u / 4, g = u % 4;
   o[(ks * 2 + 0) * 4 + g] = q[0];
   o[(ks * 2 + 1) * 4 + g] = q[1];
-  if (u == 0) mscale[box] = ldexpf(1.f, e - 14);
 }
+
+// FP16 form: a (row block, k step) product block takes all three piece
+// products h_a h_b + h_a l_b + l_a h_b when the lowest local degree n of its
+// rows plus the lowest multipole degree n' of its k values is below
+// kF16Tier, and h_a h_b alone otherwise.  A term of degrees (n, n') reaches a
+// target's potential scaled by about (a / |d|)^(n + n'), a the box
+// half-diagonal and |d| >= 2 box sizes, so at most (sqrt(3) / 4)^(n + n');
+// the dropped piece products are 2^-11 of that term: below 1e-7 relative from
+// n + n' = 11 on.
+#ifndef M2LB_TIER
+#define M2LB_TIER 11
+#endif
+constexpr int kF16Tier = M2LB_TIER;
+constexpr int isqrt_c(int v) {
+  int r = 0;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+constexpr bool f16_cross(int rb, int ks) { return isqrt_c(16 * rb) + isqrt_c(32 * ks) < kF16Tier; }
 
 // Shape of the kernel for order P and NP pieces.
 template <int P, int NP, bool F16 = false, bool AD = false>
@@ -149,24 +235,31 @@ struct Shape {
   // BF16 forms, whose extra piece would not fit the registers, and one from
   // 5 (BF16) or 6 (FP16) k steps on, where the accumulators alone take half
   // the registers (p >= 11 still spills a little)
-  static constexpr int RGW = F16 ? (KST >= 6 ? 1 : 6) : (KST >= 5 ? 1 : M2LB_RG);
+  static constexpr int RGW = F16 ? (KST >= 6 ? 1 : M2LB_RG_F16) : (KST >= 5 ? 1 : M2LB_RG);
   static constexpr int RG = RB < RGW ? RB : RGW;
   // Prefetch the next offset's B quads (a second register set) up to 3 k
   // steps (p <= 8).  From 4 on (p = 9, 10) the second set made the compiler
   // spill (84-112 bytes per lane), and the adaptive p = 10 M2L took 10.3 ms
   // instead of 6.3 ms without it.
-  static constexpr bool PREFETCH_B = KST <= 3;
+  static constexpr bool PREFETCH_B = KST <= M2LB_PB_KST;
+  // offsets of B in flight (measured at p = 8: two were no faster than one)
+  static constexpr int PBD = !PREFETCH_B ? 0 : (F16 && KST <= M2LB_PB2_KST ? 2 : 1);
+  // FP16 form, one chunk per operator: operators loaded two offsets ahead (a
+  // second register set for the staged quads; measured at p = 8: M2L 3.17 ->
+  // 3.10 ms)
+  static constexpr bool OP2 = F16 && M2LB_OP2 && NCH == 1;
 };
 
-// F16: FP16 pieces of scaled operands (FMM_M2L_F16X2): per-offset FP32 chains
-// times the source box's inverse scale, summed in two levels (partials of
-// kGroupF16 offsets), rows times rowf at the end.
+// F16: FP16 pieces of scaled operands (FMM_M2L_F16X2): FP32 chains of
+// kGroupF16 offsets summed into the total, rows times rowf and the level's
+// inverse scale (from lmax) at the end; high-degree blocks take one piece
+// product (f16_cross).
 template <int P, int NP, bool F16, bool AD>
 __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* __restrict__ multq,
                                                      const u32x4* __restrict__ zero_q,
                                                      const u32x4* __restrict__ ops,
                                                      float* __restrict__ out,
-                                                     const float* __restrict__ mscale,
+                                                     const uint32_t* __restrict__ lmax,
                                                      const float* __restrict__ rowf,
                                                      float* __restrict__ half_out) {
   typedef Shape<P, NP, F16, AD> S;
@@ -238,88 +331,90 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
         for (int rr = 0; rr < RG; ++rr)
 #pragma unroll
           for (int i = 0; i < NP; ++i)
-            if (r0 + rr < RB) av[rr][i] = sa[16 * (r0 + rr) * QCS + kc * NP + i];
+            if (r0 + rr < RB && (!F16 || i == 0 || f16_cross(r0 + rr, ks)))
+              av[rr][i] = sa[16 * (r0 + rr) * QCS + kc * NP + i];
 #pragma unroll
         for (int t = 0; t < PR::N; ++t)
 #pragma unroll
           for (int rr = 0; rr < RG; ++rr)
             if (r0 + rr < RB) {
-              if (F16)
-                acc[r0 + rr] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
-                    __builtin_bit_cast(f16x8, av[rr][PR::a[t]]),
-                    __builtin_bit_cast(f16x8, b[ks * NP + PR::b[t]]), acc[r0 + rr], 0, 0, 0);
-              else
+              if (F16) {
+                // blocks of high degree take h_a h_b only (t = N - 1)
+                if (t == PR::N - 1 || f16_cross(r0 + rr, ks))
+                  acc[r0 + rr] = __builtin_amdgcn_mfma_f32_16x16x32_f16(
+                      __builtin_bit_cast(f16x8, av[rr][PR::a[t]]),
+                      __builtin_bit_cast(f16x8, b[ks * NP + PR::b[t]]), acc[r0 + rr], 0, 0, 0);
+              } else {
                 acc[r0 + rr] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                     __builtin_bit_cast(bf16x8, av[rr][PR::a[t]]),
                     __builtin_bit_cast(bf16x8, b[ks * NP + PR::b[t]]), acc[r0 + rr], 0, 0, 0);
+              }
             }
       }
     }
   };
 
   constexpr bool PB = S::PREFETCH_B;
-  constexpr int FLUSH = F16 ? 1 : kFlush;  // FP16: each offset has its own source scale
-  u32x4 reg[S::PER_THREAD];
-  u32x4 b0[KST * NP], b1[PB ? KST * NP : 1];
-  // source box scale (FP16 form): of the current and of the next offset
-  auto scale_of = [&](m2l::Src src) -> float { return F16 && src.ok ? mscale[tl.lvl_off + src.slot] : 1.f; };
+  constexpr int FLUSH = kFlush;
+  u32x4 reg[S::PER_THREAD], reg2[S::OP2 ? S::PER_THREAD : 1];
+  u32x4 b0[KST * NP], b1[PB ? KST * NP : 1], b2[S::PBD > 1 ? KST * NP : 1];
   // Pipeline over the class's offsets: offset i is computed while the
-  // operator of the next stage and the B quads of offset i + 1 are loaded and
-  // the source slot of offset i + 2 is looked up.
-  int i = i0, dx, dy, dz, ndx, ndy, ndz;
-  int op = m2l::il_offset(pi, i0, dx, dy, dz);
-  int nop = m2l::il_offset(pi, i0 + 1, ndx, ndy, ndz);
-  m2l::Src s_cur = tl.lookup(sSlot, i0, dx, dy, dz);
-  m2l::Src s_next = tl.lookup(sSlot, i0 + 1, ndx, ndy, ndz);
+  // operator of the next stage and the B quads of offset i + PBD are loaded
+  // and the source slot of offset i + PBD + 1 is looked up (PBD offsets of B
+  // in flight: B loads from L2 are the latency the kernel waits on most).
+  constexpr int PBD = S::PBD;
+  int i = i0, ndx, ndy, ndz;
+  int op = m2l::il_offset(pi, i0, ndx, ndy, ndz);
+  int nop = m2l::il_offset(pi, i0 + 1 < i1 ? i0 + 1 : i1 - 1, ndx, ndy, ndz);
+  auto lookup_at = [&](int k) -> m2l::Src {
+    int ldx, ldy, ldz;
+    const int kk = k < i1 ? k : i1 - 1;
+    m2l::il_offset(pi, kk, ldx, ldy, ldz);
+    return tl.lookup(sSlot, kk, ldx, ldy, ldz);
+  };
+  m2l::Src sw[PBD + 1];  // sources of offsets i .. i + PBD
+#pragma unroll
+  for (int k = 0; k <= PBD; ++k) sw[k] = lookup_at(i0 + k);
   bool wave_any = false;
-  float sc_cur = scale_of(s_cur), sc_next = 0.f;
   if (PB) {
-    load_b(row_of(s_cur), b0);
-    wave_any = __any(s_cur.ok);
+    load_b(row_of(sw[0]), b0);
+    if (PBD > 1) load_b(row_of(sw[1]), b1);
+    wave_any = __any(sw[0].ok);
   }
   stage_load(op, 0, reg);
   stage_store(sT[0], reg);
+  if (S::OP2) stage_load(nop, 0, reg);  // the operator of offset i0 + 1, stored at offset i0
   __syncthreads();
   int cur = 0;
 
-  auto do_offset = [&](u32x4* bc, u32x4* bn) -> bool {
+  // bc: B quads of offset i (loaded); bl: the buffer that receives offset
+  // i + PBD.  OP2 (one chunk per operator): rin holds the operator of offset
+  // i + 1 (loaded one offset earlier), rout receives that of offset i + 2.
+  auto do_offset = [&](u32x4* bc, u32x4* bl, u32x4* rin, u32x4* rout) -> bool {
     const bool more = i + 1 < i1;
-    int fdx, fdy, fdz;
-    const int fi = i + 2 < i1 ? i + 2 : i1 - 1;
-    const int fop = m2l::il_offset(pi, fi, fdx, fdy, fdz);
-    const m2l::Src s_far = tl.lookup(sSlot, fi, fdx, fdy, fdz);
+    const int fop = m2l::il_offset(pi, i + 2 < i1 ? i + 2 : i1 - 1, ndx, ndy, ndz);
+    const m2l::Src s_far = lookup_at(i + PBD + 1);
     if (!PB) {
-      load_b(row_of(s_cur), bc);
-      wave_any = __any(s_cur.ok);
+      load_b(row_of(sw[0]), bc);
+      wave_any = __any(sw[0].ok);
     }
 #pragma unroll
     for (int ch = 0; ch < NCH; ++ch) {
       const bool last_chunk = ch == NCH - 1;
-      stage_load(last_chunk ? (more ? nop : op) : op, last_chunk ? 0 : ch + 1, reg);
-      if (PB && ch == 0) {
-        load_b(row_of(s_next), bn);
-        sc_next = scale_of(s_next);
-      }
+      if (S::OP2)
+        stage_load(fop, 0, rout);
+      else
+        stage_load(last_chunk ? (more ? nop : op) : op, last_chunk ? 0 : ch + 1, reg);
+      if (PB && ch == 0) load_b(row_of(sw[PBD]), bl);
       if (wave_any) compute_chunk(sT[cur], ch, bc);
-      if (F16 && last_chunk) {
-        // each offset's chain times its source scale into an FP32 partial
-        // (fused, exact scaling), the partial into the sum every kGroupF16
-        // offsets (emulated at the headline size: 1.9e-7 of phi from the M2L
-        // rounding, against 1.35e-7 with Kahan after every offset)
-        if (wave_any) {
+      if (F16 && last_chunk && ((i + 1 - i0) % kGroupF16 == 0 || !more)) {
+        // one scale per level: the FP32 chain runs over kGroupF16 offsets,
+        // then joins the sum (the same two-level summation as a chain per
+        // offset scaled into a partial of kGroupF16 offsets)
 #pragma unroll
-          for (int r = 0; r < RB; ++r) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) comp[r][e] = fmaf(acc[r][e], sc_cur, comp[r][e]);
-            acc[r] = f32x4{0, 0, 0, 0};
-          }
-        }
-        if ((i + 1 - i0) % kGroupF16 == 0 || !more) {
-#pragma unroll
-          for (int r = 0; r < RB; ++r) {
-            sum[r] += comp[r];
-            comp[r] = f32x4{0, 0, 0, 0};
-          }
+        for (int r = 0; r < RB; ++r) {
+          sum[r] += acc[r];
+          acc[r] = f32x4{0, 0, 0, 0};
         }
       }
       if (!F16 && last_chunk && (FLUSH == 1 ? wave_any : ((i + 1) % FLUSH == 0 || !more))) {
@@ -333,30 +428,28 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
         }
       }
       if (last_chunk && !more) return false;
-      stage_store(sT[cur ^ 1], reg);
+      stage_store(sT[cur ^ 1], S::OP2 ? rin : reg);
       __syncthreads();
       cur ^= 1;
     }
     ++i;
     op = nop;
-    dx = ndx;
-    dy = ndy;
-    dz = ndz;
     nop = fop;
-    ndx = fdx;
-    ndy = fdy;
-    ndz = fdz;
-    if (PB) wave_any = __any(s_next.ok);
-    sc_cur = PB ? sc_next : scale_of(s_next);
-    s_cur = s_next;
-    s_next = s_far;
+    if (PB) wave_any = __any(sw[1].ok);
+#pragma unroll
+    for (int k = 0; k < PBD; ++k) sw[k] = sw[k + 1];
+    sw[PBD] = s_far;
     return true;
   };
-  if (PB) {
-    while (do_offset(b0, b1) && do_offset(b1, b0)) {
+  if (PBD == 2) {
+    while (do_offset(b0, b2, reg, reg2) && do_offset(b1, b0, reg2, reg) && do_offset(b2, b1, reg, reg2) &&
+           do_offset(b0, b2, reg2, reg) && do_offset(b1, b0, reg, reg2) && do_offset(b2, b1, reg2, reg)) {
+    }
+  } else if (PBD == 1) {
+    while (do_offset(b0, b1, reg, reg2) && do_offset(b1, b0, reg2, reg)) {
     }
   } else {
-    while (do_offset(b0, b0)) {
+    while (do_offset(b0, b0, reg, reg2) && do_offset(b0, b0, reg2, reg)) {
     }
   }
 
@@ -366,6 +459,8 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
   float* o = !whole && tl.part > 0
                  ? half_out + ((tl.sidx * (kM2lParts - 1) + tl.part - 1) * m2l::kTargetsPerGroup + wave * 16 + col) * NC
                  : out + (tl.lvl_off + tl.target_slot(a)) * NC;
+  // FP16 form: rows times 2^-ra_r (rowf) and the source level's 2^(e - 14)
+  const float lsc = F16 ? ldexpf(1.f, f16_level_exp(lmax[tl.l]) - 14) : 1.f;
   // Accumulator layout of the 16x16 FP32-output MFMAs: lane l holds column
   // l % 16, rows 4 (l / 16) + i.
 #pragma unroll
@@ -373,7 +468,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int row = 16 * r + 4 * kg + e;
-      if (row < NC) o[row] = F16 ? sum[r][e] * rowf[row] : sum[r][e];
+      if (row < NC) o[row] = F16 ? sum[r][e] * (rowf[row] * lsc) : sum[r][e];
     }
 }
 
@@ -455,24 +550,42 @@ struct M2LBfRun {
     const int nc = Pl->nc, kst = m2lb_ksteps(nc);
     const int64_t box0 = exp_box0(Pl), nbox = exp_nbox(Pl) - box0;
     u32x4* mq = wsp<u32x4>(Pl, lay.multb);
-    const int qr = m2lb_row_quads(nc, 2);
-    float* msc = wsp<float>(Pl, lay.f16_mscale);
+    uint32_t* lmax = wsp<uint32_t>(Pl, lay.f16_lmax);
     const int lpb = 4 * kst <= 16 ? 16 : 32;
+    // boxes of levels 2..L (adaptive: 2..deepest) and the level-max work-groups
+    LevelBlocks lb;
+    lb.l0 = 2;
+    lb.l1 = Pl->adaptive ? Pl->Ld : Pl->L;
+    int64_t nblk = 0;
+    for (int l = lb.l0; l <= lb.l1 + 1; ++l) {
+      lb.box_off[l] = Pl->adaptive ? Pl->ce_off[l] : lay.lvl_off[l];
+      lb.blk_off[l] = nblk;
+      if (l <= lb.l1) {
+        const int64_t nb = (Pl->adaptive ? Pl->ce_off[l + 1] : lay.lvl_off[l + 1]) - lb.box_off[l];
+        nblk += std::min<int64_t>((nb + kBlock / lpb - 1) / (kBlock / lpb), kLevelMaxGroups);
+      }
+    }
     prof_begin(Pl, FMM_PHASE_SPLIT, s);
-    k_split_mult_h<<<grid_for(nbox * lpb, kBlock), kBlock, 0, s>>>(
-        wsp<float>(Pl, lay.mult32) + box0 * mstride(Pl->p), mstride(Pl->p), nc, kst, nbox, lpb,
-        wsp<float>(Pl, lay.f16_colf), mq + box0 * qr, msc + box0);
+    hipError_t e = fill_u32(lmax, FMM_DEPTH_MAX + 2, 0u, s);
+    if (e != hipSuccess) return e;
+    if (nblk > 0) {
+      k_f16_level_max<<<(unsigned)nblk, kBlock, 0, s>>>(wsp<float>(Pl, lay.mult32), mstride(Pl->p), nc,
+                                                        lpb, wsp<float>(Pl, lay.f16_colf), lb, lmax);
+      k_split_mult_h<<<grid_for(nbox * lpb, kBlock), kBlock, 0, s>>>(
+          wsp<float>(Pl, lay.mult32), mstride(Pl->p), nc, kst, lpb, wsp<float>(Pl, lay.f16_colf), lb,
+          lmax, mq);
+    }
     prof_end(Pl, s);
     const m2l::Args a = split_args(Pl);
     prof_begin(Pl, FMM_PHASE_M2L, s);
     if (Pl->adaptive)
       k_m2l_bf<P, 2, true, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-          msc, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
+          lmax, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
     else
       k_m2l_bf<P, 2, true, false><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-          msc, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
+          lmax, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
     add_halves(Pl, a, s);
     prof_end(Pl, s);
     return hipGetLastError();
