@@ -39,7 +39,8 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   }
   lay->lvl_off[L + 1] = off;
   lay->nbox = off;
-  lay->n_energy_part = (n + kBlock - 1) / kBlock;
+  // energy: q_i phi_i per particle, then sums of 4 kBlock terms
+  lay->n_energy_part = n + (n + 4 * kBlock - 1) / (4 * kBlock);
   const bool adaptive = cfg.leaf_max > 0;
   if (adaptive) {
     // Every existing box but the root is one of 8 children of a divided box.
