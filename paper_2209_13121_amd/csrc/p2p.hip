@@ -394,6 +394,117 @@ __global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p(NBS nbs, int64_
   if (lane < (int)nt) finish_particle<T>(fa, (int64_t)t0 + lane, (double)(1 << lt) / dp->side, acc[0]);
 }
 
+// Uniform tree with small leaves: one wave per parent box P (level L - 1),
+// the targets being the particles of its 8 children (consecutive Hilbert
+// slots 8P .. 8P + 7, so a contiguous particle range).  The sources of all 8
+// are the 4 x 4 x 4 leaves around P, staged once in LDS (tiles of
+// kGroupTile) as offsets from P's centre in leaf units, leaf by leaf; each
+// target reads the 27 leaves around its own from the per-leaf table.  With at
+// most 32 targets, lanes t and t + 32 share a target, taking neighbour leaves
+// 0..13 and 14..26, combined by one xor shuffle.
+constexpr int kGroupTile = 512;
+template <typename T>
+__global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p_group(
+    int L, const uint32_t* __restrict__ start, const uint32_t* __restrict__ c2s,
+    const uint32_t* __restrict__ s2c, const uint32_t* __restrict__ sorted_leaf,
+    const DevParams* __restrict__ dp, const Rec<double>* __restrict__ src, FinishArgs fa) {
+  __shared__ SSrc<T> sS[kGroupTile];
+  __shared__ uint32_t sPre[65];  // staged order: block leaf k holds [sPre[k], sPre[k + 1])
+  __shared__ uint32_t sStart[64];
+  const int64_t P = blockIdx.x;
+  const int lane = threadIdx.x;
+  const uint32_t t0 = start[8 * P], nt = start[8 * P + 8] - t0;
+  if (nt == 0) return;  // uniform over the wave
+  int px, py, pz;
+  unpack_coord(s2c[8 * P], px, py, pz);
+  px >>= 1;
+  py >>= 1;
+  pz >>= 1;
+  const int nb = 1 << L;
+  // block leaf k = 16 a + 4 b + c at cell (2 px - 1 + a, ...), centre offset
+  // from P's centre (a - 1.5, b - 1.5, c - 1.5) leaf units
+  const int ba = lane >> 4, bb = (lane >> 2) & 3, bc = lane & 3;
+  {
+    const int sx = 2 * px - 1 + ba, sy = 2 * py - 1 + bb, sz = 2 * pz - 1 + bc;
+    uint32_t st = 0, cnt = 0;
+    if (sx >= 0 && sy >= 0 && sz >= 0 && sx < nb && sy < nb && sz < nb) {
+      const uint32_t sl = c2s[lex_index(sx, sy, sz, L)];
+      st = start[sl];
+      cnt = start[sl + 1] - st;
+    }
+    uint32_t c = cnt;
+#pragma unroll
+    for (int w = 1; w < 64; w <<= 1) {
+      const uint32_t v = __shfl_up(c, w, 64);
+      if (lane >= w) c += v;
+    }
+    sStart[lane] = st;
+    sPre[lane + 1] = c;
+    if (lane == 0) sPre[0] = 0;
+  }
+  __syncthreads();
+  const uint32_t total = sPre[64];
+  const bool split = nt <= 32;
+  for (uint32_t g0 = 0; g0 < nt; g0 += (split ? 32u : 64u)) {
+    const int t = split ? (lane & 31) : lane;
+    const int h = split ? (lane >> 5) : 0;
+    const bool live = g0 + t < nt;
+    const int64_t i = (int64_t)t0 + g0 + (live ? t : 0);
+    // this target's leaf in the block and its offset from P's centre
+    int lx, ly, lz;
+    unpack_coord(s2c[sorted_leaf[i]], lx, ly, lz);
+    lx -= 2 * px - 1;
+    ly -= 2 * py - 1;
+    lz -= 2 * pz - 1;
+    Rec<double> r = src[i];
+    r.x += (double)lx - 1.5;
+    r.y += (double)ly - 1.5;
+    r.z += (double)lz - 1.5;
+    const Tgt<T> tg = make_tgt<T>(r);
+    const int kown = 16 * lx + 4 * ly + lz;
+    Acc<T> acc = {T(0), T(0), T(0), T(0), 0};
+    for (uint32_t c0 = 0; c0 < total; c0 += kGroupTile) {
+      const uint32_t ns = total - c0 < (uint32_t)kGroupTile ? total - c0 : (uint32_t)kGroupTile;
+      __syncthreads();  // the previous tile is no longer read
+      for (uint32_t m = lane; m < ns; m += 64) {
+        const uint32_t q = c0 + m;
+        int lo = 0, hi = 64;  // sPre[lo] <= q < sPre[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (sPre[mid] <= q)
+            lo = mid;
+          else
+            hi = mid;
+        }
+        const Nb nbk{0, 0, (double)(lo >> 4) - 1.5, (double)((lo >> 2) & 3) - 1.5, (double)(lo & 3) - 1.5, 1.0};
+        sS[m] = stage_one<T>(src[sStart[lo] + (q - sPre[lo])], nbk);
+      }
+      __syncthreads();
+      if (live) {
+        const int d0 = split ? 14 * h : 0, d1 = split ? (h ? 27 : 14) : 27;
+        for (int d = d0; d < d1; ++d) {
+          const int k = kown + 16 * (d / 9 - 1) + 4 * ((d / 3) % 3 - 1) + (d % 3 - 1);
+          // leaf k's sources within this tile: [a, e) (empty when e <= a)
+          const int a = (int)(sPre[k] > c0 ? sPre[k] : c0) - (int)c0;
+          const int e = (int)(sPre[k + 1] < c0 + ns ? sPre[k + 1] : c0 + ns) - (int)c0;
+          if (k == kown)
+            for (int j = a; j < e; ++j) pair<T, true>(acc, tg, sS[j]);
+          else
+            for (int j = a; j < e; ++j) pair<T, false>(acc, tg, sS[j]);
+        }
+      }
+    }
+    if (split) {
+      acc.f += __shfl_xor(acc.f, 32, 64);
+      acc.gx += __shfl_xor(acc.gx, 32, 64);
+      acc.gy += __shfl_xor(acc.gy, 32, 64);
+      acc.gz += __shfl_xor(acc.gz, 32, 64);
+      acc.nz += __shfl_xor(acc.nz, 32, 64);
+    }
+    if (live && h == 0) finish_particle<T>(fa, i, (double)nb / dp->side, acc);
+  }
+}
+
 // E = 1/2 sum q_i phi_i: per-block sums of 4 * kBlock consecutive terms in a
 // fixed tree order, then one block over the block sums.
 __global__ void k_energy_blocks(const double* __restrict__ eterm, int64_t n, double* __restrict__ part) {
@@ -465,7 +576,15 @@ hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
     UniformNbs nb{L, wsp<uint32_t>(P, lay.leaf_start), wsp<uint32_t>(P, lay.coord2slot) + lay.lvl_off[L],
                   wsp<uint32_t>(P, lay.slot2coord) + lay.lvl_off[L]};
     const int64_t nleaf = lay.nleaf;
-    if (P->mixed)
+    if (L >= 1 && n <= 8 * nleaf) {
+      // small leaves (at most 8 particles on average): a wave per parent box
+      const int64_t npar = nleaf / 8;
+      const uint32_t* sl = wsp<uint32_t>(P, lay.sorted_leaf);
+      if (P->mixed)
+        k_p2p_group<float><<<(unsigned)npar, 64, 0, s>>>(L, nb.start, nb.c2s, nb.s2c, sl, dp, src, fa);
+      else
+        k_p2p_group<double><<<(unsigned)npar, 64, 0, s>>>(L, nb.start, nb.c2s, nb.s2c, sl, dp, src, fa);
+    } else if (P->mixed)
       k_p2p<float, UniformNbs><<<(unsigned)nleaf, 64, 0, s>>>(nb, nleaf, dp, src, fa);
     else
       k_p2p<double, UniformNbs><<<(unsigned)nleaf, 64, 0, s>>>(nb, nleaf, dp, src, fa);
