@@ -2,8 +2,10 @@
 
 Workload: 2^20 charges uniform in the unit cube, Gaussian charges shifted to
 net zero (seed 1002), uniform octree of depth 6, expansion order p = 8.  One
-step = fmm_plan (tree build for the positions) + fmm_evaluate (all passes,
-potentials, forces and energy) on device-resident inputs.  Three variants are
+step = fmm_replan (the tree build for the positions; the translation
+operators, a function of p and the M2L form only, come from the first
+fmm_plan) + fmm_evaluate (all passes, potentials, forces and energy) on
+device-resident inputs.  Three variants are
 timed the same way: mixed precision with the scaled split-FP16 M2L (the
 library's default mixed form, the headline value), with the split-BF16 M2L,
 with the FP32 M2L, and FP64; every energy is compared to the stored FP64
@@ -112,64 +114,56 @@ def m2l_traffic(variant):
 
 
 def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream, breakdown_steps=3):
-    """Run warmup + steps of (plan + evaluate); returns ms/step, outputs of the
-    last step, the M2L kernel durations over the timed steps (HIP events on
-    the launch stream around that pass only, so the other passes run
-    unbroken) and the per-pass durations of breakdown_steps further, untimed
-    steps with every pass recorded."""
+    """One plan (tree and translation operators), then warmup + steps of
+    (fmm_replan + fmm_evaluate): the tree is rebuilt for the positions every
+    step, the operator tables (a function of p and the M2L form only) are
+    kept.  Returns ms/step, per-step HIP-event statistics, outputs of the last
+    step, the M2L kernel durations over the timed steps (HIP events on the
+    launch stream around that pass only), the per-pass durations of
+    breakdown_steps further, untimed steps with every pass recorded, the
+    status, the work counts, and the time of one fmm_plan with the operator
+    generation."""
     n = q.numel()
     phi = torch.empty(n, dtype=torch.float64, device=pos.device)
     force = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
     energy = torch.empty(1, dtype=torch.float64, device=pos.device)
-    plans = []
-    for _ in range(warmup):
-        p = B.fmm_plan(cfg, n, pos, ws, stream)
-        B.fmm_evaluate(p, q, phi, force, energy, stream)
-        plans.append(p)
     torch.cuda.synchronize()
-    for p in plans:
-        B.fmm_destroy(p)
-    plans = []
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan = B.fmm_plan(cfg, n, pos, ws, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    plan_ms = e0.elapsed_time(e1)
+    for _ in range(warmup):
+        B.fmm_replan(plan, pos, stream)
+        B.fmm_evaluate(plan, q, phi, force, energy, stream)
+    torch.cuda.synchronize()
+    B.fmm_profile_enable(plan, True, phases=["m2l"])
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
     ev[0].record(stream)
     for i in range(steps):
-        p = B.fmm_plan(cfg, n, pos, ws, stream)
-        B.fmm_profile_enable(p, True, phases=["m2l"])
-        B.fmm_evaluate(p, q, phi, force, energy, stream)
+        B.fmm_replan(plan, pos, stream)
+        B.fmm_evaluate(plan, q, phi, force, energy, stream)
         ev[i + 1].record(stream)
-        plans.append(p)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
     per_step = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
     step_stats = {"median_ms": per_step[steps // 2] if steps % 2 else
                   0.5 * (per_step[steps // 2 - 1] + per_step[steps // 2]),
                   "min_ms": per_step[0]}
-
-    def collect(plans):
-        out = {}
-        for p in plans:
-            for k, (t, c) in B.fmm_profile_read(p).items():
-                a = out.setdefault(k, [0.0, 0])
-                a[0] += t
-                a[1] += c
-        return out
-    m2l = collect(plans)["m2l"]
-    st = B.fmm_check(plans[-1])
-    work = B.fmm_plan_work(plans[-1])
-    for p in plans:
-        B.fmm_destroy(p)
-    plans = []
+    m2l = B.fmm_profile_read(plan)["m2l"]
+    st = B.fmm_check(plan)
+    work = B.fmm_plan_work(plan)
+    B.fmm_profile_enable(plan, True)
     for _ in range(breakdown_steps):
-        p = B.fmm_plan(cfg, n, pos, ws, stream)
-        B.fmm_profile_enable(p, True)
-        B.fmm_evaluate(p, q, phi, force, energy, stream)
-        plans.append(p)
+        B.fmm_replan(plan, pos, stream)
+        B.fmm_evaluate(plan, q, phi, force, energy, stream)
     torch.cuda.synchronize()
-    phases = {k: [t / breakdown_steps, c / breakdown_steps] for k, (t, c) in collect(plans).items()}
-    for p in plans:
-        B.fmm_destroy(p)
-    return ms, step_stats, phi, force, energy, m2l, phases, st, work
+    phases = {k: [t / breakdown_steps, c / breakdown_steps]
+              for k, (t, c) in B.fmm_profile_read(plan).items()}
+    B.fmm_destroy(plan)
+    return ms, step_stats, phi, force, energy, m2l, phases, st, work, plan_ms
 
 
 def p2p_evidence(B, torch, pos, q, stream, depth=4, reps=3):
@@ -227,7 +221,7 @@ def adaptive_bench(B, torch, args, stream):
         nbytes = B.fmm_workspace_size(cfg, wl.n)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         print(f"[bench] adaptive {name}: workspace {nbytes / 2**20:.0f} MiB", file=sys.stderr, flush=True)
-        ms, step_stats, phi, force, energy, m2l, phases, st, work = timed_steps(
+        ms, step_stats, phi, force, energy, m2l, phases, st, work, plan_ms = timed_steps(
             B, torch, pos, q, cfg, ws, max(5, args.steps // 2), args.warmup, stream)
         p = B.fmm_plan(cfg, wl.n, pos, ws, stream)
         stats = B.fmm_plan_tree_stats(p)
@@ -237,7 +231,8 @@ def adaptive_bench(B, torch, args, stream):
         flops = 2.0 * (wl.p + 1) ** 4 * stats["m2l_pairs"]
         peak = PEAK_TFLOPS[dtype]
         res[name] = {"value": wl.n / (ms / 1e3), "ms_per_step": ms, "step_events_ms": step_stats,
-                     "status": st, "phases_ms_per_step": {k: v[0] for k, v in phases.items()},
+                     "status": st, "first_plan_ms": plan_ms,
+                     "phases_ms_per_step": {k: v[0] for k, v in phases.items()},
                      "m2l": {"kernel": kernel, "avg_launch_ms": avg, "flops_per_launch": flops,
                              "achieved": flops / (avg / 1e3) / 1e12, "peak": peak,
                              "frac": flops / (avg / 1e3) / 1e12 / peak,
@@ -268,7 +263,7 @@ def adaptive_bench(B, torch, args, stream):
         for k in ("phi", "force", "energy"):
             r.pop(k)
     out = {"workload": wl.name, "n": wl.n, "leaf_max": wl.leaf_max, "depth_cap": wl.max_depth,
-           "p": wl.p, "seed": wl.seed, "metric": "particles/s per FMM evaluation (plan + evaluate)",
+           "p": wl.p, "seed": wl.seed, "metric": "particles/s per FMM evaluation (tree build + evaluate)",
            "value": m["value"], "ms_per_step": m["ms_per_step"], "tree": stats, "accuracy": acc,
            "variants": res}
     if not args.no_cpu_baseline:
@@ -313,9 +308,10 @@ def batch_bench(B, torch, args, stream):
         cfg = B.make_config(p=wl.p, depth=wl.max_depth, precision=getattr(B, "FMM_PREC_" + prec),
                             m2l_kind=getattr(B, "FMM_M2L_" + mk), leaf_max=leaf, **common)
         ws = torch.empty(B.fmm_workspace_size(cfg, n), dtype=torch.uint8, device=dev)
-        ms, step_stats, phi, force, energy, m2l, phases, st, work = timed_steps(
+        ms, step_stats, phi, force, energy, m2l, phases, st, work, plan_ms = timed_steps(
             B, torch, pos, q, cfg, ws, max(5, args.steps // 2), args.warmup, stream)
         entry = {"value": n / (ms / 1e3), "ms_per_step": ms, "step_events_ms": step_stats, "status": st,
+                 "first_plan_ms": plan_ms,
                  "phases_ms_per_step": {k: v[0] for k, v in phases.items()},
                  "m2l_avg_launch_ms": m2l[0] / m2l[1]}
         if name == "mixed":
@@ -374,7 +370,7 @@ def batch_bench(B, torch, args, stream):
             r.pop(k)
     out = {"workload": wl.name, "n": n, "systems": wl.n_systems, "n_min": int(counts.min()),
            "n_max": int(counts.max()), "p": wl.p, "depth_cap": wl.max_depth, "batch_level": wl.batch_level,
-           "seed": wl.seed, "metric": "aggregate particles/s per batch evaluation (plan + evaluate)",
+           "seed": wl.seed, "metric": "aggregate particles/s per batch evaluation (tree build + evaluate)",
            "value": m["value"], "ms_per_step": m["ms_per_step"], "tuned": tuned,
            "autotune": [{"leaf_max": r.tree["leaf_max"], "m2l_kind": r.kind, "ms": r.ms,
                          "energy_err": r.energy_err, "force_err": r.force_err} for r in table],
@@ -468,12 +464,12 @@ def main():
         nbytes = B.fmm_workspace_size(cfg, wl.n)
         ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         print(f"[bench] {name}: workspace {nbytes / 2**20:.0f} MiB", file=sys.stderr, flush=True)
-        ms, step_stats, phi, force, energy, m2l, phases, st, work = timed_steps(
+        ms, step_stats, phi, force, energy, m2l, phases, st, work, plan_ms = timed_steps(
             B, torch, pos, q, cfg, ws, args.steps, args.warmup, stream)
         results[name] = dict(ms=ms, step_stats=step_stats, phi=phi.cpu().numpy(),
                              force=force.cpu().numpy(),
                              energy=float(energy.cpu()[0]), m2l=m2l, phases=phases, status=st,
-                             work=work)
+                             work=work, plan_ms=plan_ms)
         print(f"[bench] {name}: {ms:.3f} ms/step, status {st}", file=sys.stderr, flush=True)
         del ws
         torch.cuda.empty_cache()
@@ -521,6 +517,7 @@ def main():
                 np.linalg.norm(r["phi"] - f64["phi"]) / np.linalg.norm(f64["phi"])),
             "phases_ms_per_step": {k: v[0] for k, v in r["phases"].items()},
             "m2l": m2l_rate(name),
+            "first_plan_ms": r["plan_ms"],
         }
     golden = load_golden(wl)
     acc = {name: accuracy_vs_oracle(r, golden) for name, r in results.items()}
@@ -555,7 +552,7 @@ def main():
                                  "bf16": "split-BF16 MFMA, 3 pieces",
                                  "f32": "FP32 MFMA"}[VARIANTS[HEADLINE][4]] +
                                 ", FP64 M2M/L2L/energy)",
-                   "step": "fmm_plan + fmm_evaluate"},
+                   "step": "fmm_replan (tree build) + fmm_evaluate; operators from the first fmm_plan"},
         "roofline": roofline,
     }
     detail = {"variants": variants, "p2p_pairs": p2p_pairs}

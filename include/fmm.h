@@ -153,6 +153,16 @@ fmm_status fmm_workspace_size(const fmm_config *cfg, int64_t n, size_t *bytes);
 fmm_status fmm_plan(const fmm_config *cfg, int64_t n, const double *d_pos, void *d_workspace,
                     size_t workspace_bytes, fmm_stream_t stream, fmm_plan_t **out);
 
+/* Build the tree of plan for new positions d_pos (device, n x 3 FP64, user
+ * order; the same n and configuration), keeping the translation operators
+ * already in the plan's workspace: they depend on p and the M2L form only, so
+ * a sequence of position sets (time steps of a simulation) generates them
+ * once.  Everything else is as for fmm_plan (the tree build, the adaptive
+ * tree's read-backs); charges of an earlier fmm_evaluate are forgotten; the
+ * profiling selection and unread profile records are kept.  Errors: FMM_E_INVALID_ARG (plan or
+ * d_pos NULL), FMM_E_WORKSPACE (adaptive lists over capacity), FMM_E_DEVICE. */
+fmm_status fmm_replan(fmm_plan_t *plan, const double *d_pos, fmm_stream_t stream);
+
 /* Evaluate the FMM for charges d_q (device, n FP64, user order).  Any of
  * d_phi (n), d_force (n x 3), d_energy (1 FP64) may be NULL; all are device
  * pointers in user order.  The positions of the plan are those passed to

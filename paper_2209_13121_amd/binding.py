@@ -27,7 +27,7 @@ PHASES = ["tree", "operators", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "energy
 EXPORTS = ["fmm_config_default", "fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_backward",
            "fmm_check", "fmm_destroy", "fmm_status_string", "fmm_plan_leaves", "fmm_plan_cube",
            "fmm_hilbert_index", "fmm_profile_enable", "fmm_profile_read", "fmm_plan_work", "fmm_plan_tree_stats",
-           "fmm_evaluate_static"]
+           "fmm_evaluate_static", "fmm_replan"]
 FMM_STATIC_SCRATCH_BYTES = 128 << 20
 
 
@@ -83,6 +83,7 @@ def load(path=LIB_PATH):
     lib.fmm_plan_work.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
     lib.fmm_plan_tree_stats.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fmm_evaluate_static.argtypes = [cfgp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    lib.fmm_replan.argtypes = [vp, vp, vp]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int or name in ("fmm_workspace_size", "fmm_plan", "fmm_evaluate",
@@ -90,7 +91,7 @@ def load(path=LIB_PATH):
                                                  "fmm_plan_leaves", "fmm_plan_cube",
                                                  "fmm_profile_enable", "fmm_profile_read",
                                                  "fmm_plan_work", "fmm_plan_tree_stats",
-                                                 "fmm_evaluate_static"):
+                                                 "fmm_evaluate_static", "fmm_replan"):
             f.restype = ctypes.c_int
     if path == LIB_PATH:
         _LIB = lib
@@ -167,6 +168,15 @@ def fmm_plan(cfg, n, pos, workspace, stream=None):
                            workspace.numel() * workspace.element_size(), _stream_handle(stream),
                            ctypes.byref(plan)), "fmm_plan")
     return Plan(plan, n, pos.device)
+
+
+def fmm_replan(plan, pos, stream=None):
+    """New positions for plan (same n and configuration); keeps its operators."""
+    import torch
+    n = plan.n if isinstance(plan, Plan) else pos.numel() // 3
+    _require_on(pos, "pos", torch.float64, 3 * n, plan)
+    _check(load().fmm_replan(plan, _ptr(pos), _stream_handle(stream)), "fmm_replan")
+    return plan
 
 
 def _require_on(t, name, dtype, numel, plan):

@@ -224,8 +224,20 @@ static fmm_status validate_config(const fmm_config* cfg) {
 // workspace ws laid out as lay, and enqueue the tree build and the operator
 // tables on s.  rec: kMaxProfile profile records, or NULL (no profiling).
 fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, int64_t n,
-                     const double* d_pos, char* ws, hipStream_t s, ProfileRec* rec) {
+                     const double* d_pos, char* ws, hipStream_t s, ProfileRec* rec,
+                     bool keep_operators) {
+  // what a re-plan keeps: the operator tables in the workspace, profiling state
+  const bool ops_ready = keep_operators && P->ops_ready;
+  const uint32_t mask = keep_operators ? P->profile_mask : 0u;
+  const int nevents = keep_operators ? P->nevents_created : 0;
+  const int nrec = keep_operators ? P->nrec : 0;
+  const bool is_static = keep_operators && P->is_static;
   memset(P, 0, sizeof(*P));
+  P->ops_ready = ops_ready;
+  P->profile_mask = mask;
+  P->nevents_created = nevents;
+  P->nrec = nrec;
+  P->is_static = is_static;
   P->cfg = cfg;
   P->lay = lay;
   P->n = n;
@@ -245,7 +257,10 @@ fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, in
   if (e != hipSuccess) return FMM_E_DEVICE;
   if (P->adaptive && (P->nlist[0] > lay.ucap || P->nlist[1] > lay.wcap || P->nlist[2] > lay.xcap))
     return FMM_E_WORKSPACE;  // the tree's lists do not fit the workspace's list capacity
-  if (P->Ld >= 2 && launch_operators(P, s) != hipSuccess) return FMM_E_DEVICE;
+  if (P->Ld >= 2 && !P->ops_ready) {
+    if (launch_operators(P, s) != hipSuccess) return FMM_E_DEVICE;
+    P->ops_ready = true;
+  }
   return FMM_OK;
 }
 
@@ -309,8 +324,9 @@ fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void*
     delete P;
     return FMM_E_DEVICE;
   }
+  memset(P, 0, sizeof(*P));
   st = plan_into(P, *cfg, lay, n, d_pos, static_cast<char*>(d_workspace),
-                 reinterpret_cast<hipStream_t>(stream), rec);
+                 reinterpret_cast<hipStream_t>(stream), rec, false);
   if (st != FMM_OK) {
     free(rec);
     delete P;
@@ -318,6 +334,14 @@ fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void*
   }
   *out = P;
   return FMM_OK;
+}
+
+fmm_status fmm_replan(fmm_plan_t* P, const double* d_pos, fmm_stream_t stream) {
+  if (!P || !d_pos) return FMM_E_INVALID_ARG;
+  const fmm_config cfg = P->cfg;
+  const Layout lay = P->lay;
+  return plan_into(P, cfg, lay, P->n, d_pos, P->ws, reinterpret_cast<hipStream_t>(stream), P->rec,
+                   true);
 }
 
 fmm_status fmm_evaluate(fmm_plan_t* P, const double* d_q, double* d_phi, double* d_force,

@@ -180,6 +180,7 @@ struct fmm_plan_s {
   fmm::ProfileRec* rec;  // kMaxProfile entries, events created lazily
   int nevents_created;
   bool is_static;  // the per-device plan of fmm_evaluate_static (not freed by fmm_destroy)
+  bool ops_ready;  // the workspace holds the translation operators of (p, kind)
 };
 
 namespace fmm {
@@ -192,7 +193,8 @@ inline T* wsp(fmm_plan_s* P, size_t off) {
 // ---- plan set-up and evaluation (defined in fmm_api.hip) ------------------
 fmm_status validate_config_for(const fmm_config* cfg);
 fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, int64_t n,
-                     const double* d_pos, char* ws, hipStream_t s, ProfileRec* rec);
+                     const double* d_pos, char* ws, hipStream_t s, ProfileRec* rec,
+                     bool keep_operators);
 fmm_status evaluate_into(fmm_plan_s* P, const double* d_q, double* d_phi, double* d_force,
                          double* d_energy, hipStream_t s);
 

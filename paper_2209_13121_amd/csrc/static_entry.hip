@@ -58,7 +58,7 @@ extern "C" fmm_status fmm_evaluate_static(const fmm_config* cfg, int64_t n, cons
   if (scratch_of(dev, &ws) != hipSuccess) return FMM_E_DEVICE;
   fmm_plan_s* P = &g_plan[dev];
   const hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  st = plan_into(P, *cfg, lay, n, d_pos, ws, s, nullptr);
+  st = plan_into(P, *cfg, lay, n, d_pos, ws, s, nullptr, false);
   P->is_static = true;
   if (st == FMM_OK) st = evaluate_into(P, d_q, d_phi, d_force, d_energy, s);
   if (out_plan) *out_plan = st == FMM_OK ? P : nullptr;

@@ -350,3 +350,30 @@ def test_depth5_whole_groups_sampled(precision, kind):
     tol = 1e-12 if precision == B.FMM_PREC_FP64 else 1e-5
     assert_close(phi[t], phi_o, tol, what="phi")
     assert_close(force[t], force_o, tol, what="force")
+
+
+@pytest.mark.parametrize("kw", [dict(p=6, depth=4, precision=B.FMM_PREC_FP64),
+                                dict(p=8, depth=4, precision=B.FMM_PREC_MIXED),
+                                dict(p=6, depth=6, precision=B.FMM_PREC_MIXED, leaf_max=16)],
+                         ids=["fp64", "mixed-f16", "adaptive-mixed"])
+def test_replan_equals_fresh_plan(kw):
+    """fmm_replan (new positions, the operator tables kept) gives bitwise the
+    result of a fresh fmm_plan for those positions."""
+    import torch
+    log(f"[api] replan {kw}")
+    dev = torch.device("cuda:0")
+    pos_a, q = W.uniform_gauss(20000, 81)
+    pos_b, _ = W.uniform_gauss(20000, 82)
+    tb, tq = torch.from_numpy(pos_b).to(dev), torch.from_numpy(q).to(dev)
+    f = B.FMM(torch.from_numpy(pos_a).to(dev), **kw)
+    f.evaluate(tq)
+    B.fmm_replan(f.plan, tb)
+    a = f.evaluate(tq)
+    assert f.check() == 0
+    g = B.FMM(tb, **kw)
+    b = g.evaluate(tq)
+    assert g.check() == 0
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    f.close()
+    g.close()
