@@ -68,6 +68,8 @@ def parse():
                     help="run only the 256-system batch and print its JSON object")
     ap.add_argument("--cpu-sample-boxes", type=int, default=2,
                     help="level-1 boxes (1/8 of the domain each) whose particles the oracle evaluates")
+    ap.add_argument("--p2p-only", action="store_true",
+                    help="run only the near-field pass on the depth-4 tree (profiling runs)")
     ap.add_argument("--only", choices=sorted(VARIANTS), default=None,
                     help="time one variant only (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -454,6 +456,9 @@ def main():
     q = torch.from_numpy(q_np).to(dev)
     stream = torch.cuda.current_stream()
     B.load()
+    if args.p2p_only:
+        print(json.dumps({"p2p_depth4": p2p_evidence(B, torch, pos, q, stream)}), flush=True)
+        return
 
     results = {}
     for name, (prec, kind, *_rest) in VARIANTS.items():

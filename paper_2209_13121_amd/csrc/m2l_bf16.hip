@@ -125,26 +125,27 @@ __device__ __forceinline__ int level_of_block(const LevelBlocks& lb, int64_t b) 
 
 // FP16 form, pass 1: per level, the largest |M_k colf_k| over its boxes (the
 // FP32 multipoles times the column factors), into lmax[l] as float bits.  The
-// work-groups of a level stride over its boxes (at most kLevelMaxGroups per
-// level); each group's maximum joins lmax[l] by one atomicMax on the bits
-// (non-negative floats order as their bits; a maximum is exact in any order).
-// lpb lanes per box, lane u holding k = 8u .. 8u+7.
-constexpr int64_t kLevelMaxGroups = 256;
-__global__ void k_f16_level_max(const float* __restrict__ m32, int ms, int nc, int lpb,
+// work-groups of a level stride over its rows as one flat array of float4
+// (ms is a multiple of 4; k >= nc is skipped); each group's maximum joins
+// lmax[l] by one atomicMax on the bits (non-negative floats order as their
+// bits; a maximum is exact in any order).
+constexpr int64_t kLevelMaxGroups = 1024;
+__global__ void k_f16_level_max(const float* __restrict__ m32, int ms, int nc,
                                 const float* __restrict__ colf, LevelBlocks lb,
                                 uint32_t* __restrict__ lmax) {
   __shared__ float sm[kBlock / 64];
   const int l = level_of_block(lb, blockIdx.x);
-  const int64_t ngrp = lb.blk_off[l + 1] - lb.blk_off[l], per = kBlock / lpb;
-  const int u = (int)(threadIdx.x % lpb);
+  const int64_t ngrp = lb.blk_off[l + 1] - lb.blk_off[l];
+  const int64_t n4 = (lb.box_off[l + 1] - lb.box_off[l]) * ms / 4;
+  const float4* v4 = reinterpret_cast<const float4*>(m32 + lb.box_off[l] * ms);
   float m = 0.f;
-  for (int64_t box = lb.box_off[l] + (blockIdx.x - lb.blk_off[l]) * per + threadIdx.x / lpb;
-       box < lb.box_off[l + 1]; box += ngrp * per) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int k = 8 * u + j;
-      if (k < nc) m = fmaxf(m, fabsf(m32[box * ms + k] * colf[k]));
-    }
+  for (int64_t t = (blockIdx.x - lb.blk_off[l]) * kBlock + threadIdx.x; t < n4; t += ngrp * kBlock) {
+    const float4 v = v4[t];
+    const int k = (int)((4 * t) % ms);
+    if (k < nc) m = fmaxf(m, fabsf(v.x * colf[k]));
+    if (k + 1 < nc) m = fmaxf(m, fabsf(v.y * colf[k + 1]));
+    if (k + 2 < nc) m = fmaxf(m, fabsf(v.z * colf[k + 2]));
+    if (k + 3 < nc) m = fmaxf(m, fabsf(v.w * colf[k + 3]));
   }
 #pragma unroll
   for (int w = 32; w >= 1; w >>= 1) m = fmaxf(m, __shfl_xor(m, w, 64));
@@ -562,7 +563,8 @@ struct M2LBfRun {
       lb.blk_off[l] = nblk;
       if (l <= lb.l1) {
         const int64_t nb = (Pl->adaptive ? Pl->ce_off[l + 1] : lay.lvl_off[l + 1]) - lb.box_off[l];
-        nblk += std::min<int64_t>((nb + kBlock / lpb - 1) / (kBlock / lpb), kLevelMaxGroups);
+        const int64_t n4 = nb * mstride(Pl->p) / 4;
+        nblk += std::min<int64_t>((n4 + kBlock - 1) / kBlock, kLevelMaxGroups);
       }
     }
     prof_begin(Pl, FMM_PHASE_SPLIT, s);
@@ -570,7 +572,7 @@ struct M2LBfRun {
     if (e != hipSuccess) return e;
     if (nblk > 0) {
       k_f16_level_max<<<(unsigned)nblk, kBlock, 0, s>>>(wsp<float>(Pl, lay.mult32), mstride(Pl->p), nc,
-                                                        lpb, wsp<float>(Pl, lay.f16_colf), lb, lmax);
+                                                        wsp<float>(Pl, lay.f16_colf), lb, lmax);
       k_split_mult_h<<<grid_for(nbox * lpb, kBlock), kBlock, 0, s>>>(
           wsp<float>(Pl, lay.mult32), mstride(Pl->p), nc, kst, lpb, wsp<float>(Pl, lay.f16_colf), lb,
           lmax, mq);

@@ -225,11 +225,167 @@ __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
   }
 }
 
+// Fine levels: one work-group per 128 target columns computes every row
+// block, so each source column is loaded once (the kernel above re-reads it
+// once per row block) and each target's rows are written together.  The
+// operator rows of one octant (all row blocks, only the k steps each row
+// block can touch) are staged in LDS per octant; M2M runs the 8 octants in
+// turn with the next octant's sources in flight, L2L one octant per
+// work-group.  Used where the row blocks' accumulators and the source
+// registers fit (at most 6 row blocks, p <= 8) and the level has enough
+// columns to fill the chip.
+template <int P, int MODE>
+__global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
+  typedef ShiftShape<P, MODE> S;
+  constexpr int NC = S::NC, RB = S::RB, MS = S::MS, KP = S::KP, NQ = S::NQ, RS = S::RS;
+  __shared__ f64x2 sA[RB * 16 * RS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kg = lane >> 4;
+  // group -> (8 tiles of 16 parents[, octant]), XCD-aware as above
+  const int64_t per_xcd = (a.ngroups + 7) / 8;
+  const int64_t g = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (g >= a.ngroups) return;  // uniform over the work-group
+  const int oct_l2l = MODE == 1 ? (int)(g % 8) : 0;
+  const int64_t pgroup = MODE == 1 ? g / 8 : g;
+  const int64_t ps = (pgroup * kWaves + wave) * 16 + col;
+  const bool ok = ps < a.nparent;
+  const int64_t prow = !ok ? 0 : (a.parent_of ? (int64_t)a.parent_of[8 * ps] : ps);
+  uint32_t child_bits = 0;
+  if (ok) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      int x, y, z;
+      unpack_coord(a.s2c_child[8 * ps + c], x, y, z);
+      child_bits |= (uint32_t)c << (3 * (((x & 1) << 2) | ((y & 1) << 1) | (z & 1)));
+    }
+  }
+  auto child_of = [&](int oct) { return (int)((child_bits >> (3 * oct)) & 7u); };
+  // k pairs row block rb can touch (exact zeros outside): M2M lower, L2L upper
+  auto qrange = [&](int rb, int& q0, int& q1) {
+    if (MODE == 0) {
+      const int d = degree_of(min(16 * rb + 15, NC - 1));
+      q0 = 0;
+      q1 = ((d + 1) * (d + 1) + 7) / 8;
+    } else {
+      const int d = degree_of(16 * rb);
+      q0 = (d * d) / 8;
+      q1 = NQ;
+    }
+  };
+  auto load_b = [&](int oct, f64x2* bv) {
+    const int64_t srow = !ok ? 0 : (MODE == 0 ? 8 * ps + child_of(oct) : prow);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = 8 * q + 2 * kg;
+      const int k0 = k < MS ? k : MS - 2;
+      const f64x2 v = *reinterpret_cast<const f64x2*>(static_cast<const double*>(a.src) + srow * MS + k0);
+      bv[q] = (ok && k < MS) ? v : f64x2{0.0, 0.0};
+    }
+  };
+  f64x4 acc0[RB], acc1[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc0[r] = acc1[r] = f64x4{0, 0, 0, 0};
+  f64x2 bcur[NQ], bnext[NQ];
+  load_b(MODE == 0 ? 0 : oct_l2l, bcur);
+  constexpr int NOCT = MODE == 0 ? 8 : 1;
+  for (int o = 0; o < NOCT; ++o) {
+    const int oct = MODE == 0 ? o : oct_l2l;
+    if (o > 0) __syncthreads();  // the previous octant's rows are no longer read
+    // stage every row of octant oct, the k pairs of its row block only
+    for (int e = tid; e < RB * 16 * 4 * NQ; e += kThreads) {
+      const int u = e % (4 * NQ), row = e / (4 * NQ), q = u / 4;
+      int q0, q1;
+      qrange(row / 16, q0, q1);
+      if (q >= q0 && q < q1)
+        sA[row * RS + u] = *reinterpret_cast<const f64x2*>(a.ops + ((size_t)oct * (RB * 16) + row) * KP + 2 * u);
+    }
+    __syncthreads();
+    if (MODE == 0 && o + 1 < NOCT) load_b(o + 1, bnext);  // next octant in flight
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+      int q0, q1;
+      qrange(rb, q0, q1);
+      const f64x2* sa = sA + (16 * rb + col) * RS + kg;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (q < q0 || q >= q1) continue;  // uniform over the work-group
+        const f64x2 av = sa[4 * q];
+        acc0[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bcur[q][0], acc0[rb], 0, 0, 0);
+        acc1[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bcur[q][1], acc1[rb], 0, 0, 0);
+      }
+    }
+    if (MODE == 0 && o + 1 < NOCT) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) bcur[q] = bnext[q];
+    }
+  }
+  if (!ok) return;
+  const int64_t cs = MODE == 1 ? 8 * ps + child_of(oct_l2l) : 0;
+  const double inv_h = MODE == 1 ? (double)(1 << a.l) / a.dp->side : 0.0;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    const f64x4 acc = acc0[rb] + acc1[rb];
+    // transpose across the 4 lanes of a column (as in k_shift): this lane then
+    // holds rows 16 rb + 4 kg + j, j = 0..3
+    double v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int i_send = (kg - t) & 3;
+      const double send = i_send == 0 ? acc[0] : i_send == 1 ? acc[1] : i_send == 2 ? acc[2] : acc[3];
+      const double got = __shfl(send, ((kg + t) & 3) * 16 + col);
+      const int j = (kg + t) & 3;
+      if (j == 0) v[0] = got;
+      if (j == 1) v[1] = got;
+      if (j == 2) v[2] = got;
+      if (j == 3) v[3] = got;
+    }
+    const int rr = 16 * rb + 4 * kg;
+    if (rr >= MS) continue;
+    if (MODE == 0) {
+      *reinterpret_cast<f64x2*>(a.dst64 + prow * MS + rr) = f64x2{v[0], v[1]};
+      *reinterpret_cast<f64x2*>(a.dst64 + prow * MS + rr + 2) = f64x2{v[2], v[3]};
+      if (a.dst32)
+        *reinterpret_cast<f32x4*>(a.dst32 + prow * MS + rr) =
+            f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (rr + j < NC)
+          v[j] += inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + rr + j]
+                                   : static_cast<const double*>(a.m2l)[cs * NC + rr + j]);
+      if (!(a.leaf && a.mixed)) {
+        *reinterpret_cast<f64x2*>(a.dst64 + cs * MS + rr) = f64x2{v[0], v[1]};
+        *reinterpret_cast<f64x2*>(a.dst64 + cs * MS + rr + 2) = f64x2{v[2], v[3]};
+      }
+      if (a.dst32)
+        *reinterpret_cast<f32x4*>(a.dst32 + cs * MS + rr) =
+            f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+    }
+  }
+}
+
+// Columns from which a level runs the all-rows form (64 work-groups of 128
+// columns: below that the per-row-block form spreads the level over more
+// work-groups).
+constexpr int64_t kRowsMinColumns = 64 * 128;
+
 template <int P>
 struct ShiftRun {
   static hipError_t run(ShiftArgs a, int mode, hipStream_t s) {
     typedef ShiftShape<P, 0> S;
     const int64_t pgroups = (a.nparent + 16 * kWaves - 1) / (16 * kWaves);
+    if constexpr (S::RB <= 6) {
+      if (a.nparent * (mode == 1 ? 8 : 1) >= kRowsMinColumns) {
+        a.ngroups = pgroups * (mode == 1 ? 8 : 1);
+        const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
+        if (mode == 0)
+          k_shift_rows<P, 0><<<grid, kThreads, 0, s>>>(a);
+        else
+          k_shift_rows<P, 1><<<grid, kThreads, 0, s>>>(a);
+        return hipGetLastError();
+      }
+    }
     a.ngroups = pgroups * S::RB * (mode == 1 ? 8 : 1);
     const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
     if (mode == 0)
