@@ -115,7 +115,7 @@ def m2l_traffic(variant):
     return traffic if src_hash == m2l_source_hash(variant) else None
 
 
-def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream, breakdown_steps=3):
+def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream, breakdown_steps=3, schedule=None):
     """One plan (tree and translation operators), then warmup + steps of
     (fmm_replan + fmm_evaluate): the tree is rebuilt for the positions every
     step, the operator tables (a function of p and the M2L form only) are
@@ -136,6 +136,9 @@ def timed_steps(B, torch, pos, q, cfg, ws, steps, warmup, stream, breakdown_step
     e1.record(stream)
     torch.cuda.synchronize()
     plan_ms = e0.elapsed_time(e1)
+    if schedule:
+        from paper_2209_13121_amd import autotune as T
+        T.apply_schedule(plan, schedule)
     for _ in range(warmup):
         B.fmm_replan(plan, pos, stream)
         B.fmm_evaluate(plan, q, phi, force, energy, stream)
@@ -302,23 +305,29 @@ def batch_bench(B, torch, args, stream):
     print("[bench] batch: autotune", file=sys.stderr, flush=True)
     trees = [{"depth": wl.max_depth, "leaf_max": lm} for lm in (32, 64, 128)]
     best, table = T.tune(pos, q, wl.p, trees, reps=3, stream=stream, **common)
-    tuned = {"leaf_max": best.tree["leaf_max"], "m2l_kind": best.kind} if best else None
+    tuned = ({"leaf_max": best.tree["leaf_max"], "m2l_kind": best.kind, "schedule": best.schedule}
+             if best else None)
     kind = best.kind if best else "F16X2"
     leaf = best.tree["leaf_max"] if best else wl.leaf_max
+    sched = best.schedule if best else {}
     res = {}
     for name, prec, mk in (("mixed", "MIXED", kind), ("fp64", "FP64", "AUTO")):
         cfg = B.make_config(p=wl.p, depth=wl.max_depth, precision=getattr(B, "FMM_PREC_" + prec),
                             m2l_kind=getattr(B, "FMM_M2L_" + mk), leaf_max=leaf, **common)
         ws = torch.empty(B.fmm_workspace_size(cfg, n), dtype=torch.uint8, device=dev)
+        # FP64 runs the tuned schedule's P2P form too (the split applies to split M2L forms only)
+        sc = sched if name == "mixed" else {k: v for k, v in sched.items() if k == "p2p_persistent"}
         ms, step_stats, phi, force, energy, m2l, phases, st, work, plan_ms = timed_steps(
-            B, torch, pos, q, cfg, ws, max(5, args.steps // 2), args.warmup, stream)
+            B, torch, pos, q, cfg, ws, max(5, args.steps // 2), args.warmup, stream, schedule=sc)
         entry = {"value": n / (ms / 1e3), "ms_per_step": ms, "step_events_ms": step_stats, "status": st,
+                 "schedule": sc,
                  "first_plan_ms": plan_ms,
                  "phases_ms_per_step": {k: v[0] for k, v in phases.items()},
                  "m2l_avg_launch_ms": m2l[0] / m2l[1]}
         if name == "mixed":
             # the evaluation alone, captured once and replayed as one graph launch
             plan = B.fmm_plan(cfg, n, pos, ws, stream)
+            T.apply_schedule(plan, sc)
             ph = torch.empty(n, dtype=torch.float64, device=dev)
             fo = torch.empty((n, 3), dtype=torch.float64, device=dev)
             en = torch.empty(1, dtype=torch.float64, device=dev)
@@ -374,8 +383,8 @@ def batch_bench(B, torch, args, stream):
            "n_max": int(counts.max()), "p": wl.p, "depth_cap": wl.max_depth, "batch_level": wl.batch_level,
            "seed": wl.seed, "metric": "aggregate particles/s per batch evaluation (tree build + evaluate)",
            "value": m["value"], "ms_per_step": m["ms_per_step"], "tuned": tuned,
-           "autotune": [{"leaf_max": r.tree["leaf_max"], "m2l_kind": r.kind, "ms": r.ms,
-                         "energy_err": r.energy_err, "force_err": r.force_err} for r in table],
+           "autotune": [{"leaf_max": r.tree["leaf_max"], "m2l_kind": r.kind, "schedule": r.schedule,
+                         "ms": r.ms, "energy_err": r.energy_err, "force_err": r.force_err} for r in table],
            "accuracy": acc, "variants": res}
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
@@ -593,6 +602,9 @@ def main():
                         "gate_met": d["accuracy"]["gate_1e-6_met"]}
             if "cpu_baseline" in d:
                 out[key]["cpu_particles_per_s"] = d["cpu_baseline"]["value"]
+            if key == "batch":
+                out[key]["tuned"] = d["tuned"]
+                out[key]["graph_evaluate_ms"] = d["variants"]["mixed"]["graph_evaluate"]["ms"]
     out["accuracy"] = {
         "rel_energy_err_vs_oracle": hl["rel_energy_err_vs_oracle"],
         "rel_rms_force_err_vs_oracle_sampled": hl["rel_rms_force_err_vs_oracle_sampled"],

@@ -163,6 +163,21 @@ fmm_status fmm_plan(const fmm_config *cfg, int64_t n, const double *d_pos, void 
  * d_pos NULL), FMM_E_WORKSPACE (adaptive lists over capacity), FMM_E_DEVICE. */
 fmm_status fmm_replan(fmm_plan_t *plan, const double *d_pos, fmm_stream_t stream);
 
+/* Schedule of a plan's passes: how work is spread over the GPU, never what
+ * is computed.  Keys:
+ *   FMM_SCHED_P2P_PERSISTENT: 0 (default) one wave per box; 1 (adaptive tree
+ *     only, else FMM_E_UNSUPPORTED) a persistent launch whose resident waves
+ *     take the non-empty leaves from a work-list built at plan time, costliest
+ *     (most ordered pairs) first.  Results are bitwise the same.
+ *   FMM_SCHED_M2L_SPLIT: 0..16 (default 16), split M2L forms: how many of the
+ *     last work-groups of each XCD run as four parts over the offsets, added in
+ *     part order afterwards (a shorter last round; the summation order of those
+ *     tiles changes, within rounding).
+ * Kept by fmm_replan.  Errors: FMM_E_INVALID_ARG (plan NULL, unknown key or
+ * value out of range), FMM_E_UNSUPPORTED. */
+enum { FMM_SCHED_P2P_PERSISTENT = 0, FMM_SCHED_M2L_SPLIT = 1 };
+fmm_status fmm_plan_set_schedule(fmm_plan_t *plan, int key, int value);
+
 /* Evaluate the FMM for charges d_q (device, n FP64, user order).  Any of
  * d_phi (n), d_force (n x 3), d_energy (1 FP64) may be NULL; all are device
  * pointers in user order.  The positions of the plan are those passed to

@@ -1,35 +1,49 @@
 """Autotuner: the fastest mixed-precision configuration that meets the accuracy gate.
 
-For a given charge set and tree family it searches the M2L form (scaled split
-FP16, split BF16, FP32) and the tree's leaf capacity (``leaf_max`` of an
-adaptive tree, or the depth of a uniform one), the knob that trades near-field
-(P2P) against far-field (M2L) work.  Every candidate is measured on the GPU
-through the C ABI: plan + evaluate timed with HIP events on the launch stream
-(median of ``reps``), and its energy and forces compared with the FP64 result
-of the same tree.  The gate is the library's: relative energy error <= 1e-6 and
-relative RMS force error <= 1e-5 against FP64 of the same tree.
+For a given charge set and tree family it searches
+  * the tree's leaf capacity (``leaf_max`` of an adaptive tree, or the depth
+    of a uniform one), the knob that trades near-field (P2P) against far-field
+    (M2L) work;
+  * the M2L form (scaled split FP16, split BF16, FP32);
+  * the schedule of the passes (``fmm_plan_set_schedule``): the adaptive P2P
+    as one wave per box or as a persistent launch over a cost-ordered
+    work-list, and how many tail work-groups per XCD the split M2L forms run
+    in four parts.
+Every candidate is measured on the GPU through the C ABI, the way the
+benchmark runs a step: one plan, then fmm_replan + fmm_evaluate timed with HIP
+events on the launch stream (median of ``reps``).  The gate is the library's:
+relative energy error <= 1e-6 and relative RMS force error <= 1e-5 against the
+FP64 result of the same tree; a caller may add a check of its own (e.g.
+against an independent reference on sampled systems) through ``reference``.
 
 ``select`` holds the decision rule alone (no GPU), so it can be tested on the
 host.
 """
+import itertools
 from dataclasses import dataclass, field
 
 from . import binding as B
 
 KINDS = ("F16X2", "BF16X3", "F32")
+SPLIT_KINDS = ("F16X2", "BF16X3", "BF16X2")
+# schedule values searched (key -> values); the first value is the default
+SCHEDULES = {"p2p_persistent": (0, 1), "m2l_split": (16, 8, 0)}
+_SCHED_KEY = {"p2p_persistent": B.FMM_SCHED_P2P_PERSISTENT, "m2l_split": B.FMM_SCHED_M2L_SPLIT}
 
 
 @dataclass
 class Result:
     tree: dict                 # leaf_max / depth of the candidate tree
     kind: str                  # M2L form
-    ms: float                  # median plan + evaluate time
+    ms: float                  # median replan + evaluate time
     energy_err: float          # relative to FP64 on the same tree
     force_err: float           # relative RMS, same reference
+    schedule: dict = field(default_factory=dict)
     extra: dict = field(default_factory=dict)
+    reference_ok: bool = True  # the caller's own check, when given
 
     def meets(self, gate_e, gate_f):
-        return self.energy_err <= gate_e and self.force_err <= gate_f
+        return self.energy_err <= gate_e and self.force_err <= gate_f and self.reference_ok
 
 
 def select(results, gate_e=1e-6, gate_f=1e-5):
@@ -42,35 +56,56 @@ def select(results, gate_e=1e-6, gate_f=1e-5):
     return best
 
 
-def _time(torch, cfg, n, pos, q, ws, stream, reps):
-    """Median ms of plan + evaluate, and the outputs of the last run."""
+def schedules_for(tree, kind):
+    """The schedule candidates that apply to a tree and an M2L form."""
+    keys = []
+    if tree.get("leaf_max", 0) > 0:
+        keys.append("p2p_persistent")
+    if kind in SPLIT_KINDS:
+        keys.append("m2l_split")
+    if not keys:
+        return [{}]
+    return [dict(zip(keys, vals)) for vals in itertools.product(*(SCHEDULES[k] for k in keys))]
+
+
+def apply_schedule(plan, schedule):
+    for k, v in schedule.items():
+        B.fmm_plan_set_schedule(plan, _SCHED_KEY[k], v)
+
+
+def _time(torch, cfg, n, pos, q, ws, stream, reps, schedule):
+    """Median ms of replan + evaluate after one plan, and the last outputs."""
     phi = torch.empty(n, dtype=torch.float64, device=pos.device)
     force = torch.empty((n, 3), dtype=torch.float64, device=pos.device)
     energy = torch.empty(1, dtype=torch.float64, device=pos.device)
+    plan = B.fmm_plan(cfg, n, pos, ws, stream)
+    apply_schedule(plan, schedule)
     times = []
     for r in range(reps + 1):
         t0 = torch.cuda.Event(enable_timing=True)
         t1 = torch.cuda.Event(enable_timing=True)
         t0.record(stream)
-        plan = B.fmm_plan(cfg, n, pos, ws, stream)
+        B.fmm_replan(plan, pos, stream)
         B.fmm_evaluate(plan, q, phi, force, energy, stream)
         t1.record(stream)
         torch.cuda.synchronize()
-        st = B.fmm_check(plan)
-        B.fmm_destroy(plan)
-        if st != 0:
-            raise B.FMMError(st, "autotune candidate")
         if r:  # the first run warms up
             times.append(t0.elapsed_time(t1))
+    st = B.fmm_check(plan)
+    B.fmm_destroy(plan)
+    if st != 0:
+        raise B.FMMError(st, "autotune candidate")
     times.sort()
     return times[len(times) // 2], phi, force, float(energy.cpu()[0])
 
 
 def tune(pos, q, p, trees, kinds=KINDS, lo=(0.0, 0.0, 0.0), side=1.0, batch_level=0, reps=5,
-         gate_e=1e-6, gate_f=1e-5, stream=None):
-    """Search ``kinds`` x ``trees`` (each a dict of make_config keywords, e.g.
-    {"depth": 8, "leaf_max": 64} or {"depth": 6}) for device tensors pos, q.
-    Returns (best Result or None, all Results)."""
+         gate_e=1e-6, gate_f=1e-5, stream=None, search_schedules=True, reference=None):
+    """Search ``trees`` x ``kinds`` x schedules (each tree a dict of
+    make_config keywords, e.g. {"depth": 8, "leaf_max": 64} or {"depth": 6})
+    for device tensors pos, q.  ``reference(tree, phi, force, energy) -> bool``,
+    if given, is a further check every accepted candidate must pass.  Returns
+    (best Result or None, all Results)."""
     import torch
     n = q.numel()
     stream = stream or torch.cuda.current_stream()
@@ -79,18 +114,21 @@ def tune(pos, q, p, trees, kinds=KINDS, lo=(0.0, 0.0, 0.0), side=1.0, batch_leve
         ref_cfg = B.make_config(p=p, precision=B.FMM_PREC_FP64, lo=lo, side=side,
                                 batch_level=batch_level, **tree)
         ws = torch.empty(B.fmm_workspace_size(ref_cfg, n), dtype=torch.uint8, device=pos.device)
-        ms64, _, f64, e64 = _time(torch, ref_cfg, n, pos, q, ws, stream, 1)
+        ms64, _, f64, e64 = _time(torch, ref_cfg, n, pos, q, ws, stream, 1, {})
         del ws
         fnorm = torch.linalg.vector_norm(f64)
         for kind in kinds:
             cfg = B.make_config(p=p, precision=B.FMM_PREC_MIXED, m2l_kind=getattr(B, "FMM_M2L_" + kind),
                                 lo=lo, side=side, batch_level=batch_level, **tree)
             ws = torch.empty(B.fmm_workspace_size(cfg, n), dtype=torch.uint8, device=pos.device)
-            ms, _, f, e = _time(torch, cfg, n, pos, q, ws, stream, reps)
+            for sched in (schedules_for(tree, kind) if search_schedules else [{}]):
+                ms, phi, f, e = _time(torch, cfg, n, pos, q, ws, stream, reps, sched)
+                r = Result(tree=dict(tree), kind=kind, ms=ms, energy_err=abs(e - e64) / abs(e64),
+                           force_err=float(torch.linalg.vector_norm(f - f64) / fnorm),
+                           schedule=dict(sched), extra={"fp64_ms": ms64})
+                if reference is not None and r.meets(gate_e, gate_f):
+                    r.reference_ok = bool(reference(tree, phi, f, e))
+                results.append(r)
             del ws
-            results.append(Result(tree=dict(tree), kind=kind, ms=ms,
-                                  energy_err=abs(e - e64) / abs(e64),
-                                  force_err=float(torch.linalg.vector_norm(f - f64) / fnorm),
-                                  extra={"fp64_ms": ms64}))
         torch.cuda.empty_cache()
     return select(results, gate_e, gate_f), results

@@ -27,7 +27,8 @@ PHASES = ["tree", "operators", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p", "energy
 EXPORTS = ["fmm_config_default", "fmm_workspace_size", "fmm_plan", "fmm_evaluate", "fmm_backward",
            "fmm_check", "fmm_destroy", "fmm_status_string", "fmm_plan_leaves", "fmm_plan_cube",
            "fmm_hilbert_index", "fmm_profile_enable", "fmm_profile_read", "fmm_plan_work", "fmm_plan_tree_stats",
-           "fmm_evaluate_static", "fmm_replan"]
+           "fmm_evaluate_static", "fmm_replan", "fmm_plan_set_schedule"]
+FMM_SCHED_P2P_PERSISTENT, FMM_SCHED_M2L_SPLIT = 0, 1
 FMM_STATIC_SCRATCH_BYTES = 128 << 20
 
 
@@ -84,6 +85,7 @@ def load(path=LIB_PATH):
     lib.fmm_plan_tree_stats.argtypes = [vp, ctypes.POINTER(i64)]
     lib.fmm_evaluate_static.argtypes = [cfgp, i64, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
     lib.fmm_replan.argtypes = [vp, vp, vp]
+    lib.fmm_plan_set_schedule.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     for name in EXPORTS:
         f = getattr(lib, name)
         if f.restype is ctypes.c_int or name in ("fmm_workspace_size", "fmm_plan", "fmm_evaluate",
@@ -91,7 +93,8 @@ def load(path=LIB_PATH):
                                                  "fmm_plan_leaves", "fmm_plan_cube",
                                                  "fmm_profile_enable", "fmm_profile_read",
                                                  "fmm_plan_work", "fmm_plan_tree_stats",
-                                                 "fmm_evaluate_static", "fmm_replan"):
+                                                 "fmm_evaluate_static", "fmm_replan",
+                                                 "fmm_plan_set_schedule"):
             f.restype = ctypes.c_int
     if path == LIB_PATH:
         _LIB = lib
@@ -177,6 +180,12 @@ def fmm_replan(plan, pos, stream=None):
     _require_on(pos, "pos", torch.float64, 3 * n, plan)
     _check(load().fmm_replan(plan, _ptr(pos), _stream_handle(stream)), "fmm_replan")
     return plan
+
+
+def fmm_plan_set_schedule(plan, key, value):
+    """Work distribution of the plan's passes (FMM_SCHED_*); results are unchanged
+    (M2L split: within rounding)."""
+    _check(load().fmm_plan_set_schedule(plan, int(key), int(value)), "fmm_plan_set_schedule")
 
 
 def _require_on(t, name, dtype, numel, plan):

@@ -153,6 +153,9 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
     lay->a_fscan = take(sizeof(uint32_t) * 2 * (BM + 1));
     lay->a_tgt = take(sizeof(uint32_t) * BM);
     lay->a_vtab = take(sizeof(uint32_t) * (size_t)lay->vtcap);
+    lay->a_p2p_bucket = take(BM);
+    lay->a_p2p_list = take(sizeof(uint32_t) * BM);
+    lay->a_p2p_ctl = take(sizeof(uint32_t) * 66);
     lay->a_small = take(sizeof(uint32_t) * 64);
     lay->a_stats = take(sizeof(int64_t) * 8);
   }
@@ -232,7 +235,11 @@ fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, in
   const int nevents = keep_operators ? P->nevents_created : 0;
   const int nrec = keep_operators ? P->nrec : 0;
   const bool is_static = keep_operators && P->is_static;
+  const int p2p_persistent = keep_operators ? P->p2p_persistent : 0;
+  const int m2l_split = keep_operators ? P->m2l_split : kM2lSplitPerXcd;
   memset(P, 0, sizeof(*P));
+  P->p2p_persistent = p2p_persistent;
+  P->m2l_split = m2l_split;
   P->ops_ready = ops_ready;
   P->profile_mask = mask;
   P->nevents_created = nevents;
@@ -257,6 +264,7 @@ fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, in
   if (e != hipSuccess) return FMM_E_DEVICE;
   if (P->adaptive && (P->nlist[0] > lay.ucap || P->nlist[1] > lay.wcap || P->nlist[2] > lay.xcap))
     return FMM_E_WORKSPACE;  // the tree's lists do not fit the workspace's list capacity
+  if (P->adaptive && launch_p2p_worklist(P, s) != hipSuccess) return FMM_E_DEVICE;
   if (P->Ld >= 2 && !P->ops_ready) {
     if (launch_operators(P, s) != hipSuccess) return FMM_E_DEVICE;
     P->ops_ready = true;
@@ -334,6 +342,22 @@ fmm_status fmm_plan(const fmm_config* cfg, int64_t n, const double* d_pos, void*
   }
   *out = P;
   return FMM_OK;
+}
+
+fmm_status fmm_plan_set_schedule(fmm_plan_t* P, int key, int value) {
+  if (!P) return FMM_E_INVALID_ARG;
+  switch (key) {
+    case FMM_SCHED_P2P_PERSISTENT:
+      if (value != 0 && value != 1) return FMM_E_INVALID_ARG;
+      if (value && !P->adaptive) return FMM_E_UNSUPPORTED;
+      P->p2p_persistent = value;
+      return FMM_OK;
+    case FMM_SCHED_M2L_SPLIT:
+      if (value < 0 || value > kM2lSplitPerXcd) return FMM_E_INVALID_ARG;
+      P->m2l_split = value;
+      return FMM_OK;
+  }
+  return FMM_E_INVALID_ARG;
 }
 
 fmm_status fmm_replan(fmm_plan_t* P, const double* d_pos, fmm_stream_t stream) {

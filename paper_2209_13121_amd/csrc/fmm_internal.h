@@ -133,6 +133,9 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t a_flag, a_fscan;  // scratch of the compaction (bmax + 1 each)
   size_t a_tgt;            // M2L targets per level and parity class (rows within the level)
   size_t a_vtab;           // M2L source rows per (tile, class, offset, target); vtcap entries
+  size_t a_p2p_bucket;     // P2P work-list: per box its cost bucket (255: no task)
+  size_t a_p2p_list;       // P2P work-list: leaves by decreasing pair count
+  size_t a_p2p_ctl;        // P2P work-list: 64 bucket offsets, the length, the ticket
   size_t a_small;          // per-level offsets and totals read back by the host
   size_t a_stats;          // 8 x int64 counters of the tree statistics
   int64_t bmax, ucap, wcap, xcap, vtcap, nbox_exp;  // bounds; nbox_exp = rows of the expansion arrays
@@ -181,6 +184,9 @@ struct fmm_plan_s {
   int nevents_created;
   bool is_static;  // the per-device plan of fmm_evaluate_static (not freed by fmm_destroy)
   bool ops_ready;  // the workspace holds the translation operators of (p, kind)
+  // schedule (fmm_plan_set_schedule): work distribution only
+  int p2p_persistent;  // adaptive P2P as a persistent kernel over the work-list
+  int m2l_split;       // split-M2L tail work-groups per XCD (0 .. kM2lSplitPerXcd)
 };
 
 namespace fmm {
@@ -225,6 +231,7 @@ hipError_t launch_adaptive_upward(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_adaptive_p2l(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_adaptive_downward(fmm_plan_s* P, hipStream_t s);
 hipError_t launch_adaptive_stats(fmm_plan_s* P, hipStream_t s);
+hipError_t launch_p2p_worklist(fmm_plan_s* P, hipStream_t s);  // p2p.hip
 hipError_t launch_l2p_adaptive(fmm_plan_s* P, hipStream_t s);  // downward.hip
 // M2M / L2L over the divided boxes of the adaptive tree (shift.hip)
 hipError_t launch_m2m_adaptive(fmm_plan_s* P, hipStream_t s);

@@ -502,7 +502,7 @@ __global__ __launch_bounds__(64) void k_m2l_add_half(m2l::Args a, int nc, const 
 m2l::Args split_args(fmm_plan_s* Pl) {
   m2l::Args a = m2l::make_args(Pl);
   const int64_t per_xcd = (a.ngroups + 7) / 8;
-  a.ksplit = per_xcd < kM2lSplitPerXcd ? per_xcd : kM2lSplitPerXcd;
+  a.ksplit = per_xcd < Pl->m2l_split ? per_xcd : Pl->m2l_split;
   return a;
 }
 

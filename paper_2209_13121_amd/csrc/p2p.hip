@@ -291,17 +291,26 @@ __device__ __forceinline__ void tile_big(Acc<T> (&acc)[kKMax], const Tgt<T> (&tg
   }
 }
 
+// LDS of one wave's leaf.
+template <typename T>
+struct P2PShared {
+  SSrc<T> sS[kTile];
+  Nb sNb[kNbBatch];
+  uint32_t sPre[kNbBatch + 1];
+};
+
+// The near field of target leaf b (one wave).
 template <typename T, typename NBS>
-__global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p(NBS nbs, int64_t nbox, const DevParams* __restrict__ dp,
-                                            const Rec<double>* __restrict__ src, FinishArgs fa) {
-  __shared__ SSrc<T> sS[kTile];
-  __shared__ Nb sNb[kNbBatch];
-  __shared__ uint32_t sPre[kNbBatch + 1];
-  const int64_t b = blockIdx.x;
+__device__ __forceinline__ void p2p_leaf(const NBS& nbs, int64_t b, P2PShared<T>& sh,
+                                         const DevParams* __restrict__ dp,
+                                         const Rec<double>* __restrict__ src, const FinishArgs& fa) {
+  SSrc<T>* sS = sh.sS;
+  Nb* sNb = sh.sNb;
+  uint32_t* sPre = sh.sPre;
   const int lane = threadIdx.x;
   uint32_t t0, nt;
   int lt;
-  if (b >= nbox || !nbs.target(b, t0, nt, lt)) return;  // uniform over the wave
+  if (!nbs.target(b, t0, nt, lt)) return;  // uniform over the wave
   // target layout: small leaves split the sources over lane groups, large
   // ones take up to kKMax targets per lane, in groups of 64 kKMax targets
   // (each group stages the sources again)
@@ -392,6 +401,93 @@ __global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p(NBS nbs, int64_
     acc[0].nz += __shfl_xor(acc[0].nz, w, 64);
   }
   if (lane < (int)nt) finish_particle<T>(fa, (int64_t)t0 + lane, (double)(1 << lt) / dp->side, acc[0]);
+}
+
+// One wave per box (boxes that are no leaf, or empty, return at once).
+template <typename T, typename NBS>
+__global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p(NBS nbs, int64_t nbox, const DevParams* __restrict__ dp,
+                                            const Rec<double>* __restrict__ src, FinishArgs fa) {
+  __shared__ P2PShared<T> sh;
+  if ((int64_t)blockIdx.x >= nbox) return;
+  p2p_leaf<T, NBS>(nbs, blockIdx.x, sh, dp, src, fa);
+}
+
+// Persistent form over a work-list: the non-empty leaves in order of
+// decreasing pair count (built at plan time by k_p2p_worklist), taken one at a
+// time by resident waves through a ticket counter (zeroed before the launch),
+// so the costliest leaves start first and no wave waits for an empty box.
+// Every wave leaves once the tickets pass the list's length.  Each leaf's
+// outputs are written by its one task in a fixed order, so the result does
+// not depend on which wave takes it.
+template <typename T, typename NBS>
+__global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p_persistent(
+    NBS nbs, const uint32_t* __restrict__ worklist, const uint32_t* __restrict__ ntasks,
+    uint32_t* __restrict__ ticket, const DevParams* __restrict__ dp, const Rec<double>* __restrict__ src,
+    FinishArgs fa) {
+  __shared__ P2PShared<T> sh;
+  const uint32_t n = ntasks[0];
+  for (;;) {
+    uint32_t t = 0;
+    if (threadIdx.x == 0) t = atomicAdd(ticket, 1u);
+    t = __shfl(t, 0, 64);
+    if (t >= n) break;  // uniform over the wave
+    p2p_leaf<T, NBS>(nbs, worklist[t], sh, dp, src, fa);
+    __syncthreads();  // the tile of this leaf is no longer read
+  }
+}
+
+// Work-list of the adaptive tree's non-empty leaves by decreasing pair count
+// n_b sum_{c in U(b)} n_c: a leaf's bucket is the bit length of its count
+// (64 buckets, costliest first).  Counts and positions are taken per
+// work-group in LDS and reserved in the global buckets by one atomic per
+// (work-group, bucket); the order within a bucket only steers the schedule.
+__global__ void k_p2p_cost(AdaptiveNbs nbs, int64_t nbox, uint8_t* __restrict__ bucket,
+                           uint32_t* __restrict__ hist) {
+  __shared__ uint32_t sh[64];
+  if (threadIdx.x < 64) sh[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint8_t k = 255;  // not a task
+  uint32_t t0, nt;
+  int lt;
+  if (b < nbox && nbs.target(b, t0, nt, lt)) {
+    uint64_t ns = 0;
+    const int nn = nbs.count(b);
+    for (int j = 0; j < nn; ++j) ns += nbs.range[2 * nbs.uidx[nbs.uoff[b] + j] + 1];
+    const uint64_t cost = (uint64_t)nt * ns;
+    k = (uint8_t)(63 - __clzll(cost | 1ull));
+    atomicAdd(&sh[63 - k], 1u);  // bucket 63 - k: the costliest first
+  }
+  if (b < nbox) bucket[b] = k;
+  __syncthreads();
+  if (threadIdx.x < 64 && sh[threadIdx.x]) atomicAdd(&hist[threadIdx.x], sh[threadIdx.x]);
+}
+
+// Exclusive scan of the 64 bucket counts (one wave) and the list length.
+__global__ void k_p2p_hist_scan(uint32_t* __restrict__ hist, uint32_t* __restrict__ ntasks) {
+  const int lane = threadIdx.x;
+  uint32_t c = hist[lane];
+#pragma unroll
+  for (int w = 1; w < 64; w <<= 1) {
+    const uint32_t v = __shfl_up(c, w, 64);
+    if (lane >= w) c += v;
+  }
+  hist[lane] = c - hist[lane];  // exclusive
+  if (lane == 63) ntasks[0] = c;
+}
+
+__global__ void k_p2p_worklist(int64_t nbox, const uint8_t* __restrict__ bucket,
+                               uint32_t* __restrict__ hist, uint32_t* __restrict__ worklist) {
+  __shared__ uint32_t cnt[64], base[64];
+  if (threadIdx.x < 64) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = b < nbox && bucket[b] != 255 ? 63 - bucket[b] : -1;
+  const uint32_t r = k >= 0 ? atomicAdd(&cnt[k], 1u) : 0u;
+  __syncthreads();
+  if (threadIdx.x < 64) base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&hist[threadIdx.x], cnt[threadIdx.x]) : 0u;
+  __syncthreads();
+  if (k >= 0) worklist[base[k] + r] = (uint32_t)b;
 }
 
 // Uniform tree with small leaves: one wave per parent box P (level L - 1),
@@ -539,6 +635,32 @@ __global__ void k_energy(const double* __restrict__ part, int64_t nparts, double
 
 }  // namespace
 
+namespace {
+AdaptiveNbs adaptive_nbs(fmm_plan_s* P) {
+  const Layout& lay = P->lay;
+  return AdaptiveNbs{wsp<int32_t>(P, lay.a_level), wsp<uint32_t>(P, lay.a_coord),
+                     wsp<uint32_t>(P, lay.a_range), wsp<int32_t>(P, lay.a_child0),
+                     wsp<uint32_t>(P, lay.a_off), wsp<uint32_t>(P, lay.a_uidx)};
+}
+}  // namespace
+
+// Plan time (adaptive tree, after its lists): the P2P work-list of the
+// persistent form.  Device work only; no read-back.
+hipError_t launch_p2p_worklist(fmm_plan_s* P, hipStream_t s) {
+  const Layout& lay = P->lay;
+  const int64_t nbox = P->ce_off[P->Ld + 1];
+  uint32_t* ctl = wsp<uint32_t>(P, lay.a_p2p_ctl);  // [64] bucket counts, [64] tasks, [65] ticket
+  uint8_t* bucket = wsp<uint8_t>(P, lay.a_p2p_bucket);
+  hipError_t e = fill_u32(ctl, 66, 0u, s);
+  if (e != hipSuccess) return e;
+  if (nbox > 0) k_p2p_cost<<<grid_for(nbox, kBlock), kBlock, 0, s>>>(adaptive_nbs(P), nbox, bucket, ctl);
+  k_p2p_hist_scan<<<1, 64, 0, s>>>(ctl, ctl + 64);
+  if (nbox > 0)
+    k_p2p_worklist<<<grid_for(nbox, kBlock), kBlock, 0, s>>>(nbox, bucket, ctl,
+                                                               wsp<uint32_t>(P, lay.a_p2p_list));
+  return hipGetLastError();
+}
+
 hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
                                   double* d_energy, const double* adj_g, double* dEdq,
                                   double* dEdx, hipStream_t s) {
@@ -564,14 +686,26 @@ hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
   const DevParams* dp = wsp<DevParams>(P, lay.params);
   const Rec<double>* src = wsp<Rec<double>>(P, P->mixed ? lay.src64 : lay.src);
   if (P->adaptive) {
-    AdaptiveNbs nb{wsp<int32_t>(P, lay.a_level), wsp<uint32_t>(P, lay.a_coord),
-                   wsp<uint32_t>(P, lay.a_range), wsp<int32_t>(P, lay.a_child0),
-                   wsp<uint32_t>(P, lay.a_off), wsp<uint32_t>(P, lay.a_uidx)};
+    const AdaptiveNbs nb = adaptive_nbs(P);
     const int64_t nbox = P->ce_off[P->Ld + 1];
-    if (P->mixed)
+    if (P->p2p_persistent) {
+      // resident waves over the work-list (16 per CU cover the occupancy of
+      // both forms; surplus waves find no ticket and leave)
+      uint32_t* ticket = wsp<uint32_t>(P, lay.a_p2p_ctl) + 65;
+      hipError_t e = fill_u32(ticket, 1, 0u, s);
+      if (e != hipSuccess) return e;
+      const uint32_t* wl = wsp<uint32_t>(P, lay.a_p2p_list);
+      const uint32_t* nt = wsp<uint32_t>(P, lay.a_p2p_ctl) + 64;
+      const unsigned grid = 256 * 16;
+      if (P->mixed)
+        k_p2p_persistent<float, AdaptiveNbs><<<grid, 64, 0, s>>>(nb, wl, nt, ticket, dp, src, fa);
+      else
+        k_p2p_persistent<double, AdaptiveNbs><<<grid, 64, 0, s>>>(nb, wl, nt, ticket, dp, src, fa);
+    } else if (P->mixed) {
       k_p2p<float, AdaptiveNbs><<<(unsigned)nbox, 64, 0, s>>>(nb, nbox, dp, src, fa);
-    else
+    } else {
       k_p2p<double, AdaptiveNbs><<<(unsigned)nbox, 64, 0, s>>>(nb, nbox, dp, src, fa);
+    }
   } else {
     UniformNbs nb{L, wsp<uint32_t>(P, lay.leaf_start), wsp<uint32_t>(P, lay.coord2slot) + lay.lvl_off[L],
                   wsp<uint32_t>(P, lay.slot2coord) + lay.lvl_off[L]};

@@ -25,15 +25,50 @@ def test_select_ties_and_none():
     assert T.select([R(1.0, 1e-6, 1e-5)]) is not None
 
 
+def test_schedules_per_form_and_tree():
+    # the P2P schedule applies to adaptive trees, the tail split to split forms
+    assert T.schedules_for({"depth": 6}, "F32") == [{}]
+    assert len(T.schedules_for({"depth": 6}, "F16X2")) == 3
+    assert len(T.schedules_for({"depth": 7, "leaf_max": 64}, "F32")) == 2
+    s = T.schedules_for({"depth": 7, "leaf_max": 64}, "BF16X3")
+    assert len(s) == 6 and all(set(x) == {"p2p_persistent", "m2l_split"} for x in s)
+
+
+def test_reference_check_excludes():
+    r = R(1.0, 1e-9, 1e-9)
+    r.reference_ok = False
+    assert T.select([r]) is None
+
+
 @pytest.mark.gpu
 def test_tune_on_clusters():
+    """The tuner's choice meets the gate, is the fastest candidate that does,
+    and every accepted candidate also matches the oracle's adaptive FMM (same
+    tree and p) on 512 sampled sites."""
+    import numpy as np
     import torch
+
+    import oracle
+    from gpu_util import elem, rel
     from paper_2209_13121_amd import workloads as W
-    pos, q, _ = W.molecular_clusters(50_000, 61)
+    pos, q, _ = W.molecular_clusters(10_000, 61)
     dev = torch.device("cuda:0")
     tp, tq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
-    best, results = T.tune(tp, tq, 8, [{"depth": 7, "leaf_max": 32}, {"depth": 7, "leaf_max": 64}],
-                           side=0.0, reps=3)
-    assert len(results) == 6
+    idx = np.random.default_rng(62).choice(len(q), 512, replace=False)
+    cache = {}
+
+    def reference(tree, phi, force, energy):
+        key = tree["leaf_max"]
+        if key not in cache:
+            ph, fo, _, _ = oracle.fmm_adaptive(pos, q, tree["leaf_max"], tree["depth"], 8, side=0.0)
+            cache[key] = (ph[idx], fo[idx])
+        ph, fo = cache[key]
+        fg = force.cpu().numpy()[idx]
+        return rel(fg, fo) <= 1e-5 and elem(fg, fo) <= 1e-4 and rel(phi.cpu().numpy()[idx], ph) <= 1e-5
+
+    trees = [{"depth": 7, "leaf_max": 32}, {"depth": 7, "leaf_max": 64}]
+    best, results = T.tune(tp, tq, 8, trees, side=0.0, reps=3, reference=reference)
+    assert len(results) == 2 * (6 + 6 + 2)
     assert best is not None and best.meets(1e-6, 1e-5)
     assert all(best.ms <= r.ms for r in results if r.meets(1e-6, 1e-5))
+    assert all(r.reference_ok for r in results)

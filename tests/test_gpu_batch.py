@@ -93,6 +93,41 @@ def test_many_tiny_systems_depth_at_batch_level():
     assert abs(e - (-1.0 / r).sum()) <= 1e-13 * abs((1.0 / r).sum())
 
 
+@pytest.mark.parametrize("prec", [B.FMM_PREC_MIXED, B.FMM_PREC_FP64])
+def test_schedules_give_the_same_result(prec):
+    """The persistent work-list P2P equals the per-box launch bitwise; the M2L
+    tail split only reorders a sum (within rounding); bad keys are refused."""
+    import torch
+    pos, q, counts = small_batch()
+    dev = torch.device("cuda:0")
+    tp, tq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
+    f = B.FMM(tp, p=4, depth=6, precision=prec, lo=(0.0, 0.0, 0.0), side=4.0, leaf_max=16,
+              batch_level=2)
+    a = f.evaluate(tq)
+    B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_P2P_PERSISTENT, 1)
+    b = f.evaluate(tq)
+    B.fmm_replan(f.plan, tp)  # the schedule survives a re-plan
+    c = f.evaluate(tq)
+    assert f.check() == 0
+    for x, y, z in zip(a, b, c):
+        assert torch.equal(x, y) and torch.equal(x, z)
+    for split in (0, 8):
+        B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_M2L_SPLIT, split)
+        d = f.evaluate(tq)
+        assert_close(d[0].cpu().numpy(), a[0].cpu().numpy(), 1e-12 if prec == B.FMM_PREC_FP64 else 1e-6,
+                     what=f"phi split {split}")
+    with pytest.raises(B.FMMError):
+        B.fmm_plan_set_schedule(f.plan, 7, 0)
+    with pytest.raises(B.FMMError):
+        B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_M2L_SPLIT, 17)
+    f.close()
+    u = B.FMM(tp[:1000].contiguous(), p=4, depth=3, precision=prec, lo=(0.0, 0.0, 0.0), side=4.0)
+    with pytest.raises(B.FMMError) as ei:  # the work-list exists for adaptive trees only
+        B.fmm_plan_set_schedule(u.plan, B.FMM_SCHED_P2P_PERSISTENT, 1)
+    assert ei.value.status == 6
+    u.close()
+
+
 def test_graph_replay_equals_eager():
     import torch
     pos, q, counts = small_batch()
