@@ -68,6 +68,17 @@ constexpr int kM2lbLdsBudgetAd = 156 * 1024;
 __host__ __device__ constexpr int m2lb_gq(int kc, int np) { return (kc * np) | 1; }
 __host__ __device__ constexpr int m2lb_qcs(int kc, int np) { return 4 * m2lb_gq(kc, np) + 2; }
 __host__ __device__ constexpr int m2lb_rows(int nc) { return ((nc + 15) / 16) * 16; }
+// Wide FP16 form (p <= kM2lWidePMax; 32 x 32 x 16 MFMA, a wave per 32
+// targets): an operator is stored [row < ncoef][quad], quad 2 kb + piece
+// holding k = 8 kb .. 8 kb + 7, then one zero quad, so rows are an odd number
+// of quads apart: the 32 rows of a 16-byte LDS read fall on distinct quads
+// modulo 32.  Staged into LDS as one contiguous copy.
+#ifndef M2L_WIDE_PMAX
+#define M2L_WIDE_PMAX 8
+#endif
+constexpr int kM2lWidePMax = M2L_WIDE_PMAX;
+__host__ __device__ constexpr bool m2l_f16_wide(int p) { return p <= kM2lWidePMax; }
+__host__ __device__ constexpr int m2lw_row_quads(int nc) { return 8 * m2lb_ksteps(nc) + 1; }
 __host__ __device__ constexpr int m2lb_kc_fit(int nc, int np, int n, bool ad) {
   return n <= 1 ? 1
                 : (2 * m2lb_rows(nc) * m2lb_qcs(n, np) * 16 <= (ad ? kM2lbLdsBudgetAd : kM2lbLdsBudget)

@@ -63,6 +63,8 @@ using m2l::kThreads;
 #define M2LB_OP2 1
 #endif
 constexpr int kFlush = M2LB_FLUSH;
+// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt not waited for
+constexpr int kVmcntZero = 0x0F70;
 // FP16 form: offsets per FP32 partial sum.
 constexpr int kGroupF16 = 8;
 
@@ -473,6 +475,351 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
     }
 }
 
+// Wide FP16 form (p <= kM2lWidePMax): the same products on
+// v_mfma_f32_32x32x16_f16.  A work-group of 4 waves owns a 128-target tile
+// (the tiles of m2l_common.h); lane (c, h) = (lane % 32, lane / 32) of a wave
+// holds target c of its 32 and the k half h of every 16-wide k step.  Each
+// 16-byte A read from LDS feeds a 32 x 32 block, and the work-group's LDS (two
+// operator buffers and the halo) leaves room for two work-groups per CU.
+//  * Operators: [row][quad] (m2lw_row_quads), copied per offset from global
+//    memory straight into the LDS buffer not being read (global_load_lds, 64
+//    quads per wave instruction), waited for before the offset's barrier.
+//  * Sources: the FP16 pieces of k_split_mult_h (quad (ks * 2 + piece) * 4 +
+//    g holds k = 32 ks + 8 g ..); lane (c, h) takes quad (ks * 2 + piece) * 4
+//    + 2 (s % 2) + h of k step s (ks = s / 2), all loaded one offset ahead.
+//  * Source reuse between offsets (uniform tree, whole tiles): the source of
+//    target t at offset d is box t - d, so after offset d the source of t at
+//    d + D is the one its lattice neighbour t - D held at d.  The 128 targets
+//    of a full tile are the class-pi children of an 8 x 4 x 4 block of
+//    parents; they are laid out so that each wave holds a 4 x 4 x 2 sub-block,
+//    lane c = a + 4 b + 16 c' along the block's axes (A the long one, B, C the
+//    others in index order), and every class walks its 189 offsets in an
+//    order (kChainOrder) of 3 x 3 snakes in (d_A, d_B) with steps of 2 per
+//    d_C: after a step D = +-2 e_A or +-2 e_B a lane takes its neighbour's
+//    source quads by a DPP row shift (the rows of 16 lanes hold a 4 x 4 (a,
+//    b) layer), and only the lanes on the face the step uncovers load from
+//    memory.  39 of the 189 offsets load every row, 150 a quarter of them: the
+//    source traffic drops to 40 %.
+//  * Accumulator layout (32 x 32 FP32 output): lane l holds column l % 32,
+//    element e row 8 (e / 4) + 4 (l / 32) + e % 4.
+//  * Rows past ncoef read row ncoef - 1 (their output rows are not stored).
+//  * Tiers, chains of kGroupF16 offsets and the final scaling as in k_m2l_bf.
+constexpr int kWideWaves = 4;
+constexpr int kWideThreads = kWideWaves * 64;
+static_assert(kWideWaves * 32 == m2l::kTargetsPerGroup, "a wide work-group covers one tile");
+constexpr bool f16_cross_w(int rb, int s) { return isqrt_c(32 * rb) + isqrt_c(16 * s) < kF16Tier; }
+
+// Offset orders of the reuse form, per long axis A and class: code = op |
+// (dx + 4) << 9 | (dy + 4) << 13 | (dz + 4) << 17 | move << 21, move = how the
+// offset follows the previous one: 0 none (every lane loads), 1 d_A + 2,
+// 2 d_A - 2, 3 d_B + 2, 4 d_B - 2.
+struct ChainOrder {
+  uint32_t v[3][8][kIL];
+};
+constexpr int chain_other(int A, int k) { return k == 0 ? (A == 0 ? 1 : 0) : (A == 2 ? 1 : 2); }
+constexpr ChainOrder make_chain_order() {
+  ChainOrder t{};
+  for (int A = 0; A < 3; ++A) {
+    const int B = chain_other(A, 0), C = chain_other(A, 1);
+    for (int pi = 0; pi < 8; ++pi) {
+      const int pa[3] = {(pi >> 2) & 1, (pi >> 1) & 1, pi & 1};
+      int n = 0, prev[3] = {0, 0, 0};
+      bool have = false;
+      for (int dc = pa[C] - 3; dc <= pa[C] + 2; ++dc)
+        for (int ra = 0; ra < 2; ++ra)
+          for (int rb = 0; rb < 2; ++rb)
+            for (int jj = 0; jj < 3; ++jj)
+              for (int ii = 0; ii < 3; ++ii) {
+                const int i = jj % 2 == 0 ? ii : 2 - ii;  // snake over the 3 x 3 grid
+                int d[3] = {0, 0, 0};
+                d[A] = pa[A] - 3 + ra + 2 * i;
+                d[B] = pa[B] - 3 + rb + 2 * jj;
+                d[C] = dc;
+                if (d[0] >= -1 && d[0] <= 1 && d[1] >= -1 && d[1] <= 1 && d[2] >= -1 && d[2] <= 1) continue;
+                uint32_t move = 0;
+                if (have && d[C] == prev[C]) {
+                  if (d[B] == prev[B] && d[A] == prev[A] + 2) move = 1;
+                  if (d[B] == prev[B] && d[A] == prev[A] - 2) move = 2;
+                  if (d[A] == prev[A] && d[B] == prev[B] + 2) move = 3;
+                  if (d[A] == prev[A] && d[B] == prev[B] - 2) move = 4;
+                }
+                t.v[A][pi][n++] = (uint32_t)m2l_op_index(d[0], d[1], d[2]) | (uint32_t)(d[0] + 4) << 9 |
+                                  (uint32_t)(d[1] + 4) << 13 | (uint32_t)(d[2] + 4) << 17 | move << 21;
+                prev[0] = d[0];
+                prev[1] = d[1];
+                prev[2] = d[2];
+                have = true;
+              }
+    }
+  }
+  return t;
+}
+// every order holds the class's 189 interaction-list offsets once each
+constexpr bool chain_order_ok(const ChainOrder& t) {
+  for (int A = 0; A < 3; ++A)
+    for (int pi = 0; pi < 8; ++pi) {
+      bool seen[216] = {};
+      for (int k = 0; k < kIL; ++k) {
+        const uint32_t c = t.v[A][pi][k];
+        const int d[3] = {(int)((c >> 9) & 15u) - 4, (int)((c >> 13) & 15u) - 4, (int)((c >> 17) & 15u) - 4};
+        int cell = 0;
+        bool near = true;
+        for (int q = 0; q < 3; ++q) {
+          const int pq = (pi >> (2 - q)) & 1, u = d[q] - (pq - 3);
+          if (u < 0 || u > 5) return false;
+          cell = cell * 6 + u;
+          near = near && d[q] >= -1 && d[q] <= 1;
+        }
+        if (near || seen[cell] || (int)(c & 511u) != m2l_op_index(d[0], d[1], d[2])) return false;
+        seen[cell] = true;
+      }
+    }
+  return true;
+}
+static_assert(chain_order_ok(make_chain_order()), "offset orders of the reuse form");
+static __constant__ ChainOrder kChainOrder = make_chain_order();
+
+template <int P>
+struct WShape {
+  static constexpr int NC = (P + 1) * (P + 1);
+  static constexpr int RB = (NC + 31) / 32;        // 32-row blocks
+  static constexpr int KS = (NC + 15) / 16;        // 16-wide k steps with data
+  static constexpr int QR = m2lb_row_quads(NC, 2);  // quads per source box
+  static constexpr int QW = m2lw_row_quads(NC);     // quads per operator row
+  static constexpr int NQ = NC * QW;               // quads per operator
+  static constexpr int NCHUNK = (NQ + 63) / 64;    // 64-quad copies per operator
+  static constexpr int NQP = NCHUNK * 64;          // LDS quads per buffer
+};
+
+// The 16-byte quad v of the lane that the DPP row shift CTRL names (zero
+// where the row has no such lane)
+template <int CTRL>
+__device__ __forceinline__ u32x4 dpp_quad(u32x4 v) {
+  u32x4 r;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) r[w] = (uint32_t)__builtin_amdgcn_mov_dpp((int)v[w], CTRL, 0xF, 0xF, true);
+  return r;
+}
+template <int CTRL, int KS>
+__device__ __forceinline__ void dpp_rows(const u32x4* bh, const u32x4* bl, u32x4* nh, u32x4* nl) {
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    nh[s] = dpp_quad<CTRL>(bh[s]);
+    nl[s] = dpp_quad<CTRL>(bl[s]);
+  }
+}
+
+template <int P, bool AD>
+__global__ __launch_bounds__(kWideThreads, 2) void k_m2l_w(m2l::Args a, const u32x4* __restrict__ multq,
+                                                         const u32x4* __restrict__ zero_q,
+                                                         const u32x4* __restrict__ ops,
+                                                         float* __restrict__ out,
+                                                         const uint32_t* __restrict__ lmax,
+                                                         const float* __restrict__ rowf,
+                                                         float* __restrict__ half_out) {
+  typedef WShape<P> S;
+  typedef Prod<2> PR;
+  typedef float f32x16 __attribute__((ext_vector_type(16)));
+  constexpr int NC = S::NC, RB = S::RB, KS = S::KS, QR = S::QR, QW = S::QW;
+  static_assert(S::NQ <= m2lb_op_quads(S::NC, 2, AD), "the wide operators fit the split-operator array");
+  __shared__ u32x4 sT0[S::NQP];
+  __shared__ u32x4 sT1[S::NQP];
+  __shared__ uint32_t sSlot[AD ? 1 : m2l::kHalo];
+  __shared__ int sBox[6];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 31, hk = lane >> 5;
+  m2l::TileT<AD, true> tl;
+  if (!tl.setup(a, wave * 32 + col, sSlot, sBox)) return;  // uniform over the work-group
+  const int pi = tl.pi;
+  const bool whole = tl.part < 0;
+  const int i0 = whole ? 0 : tl.part * kIL / kM2lParts;
+  const int i1 = whole ? kIL : (tl.part + 1) * kIL / kM2lParts;
+  const u32x4* mlev = multq + tl.lvl_off * QR;
+
+  // Source reuse: a whole tile of the uniform tree whose parents form an
+  // 8 x 4 x 4 block (sBox holds 2 pmin - 2 and 2 pmax + 3 per axis).
+  bool chain = false;
+  int ax = 0;
+  if constexpr (!AD) {
+    int ext[3], lo[3], n8 = 0, n4 = 0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = (sBox[k] + 2) / 2;
+      ext[k] = (sBox[3 + k] - 3) / 2 - lo[k] + 1;
+      n8 += ext[k] == 8;
+      n4 += ext[k] == 4;
+      if (ext[k] == 8) ax = k;
+    }
+    chain = __syncthreads_and(whole && n8 == 1 && n4 == 2 && tl.col_ok);  // a full tile
+    if (chain) {
+      // lane c = a + 4 b + 16 c': parent lo + (4 (w & 1) + a) e_A + b e_B + (2 (w >> 1) + c') e_C
+      const int B = chain_other(ax, 0);
+      const int ua = 4 * (wave & 1) + (col & 3), ub = (col >> 2) & 3, uc = 2 * (wave >> 1) + (col >> 4);
+      int pc[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) pc[k] = lo[k] + (k == ax ? ua : (k == B ? ub : uc));
+      tl.tx = 2 * pc[0] + ((pi >> 2) & 1);
+      tl.ty = 2 * pc[1] + ((pi >> 1) & 1);
+      tl.tz = 2 * pc[2] + (pi & 1);
+      tl.col_ok = true;
+    }
+  }
+  const uint32_t* ord = kChainOrder.v[ax][pi];
+  // offset k of this work-group's order: its operator and (dx, dy, dz)
+  auto offset_at = [&](int k, int& dx, int& dy, int& dz) -> int {
+    if constexpr (AD) return m2l::il_offset(pi, k, dx, dy, dz);  // the source table's order
+    const uint32_t c = ord[k];
+    dx = (int)((c >> 9) & 15u) - 4;
+    dy = (int)((c >> 13) & 15u) - 4;
+    dz = (int)((c >> 17) & 15u) - 4;
+    return (int)(c & 511u);
+  };
+  auto move_at = [&](int k) -> int { return chain ? (int)((ord[k] >> 21) & 7u) : 0; };
+
+  f32x16 sum[RB], acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) sum[r][e] = acc[r][e] = 0.f;
+
+  // operator op into buf: wave w copies the 64-quad chunks w, w + 4, ...
+  // (reads past the operator's end are clamped to its last quad; they land
+  // in the buffer's padding)
+  auto stage = [&](int op, u32x4* buf) {
+    const u32x4* base = ops + (size_t)op * S::NQ;
+#pragma unroll
+    for (int j = 0; j < (S::NCHUNK + kWideWaves - 1) / kWideWaves; ++j) {
+      const int e0 = (j * kWideWaves + wave) * 64;
+      if (e0 < S::NQP) {
+        const int e = e0 + lane;
+        __builtin_amdgcn_global_load_lds(
+            (__attribute__((address_space(1))) void*)(base + (e < S::NQ ? e : S::NQ - 1)),
+            (__attribute__((address_space(3))) void*)(buf + e0), 16, 0, 0);
+      }
+    }
+  };
+  auto row_of = [&](m2l::Src src) -> const u32x4* {
+    return src.ok ? mlev + (int64_t)src.slot * QR : zero_q;
+  };
+  // B quads of a source row for this lane: all k steps, both pieces
+  auto load_b = [&](const u32x4* ms, u32x4* bh, u32x4* bl) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      bh[s] = ms[((s >> 1) * 2 + 0) * 4 + 2 * (s & 1) + hk];
+      bl[s] = ms[((s >> 1) * 2 + 1) * 4 + 2 * (s & 1) + hk];
+    }
+  };
+  // B of the next offset from this one's by a row shift
+  auto shift_b = [&](int mv, const u32x4* bh, const u32x4* bl, u32x4* nh, u32x4* nl) {
+    switch (mv) {
+      case 1:  // from lane a - 1 (row_shr:1)
+        dpp_rows<0x111, KS>(bh, bl, nh, nl);
+        break;
+      case 2:  // from lane a + 1 (row_shl:1)
+        dpp_rows<0x101, KS>(bh, bl, nh, nl);
+        break;
+      case 3:  // from lane b - 1 (row_shr:4)
+        dpp_rows<0x114, KS>(bh, bl, nh, nl);
+        break;
+      default:  // from lane b + 1 (row_shl:4)
+        dpp_rows<0x104, KS>(bh, bl, nh, nl);
+        break;
+    }
+  };
+  // lanes with no neighbour for move mv (they load)
+  const int la = col & 3, lb = (col >> 2) & 3;
+  auto face = [&](int mv) -> bool {
+    return mv == 0 || (mv == 1 && la == 0) || (mv == 2 && la == 3) || (mv == 3 && lb == 0) ||
+           (mv == 4 && lb == 3);
+  };
+  // this lane's operator rows (rows past ncoef read the last one)
+  int arow[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int row = 32 * r + col;
+    arow[r] = (row < NC ? row : NC - 1) * QW + 2 * hk;
+  }
+  auto compute = [&](const u32x4* buf, const u32x4* bh, const u32x4* bl) {
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      u32x4 ah[RB], al[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        ah[r] = buf[arow[r] + 4 * s];
+        if (f16_cross_w(r, s)) al[r] = buf[arow[r] + 4 * s + 1];
+      }
+#pragma unroll
+      for (int t = 0; t < PR::N; ++t)
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+          if (t == PR::N - 1 || f16_cross_w(r, s))
+            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                __builtin_bit_cast(f16x8, PR::a[t] ? al[r] : ah[r]),
+                __builtin_bit_cast(f16x8, PR::b[t] ? bl[s] : bh[s]), acc[r], 0, 0, 0);
+    }
+  };
+
+  u32x4 bh0[KS], bl0[KS], bh1[KS], bl1[KS];
+  int i = i0, ndx, ndy, ndz;
+  auto lookup_at = [&](int k) -> m2l::Src {
+    int ldx, ldy, ldz;
+    const int kk = k < i1 ? k : i1 - 1;
+    offset_at(kk, ldx, ldy, ldz);
+    return tl.lookup(sSlot, kk, ldx, ldy, ldz);
+  };
+  m2l::Src cur_src = lookup_at(i0), next_src = lookup_at(i0 + 1);
+  load_b(row_of(cur_src), bh0, bl0);
+  stage(offset_at(i0, ndx, ndy, ndz), sT0);
+  __builtin_amdgcn_s_waitcnt(kVmcntZero);
+  __syncthreads();
+  // offset i: its operator in bufc, its B in (bhc, blc); the next offset's B
+  // goes to (bhn, bln) (shifted from this one's and completed by the face
+  // lanes' loads, or loaded by every lane) and its operator to bufn.
+  auto do_offset = [&](const u32x4* bufc, u32x4* bufn, u32x4* bhc, u32x4* blc, u32x4* bhn,
+                       u32x4* bln) -> bool {
+    const bool more = i + 1 < i1;
+    const m2l::Src far_src = lookup_at(i + 2);
+    if (more) {
+      stage(offset_at(i + 1, ndx, ndy, ndz), bufn);
+      const int mv = move_at(i + 1);
+      if (mv != 0) shift_b(mv, bhc, blc, bhn, bln);
+      if (face(mv)) load_b(row_of(next_src), bhn, bln);
+    }
+    if (__any(cur_src.ok)) compute(bufc, bhc, blc);
+    if ((i + 1 - i0) % kGroupF16 == 0 || !more) {
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        sum[r] += acc[r];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[r][e] = 0.f;
+      }
+    }
+    if (!more) return false;
+    __builtin_amdgcn_s_waitcnt(kVmcntZero);  // this wave's part of the copy has landed
+    __syncthreads();
+    ++i;
+    cur_src = next_src;
+    next_src = far_src;
+    return true;
+  };
+  while (do_offset(sT0, sT1, bh0, bl0, bh1, bl1) && do_offset(sT1, sT0, bh1, bl1, bh0, bl0)) {
+  }
+
+  if (!tl.col_ok) return;
+  float* o = !whole && tl.part > 0
+                 ? half_out + ((tl.sidx * (kM2lParts - 1) + tl.part - 1) * m2l::kTargetsPerGroup + wave * 32 + col) * NC
+                 : out + (tl.lvl_off + tl.target_slot(a)) * NC;
+  const float lsc = ldexpf(1.f, f16_level_exp(lmax[tl.l]) - 14);
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int row = 32 * r + 8 * (e / 4) + 4 * hk + e % 4;
+      if (row < NC) o[row] = sum[r][e] * (rowf[row] * lsc);
+    }
+}
+
 // Parts 1.. of the split groups into the M2L result: one wave per (split
 // group, target of its tile), the lanes along the target's row (the same
 // decoding as the M2L kernel); each sum is part 0 + part 1 + ..., in that
@@ -580,7 +927,16 @@ struct M2LBfRun {
     prof_end(Pl, s);
     const m2l::Args a = split_args(Pl);
     prof_begin(Pl, FMM_PHASE_M2L, s);
-    if (Pl->adaptive)
+    if constexpr (m2l_f16_wide(P)) {
+      if (Pl->adaptive)
+        k_m2l_w<P, true><<<m2l::grid_of(a), kWideThreads, 0, s>>>(
+            a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+            lmax, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
+      else
+        k_m2l_w<P, false><<<m2l::grid_of(a), kWideThreads, 0, s>>>(
+            a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+            lmax, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
+    } else if (Pl->adaptive)
       k_m2l_bf<P, 2, true, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
           lmax, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));

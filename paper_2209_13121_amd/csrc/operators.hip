@@ -332,8 +332,9 @@ __global__ void k_f16_fit(int rp, int kp, const float* __restrict__ tbl, float* 
 }
 
 // Pass 4: scaled entries split into 2 FP16 pieces, in the split-M2L operator
-// layout (m2lb_* with np = 2); one thread per (op, row, k step, lane group).
-__global__ void k_f16_split_ops(int p, bool ad, int64_t nitems, const double* __restrict__ scratch,
+// layout (m2lb_* with np = 2) or the wide form's (m2lw_*); one thread per
+// (op, row, k step, lane group).
+__global__ void k_f16_split_ops(int p, bool ad, bool wide, int64_t nitems, const double* __restrict__ scratch,
                                 const float* __restrict__ rowf, const float* __restrict__ colf,
                                 u32x4* __restrict__ ops) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -343,6 +344,7 @@ __global__ void k_f16_split_ops(int p, bool ad, int64_t nitems, const double* __
   const int gq = m2lb_gq(kc, 2), qcs = m2lb_qcs(kc, 2);
   const int g = (int)(t % 4), ks = (int)(t / 4 % kst), row = (int)(t / (4 * kst) % rp);
   const int op = (int)(t / (4 * kst * rp));
+  if (wide && row >= nc) return;  // the wide form stores the ncoef real rows only
   const double* src = scratch + ((size_t)op * rp + row) * kp;
   const double rs = 1.0 / (double)rowf[row];
   uint32_t pc[8][2];
@@ -353,8 +355,9 @@ __global__ void k_f16_split_ops(int p, bool ad, int64_t nitems, const double* __
   }
   u32x4 q[2];
   pack_quads<2>(pc, q);
-  u32x4* o = ops + (size_t)op * m2lb_op_quads(nc, 2, ad) + ((size_t)(ks / kc) * rp + row) * qcs + g * gq +
-             (ks % kc) * 2;
+  u32x4* o = wide ? ops + ((size_t)op * nc + row) * m2lw_row_quads(nc) + (ks * 4 + g) * 2
+                  : ops + (size_t)op * m2lb_op_quads(nc, 2, ad) + ((size_t)(ks / kc) * rp + row) * qcs +
+                        g * gq + (ks % kc) * 2;
   o[0] = q[0];
   o[1] = q[1];
 }
@@ -379,7 +382,7 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
     k_f16_table<<<grid_for(rpp * kp, kBlock), kBlock, 0, s>>>(rpp * kp, scratch, tbl);
     k_f16_fit<<<1, kBlock, 0, s>>>(rpp, kp, tbl, rowf, colf);
     const int64_t items = (int64_t)kNumM2LOps * rpp * m2lb_ksteps(nc) * 4;
-    k_f16_split_ops<<<grid_for(items, kBlock), kBlock, 0, s>>>(P->p, P->adaptive, items, scratch, rowf,
+    k_f16_split_ops<<<grid_for(items, kBlock), kBlock, 0, s>>>(P->p, P->adaptive, m2l_f16_wide(P->p), items, scratch, rowf,
                                                                colf, wsp<u32x4>(P, lay.op_m2lb));
   } else if (P->m2l_np) {
     const int np = P->m2l_np;
