@@ -34,7 +34,7 @@ VARIANTS = {
                      ["paper_2209_13121_amd/csrc/m2l_bf16.hip", "paper_2209_13121_amd/csrc/m2l_common.h",
                       "paper_2209_13121_amd/csrc/bf16_split.h", "paper_2209_13121_amd/csrc/fmm_internal.h"],
                      "bf16", 6),
-    "mixed_f16x2": ("MIXED", "F16X2", "k_m2l_bf<8,2,f16>",
+    "mixed_f16x2": ("MIXED", "F16X2", "k_m2l_w<8>",
                     ["paper_2209_13121_amd/csrc/m2l_bf16.hip", "paper_2209_13121_amd/csrc/m2l_common.h",
                      "paper_2209_13121_amd/csrc/bf16_split.h", "paper_2209_13121_amd/csrc/fmm_internal.h"],
                     "f16", 3),
