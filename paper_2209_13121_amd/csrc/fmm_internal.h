@@ -69,16 +69,66 @@ __host__ __device__ constexpr int m2lb_gq(int kc, int np) { return (kc * np) | 1
 __host__ __device__ constexpr int m2lb_qcs(int kc, int np) { return 4 * m2lb_gq(kc, np) + 2; }
 __host__ __device__ constexpr int m2lb_rows(int nc) { return ((nc + 15) / 16) * 16; }
 // Wide FP16 form (p <= kM2lWidePMax; 32 x 32 x 16 MFMA, a wave per 32
-// targets): an operator is stored [row < ncoef][quad], quad 2 kb + piece
-// holding k = 8 kb .. 8 kb + 7, then one zero quad, so rows are an odd number
-// of quads apart: the 32 rows of a 16-byte LDS read fall on distinct quads
-// modulo 32.  Staged into LDS as one contiguous copy.
+// targets).  Its operators hold only the quads its products read: row block
+// rb (32 rows) takes both FP16 pieces for its first m2lw_cross_steps k steps
+// (16 k values each) and the leading piece alone for the others (the product
+// tiers: h h + h l + l h while the lowest local degree of the block plus the
+// lowest multipole degree of the step is below kF16Tier, h h alone after),
+// and no quad whose 8 k values all lie past ncoef.  A row of block rb holds
+// its quads in k order (quad 4 s + 2 h + piece while s is below the cross
+// steps S, then 4 S + 2 (s - S) + h), padded to an odd count so that the 32
+// rows of a 16-byte LDS read fall on distinct quads modulo 32; the blocks
+// follow each other, and one zero quad ends the operator (read by the lanes
+// whose k half lies past ncoef).  Staged into LDS as one contiguous copy.
 #ifndef M2L_WIDE_PMAX
 #define M2L_WIDE_PMAX 8
 #endif
+#ifndef M2LB_TIER
+#define M2LB_TIER 11
+#endif
 constexpr int kM2lWidePMax = M2L_WIDE_PMAX;
+constexpr int kF16Tier = M2LB_TIER;
 __host__ __device__ constexpr bool m2l_f16_wide(int p) { return p <= kM2lWidePMax; }
-__host__ __device__ constexpr int m2lw_row_quads(int nc) { return 8 * m2lb_ksteps(nc) + 1; }
+__host__ __device__ constexpr int isqrt_c(int v) {
+  int r = 0;
+  while ((r + 1) * (r + 1) <= v) ++r;
+  return r;
+}
+// 32-row block rb and 16-wide k step s take all three piece products
+__host__ __device__ constexpr bool f16_cross_w(int rb, int s) {
+  return isqrt_c(32 * rb) + isqrt_c(16 * s) < kF16Tier;
+}
+__host__ __device__ constexpr int m2lw_ksteps(int nc) { return (nc + 15) / 16; }
+__host__ __device__ constexpr int m2lw_cross_steps(int nc, int rb) {
+  int n = 0;
+  while (n < m2lw_ksteps(nc) && f16_cross_w(rb, n)) ++n;
+  return n;
+}
+// k half (s, h) holds data
+__host__ __device__ constexpr bool m2lw_half_live(int nc, int s, int h) { return 16 * s + 8 * h < nc; }
+// position of (k step s, half h, piece i) in a row of block rb
+__host__ __device__ constexpr int m2lw_pos(int nc, int rb, int s, int h, int i) {
+  return s < m2lw_cross_steps(nc, rb) ? 4 * s + 2 * h + i
+                                      : 4 * m2lw_cross_steps(nc, rb) + 2 * (s - m2lw_cross_steps(nc, rb)) + h;
+}
+__host__ __device__ constexpr int m2lw_row_len(int nc, int rb) {
+  int len = 0;
+  for (int s = 0; s < m2lw_ksteps(nc); ++s)
+    for (int h = 0; h < 2; ++h)
+      if (m2lw_half_live(nc, s, h)) {
+        const int top = m2lw_pos(nc, rb, s, h, s < m2lw_cross_steps(nc, rb) ? 1 : 0) + 1;
+        len = len > top ? len : top;
+      }
+  return len | 1;
+}
+__host__ __device__ constexpr int m2lw_rows_in(int nc, int rb) { return nc - 32 * rb < 32 ? nc - 32 * rb : 32; }
+__host__ __device__ constexpr int m2lw_block_base(int nc, int rb) {
+  int b = 0;
+  for (int r = 0; r < rb; ++r) b += m2lw_rows_in(nc, r) * m2lw_row_len(nc, r);
+  return b;
+}
+// quads of one operator (the last is the zero quad)
+__host__ __device__ constexpr int m2lw_op_quads(int nc) { return m2lw_block_base(nc, (nc + 31) / 32) + 1; }
 __host__ __device__ constexpr int m2lb_kc_fit(int nc, int np, int n, bool ad) {
   return n <= 1 ? 1
                 : (2 * m2lb_rows(nc) * m2lb_qcs(n, np) * 16 <= (ad ? kM2lbLdsBudgetAd : kM2lbLdsBudget)

@@ -206,15 +206,6 @@ __global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, in
 // half-diagonal and |d| >= 2 box sizes, so at most (sqrt(3) / 4)^(n + n');
 // the dropped piece products are 2^-11 of that term: below 1e-7 relative from
 // n + n' = 11 on.
-#ifndef M2LB_TIER
-#define M2LB_TIER 11
-#endif
-constexpr int kF16Tier = M2LB_TIER;
-constexpr int isqrt_c(int v) {
-  int r = 0;
-  while ((r + 1) * (r + 1) <= v) ++r;
-  return r;
-}
 constexpr bool f16_cross(int rb, int ks) { return isqrt_c(16 * rb) + isqrt_c(32 * ks) < kF16Tier; }
 
 // Shape of the kernel for order P and NP pieces.
@@ -481,7 +472,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
 // holds target c of its 32 and the k half h of every 16-wide k step.  Each
 // 16-byte A read from LDS feeds a 32 x 32 block, and the work-group's LDS (two
 // operator buffers and the halo) leaves room for two work-groups per CU.
-//  * Operators: [row][quad] (m2lw_row_quads), copied per offset from global
+//  * Operators: the quads the products read (m2lw_*), copied per offset from global
 //    memory straight into the LDS buffer not being read (global_load_lds, 64
 //    quads per wave instruction), waited for before the offset's barrier.
 //  * Sources: the FP16 pieces of k_split_mult_h (quad (ks * 2 + piece) * 4 +
@@ -507,7 +498,6 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
 constexpr int kWideWaves = 4;
 constexpr int kWideThreads = kWideWaves * 64;
 static_assert(kWideWaves * 32 == m2l::kTargetsPerGroup, "a wide work-group covers one tile");
-constexpr bool f16_cross_w(int rb, int s) { return isqrt_c(32 * rb) + isqrt_c(16 * s) < kF16Tier; }
 
 // Offset orders of the reuse form, per long axis A and class: code = op |
 // (dx + 4) << 9 | (dy + 4) << 13 | (dz + 4) << 17 | move << 21, move = how the
@@ -583,10 +573,9 @@ template <int P>
 struct WShape {
   static constexpr int NC = (P + 1) * (P + 1);
   static constexpr int RB = (NC + 31) / 32;        // 32-row blocks
-  static constexpr int KS = (NC + 15) / 16;        // 16-wide k steps with data
+  static constexpr int KS = m2lw_ksteps(NC);       // 16-wide k steps with data
   static constexpr int QR = m2lb_row_quads(NC, 2);  // quads per source box
-  static constexpr int QW = m2lw_row_quads(NC);     // quads per operator row
-  static constexpr int NQ = NC * QW;               // quads per operator
+  static constexpr int NQ = m2lw_op_quads(NC);     // quads per operator (last: zero)
   static constexpr int NCHUNK = (NQ + 63) / 64;    // 64-quad copies per operator
   static constexpr int NQP = NCHUNK * 64;          // LDS quads per buffer
 };
@@ -620,7 +609,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void k_m2l_w(m2l::Args a, const u3
   typedef WShape<P> S;
   typedef Prod<2> PR;
   typedef float f32x16 __attribute__((ext_vector_type(16)));
-  constexpr int NC = S::NC, RB = S::RB, KS = S::KS, QR = S::QR, QW = S::QW;
+  constexpr int NC = S::NC, RB = S::RB, KS = S::KS, QR = S::QR;
   static_assert(S::NQ <= m2lb_op_quads(S::NC, 2, AD), "the wide operators fit the split-operator array");
   __shared__ u32x4 sT0[S::NQP];
   __shared__ u32x4 sT1[S::NQP];
@@ -702,7 +691,8 @@ __global__ __launch_bounds__(kWideThreads, 2) void k_m2l_w(m2l::Args a, const u3
   auto row_of = [&](m2l::Src src) -> const u32x4* {
     return src.ok ? mlev + (int64_t)src.slot * QR : zero_q;
   };
-  // B quads of a source row for this lane: all k steps, both pieces
+  // B quads of a source row for this lane: all k steps, both pieces (the
+  // quads past ncoef hold zeros)
   auto load_b = [&](const u32x4* ms, u32x4* bh, u32x4* bl) {
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
@@ -733,21 +723,29 @@ __global__ __launch_bounds__(kWideThreads, 2) void k_m2l_w(m2l::Args a, const u3
     return mv == 0 || (mv == 1 && la == 0) || (mv == 2 && la == 3) || (mv == 3 && lb == 0) ||
            (mv == 4 && lb == 3);
   };
-  // this lane's operator rows (rows past ncoef read the last one)
-  int arow[RB];
+  // this lane's operator rows (rows past ncoef read the block's last one),
+  // offset by its k half: + 2 h in the steps with both pieces, + h after
+  int arc[RB], arn[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) {
     const int row = 32 * r + col;
-    arow[r] = (row < NC ? row : NC - 1) * QW + 2 * hk;
+    const int a0 = m2lw_block_base(NC, r) + ((row < NC ? row : NC - 1) - 32 * r) * m2lw_row_len(NC, r);
+    arc[r] = a0 + 2 * hk;
+    arn[r] = a0 + hk;
   }
+  // the lanes whose k half of the last step lies past ncoef read the zero quad
+  const bool dead = !m2lw_half_live(NC, KS - 1, 1) && hk == 1;
   auto compute = [&](const u32x4* buf, const u32x4* bh, const u32x4* bl) {
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
       u32x4 ah[RB], al[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        ah[r] = buf[arow[r] + 4 * s];
-        if (f16_cross_w(r, s)) al[r] = buf[arow[r] + 4 * s + 1];
+        const bool cr = s < m2lw_cross_steps(NC, r);
+        int q0 = (cr ? arc[r] : arn[r]) + m2lw_pos(NC, r, s, 0, 0);
+        if (s == KS - 1 && dead) q0 = S::NQ - 1;
+        ah[r] = buf[q0];
+        if (f16_cross_w(r, s)) al[r] = buf[s == KS - 1 && dead ? S::NQ - 1 : q0 + 1];
       }
 #pragma unroll
       for (int t = 0; t < PR::N; ++t)

@@ -345,6 +345,10 @@ __global__ void k_f16_split_ops(int p, bool ad, bool wide, int64_t nitems, const
   const int g = (int)(t % 4), ks = (int)(t / 4 % kst), row = (int)(t / (4 * kst) % rp);
   const int op = (int)(t / (4 * kst * rp));
   if (wide && row >= nc) return;  // the wide form stores the ncoef real rows only
+  // wide form: this thread's 8 k values are half h of 16-wide step sw; its
+  // row block's products may need the leading piece only, or none
+  const int sw = 2 * ks + g / 2, hw = g % 2, rbw = row / 32;
+  if (wide && !m2lw_half_live(nc, sw, hw)) return;
   const double* src = scratch + ((size_t)op * rp + row) * kp;
   const double rs = 1.0 / (double)rowf[row];
   uint32_t pc[8][2];
@@ -355,9 +359,15 @@ __global__ void k_f16_split_ops(int p, bool ad, bool wide, int64_t nitems, const
   }
   u32x4 q[2];
   pack_quads<2>(pc, q);
-  u32x4* o = wide ? ops + ((size_t)op * nc + row) * m2lw_row_quads(nc) + (ks * 4 + g) * 2
-                  : ops + (size_t)op * m2lb_op_quads(nc, 2, ad) + ((size_t)(ks / kc) * rp + row) * qcs +
-                        g * gq + (ks % kc) * 2;
+  if (wide) {
+    u32x4* o = ops + (size_t)op * m2lw_op_quads(nc) + m2lw_block_base(nc, rbw) +
+               (row - 32 * rbw) * m2lw_row_len(nc, rbw);
+    o[m2lw_pos(nc, rbw, sw, hw, 0)] = q[0];
+    if (sw < m2lw_cross_steps(nc, rbw)) o[m2lw_pos(nc, rbw, sw, hw, 1)] = q[1];
+    return;
+  }
+  u32x4* o = ops + (size_t)op * m2lb_op_quads(nc, 2, ad) + ((size_t)(ks / kc) * rp + row) * qcs + g * gq +
+             (ks % kc) * 2;
   o[0] = q[0];
   o[1] = q[1];
 }
