@@ -63,8 +63,9 @@ using m2l::kThreads;
 #define M2LB_OP2 1
 #endif
 constexpr int kFlush = M2LB_FLUSH;
-// s_waitcnt operand: vmcnt(0), expcnt and lgkmcnt not waited for
-constexpr int kVmcntZero = 0x0F70;
+// s_waitcnt operand: vmcnt(n) (n < 64), expcnt and lgkmcnt not waited for
+constexpr int vmcnt_op(int n) { return 0x0F70 | (n & 15) | ((n >> 4) << 14); }
+constexpr int kVmcntZero = vmcnt_op(0);
 // FP16 form: offsets per FP32 partial sum.
 constexpr int kGroupF16 = 8;
 
@@ -569,6 +570,9 @@ constexpr bool chain_order_ok(const ChainOrder& t) {
 static_assert(chain_order_ok(make_chain_order()), "offset orders of the reuse form");
 static __constant__ ChainOrder kChainOrder = make_chain_order();
 
+#ifndef M2LW_VMB
+#define M2LW_VMB 1
+#endif
 template <int P>
 struct WShape {
   static constexpr int NC = (P + 1) * (P + 1);
@@ -778,10 +782,13 @@ __global__ __launch_bounds__(kWideThreads, 2) void k_m2l_w(m2l::Args a, const u3
                        u32x4* bln) -> bool {
     const bool more = i + 1 < i1;
     const m2l::Src far_src = lookup_at(i + 2);
+    // this offset's source quads (loaded during the previous one) first: the
+    // copy and the loads issued below then need no wait until the barrier
+    __builtin_amdgcn_s_waitcnt(kVmcntZero);
     if (more) {
-      stage(offset_at(i + 1, ndx, ndy, ndz), bufn);
       const int mv = move_at(i + 1);
       if (mv != 0) shift_b(mv, bhc, blc, bhn, bln);
+      stage(offset_at(i + 1, ndx, ndy, ndz), bufn);
       if (face(mv)) load_b(row_of(next_src), bhn, bln);
     }
     if (__any(cur_src.ok)) compute(bufc, bhc, blc);
@@ -794,8 +801,15 @@ __global__ __launch_bounds__(kWideThreads, 2) void k_m2l_w(m2l::Args a, const u3
       }
     }
     if (!more) return false;
-    __builtin_amdgcn_s_waitcnt(kVmcntZero);  // this wave's part of the copy has landed
-    __syncthreads();
+    // this wave's part of the copy has landed (the next offset's source
+    // loads, issued after it, may still be in flight), and every LDS read of
+    // this offset has returned (each fed a product); then the work-group's
+    // barrier, without the memory fence of __syncthreads (which would wait
+    // for the source loads too)
+    __builtin_amdgcn_s_waitcnt(vmcnt_op(M2LW_VMB ? 2 * KS : 0));
+    __asm__ volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    __asm__ volatile("" ::: "memory");
     ++i;
     cur_src = next_src;
     next_src = far_src;
