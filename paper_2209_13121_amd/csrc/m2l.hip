@@ -307,7 +307,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l(m2l::Args a, const T* __restri
       }
       if (last_chunk && !more) return false;
       stage_store(sT[cur ^ 1], reg);
-      __syncthreads();
+      m2l::lds_barrier();
       cur ^= 1;
     }
     ++i;

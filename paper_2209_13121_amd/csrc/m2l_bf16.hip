@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kThreads) void k_m2l_bf(m2l::Args a, const u32x4* _
       }
       if (last_chunk && !more) return false;
       stage_store(sT[cur ^ 1], S::OP2 ? rin : reg);
-      __syncthreads();
+      m2l::lds_barrier();
       cur ^= 1;
     }
     ++i;

@@ -46,6 +46,17 @@ constexpr ILTable make_il_table() {
 }
 static __constant__ ILTable kILTable = make_il_table();
 
+// Work-group barrier of the double-buffered operator staging: this wave's
+// LDS reads and writes have completed (lgkmcnt(0)), then s_barrier.  Unlike
+// __syncthreads it does not wait for outstanding global loads (the next
+// offset's source prefetch stays in flight across it).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited for
+  __asm__ volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
+}
+
 // Offset i of class pi and its operator number.
 __device__ __forceinline__ int il_offset(int pi, int i, int& dx, int& dy, int& dz) {
   const uint32_t c = kILTable.v[pi][i];
