@@ -334,7 +334,23 @@ __global__ void k_f16_fit(int rp, int kp, const float* __restrict__ tbl, float* 
 // Pass 4: scaled entries split into 2 FP16 pieces, in the split-M2L operator
 // layout (m2lb_* with np = 2) or the wide form's (m2lw_*); one thread per
 // (op, row, k step, lane group).
-__global__ void k_f16_split_ops(int p, bool ad, bool wide, int64_t nitems, const double* __restrict__ scratch,
+// The wide form's operator layout for one p (row blocks of 32), from the
+// m2lw_* rules on the host.
+struct WideOps {
+  int base[4], len[4], cross[4], quads;
+};
+inline WideOps wide_ops(int nc) {
+  WideOps w{};
+  for (int rb = 0; rb < 4; ++rb) {
+    w.base[rb] = m2lw_block_base(nc, rb < (nc + 31) / 32 ? rb : 0);
+    w.len[rb] = m2lw_row_len(nc, rb);
+    w.cross[rb] = m2lw_cross_steps(nc, rb);
+  }
+  w.quads = m2lw_op_quads(nc);
+  return w;
+}
+
+__global__ void k_f16_split_ops(int p, bool ad, bool wide, WideOps wl, int64_t nitems, const double* __restrict__ scratch,
                                 const float* __restrict__ rowf, const float* __restrict__ colf,
                                 u32x4* __restrict__ ops) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -360,10 +376,15 @@ __global__ void k_f16_split_ops(int p, bool ad, bool wide, int64_t nitems, const
   u32x4 q[2];
   pack_quads<2>(pc, q);
   if (wide) {
-    u32x4* o = ops + (size_t)op * m2lw_op_quads(nc) + m2lw_block_base(nc, rbw) +
-               (row - 32 * rbw) * m2lw_row_len(nc, rbw);
-    o[m2lw_pos(nc, rbw, sw, hw, 0)] = q[0];
-    if (sw < m2lw_cross_steps(nc, rbw)) o[m2lw_pos(nc, rbw, sw, hw, 1)] = q[1];
+    // m2lw_pos with the row block's values from the host
+    const int cs = wl.cross[rbw];
+    u32x4* o = ops + (size_t)op * wl.quads + wl.base[rbw] + (row - 32 * rbw) * wl.len[rbw];
+    if (sw < cs) {
+      o[4 * sw + 2 * hw] = q[0];
+      o[4 * sw + 2 * hw + 1] = q[1];
+    } else {
+      o[4 * cs + 2 * (sw - cs) + hw] = q[0];
+    }
     return;
   }
   u32x4* o = ops + (size_t)op * m2lb_op_quads(nc, 2, ad) + ((size_t)(ks / kc) * rp + row) * qcs + g * gq +
@@ -383,7 +404,8 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
   if (P->m2l_f16) {
     const int nc = P->nc, rpp = m2lb_rows(nc), kp = 32 * m2lb_ksteps(nc);
     const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(nc, 2, P->adaptive) * 4;
-    fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads
+    hipError_t e = fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads
+    if (e != hipSuccess) return e;
     double* scratch = wsp<double>(P, lay.op_m2l_scratch);
     float* tbl = wsp<float>(P, lay.f16_tbl);
     float* rowf = wsp<float>(P, lay.f16_rowf);
@@ -392,12 +414,14 @@ hipError_t launch_operators(fmm_plan_s* P, hipStream_t s) {
     k_f16_table<<<grid_for(rpp * kp, kBlock), kBlock, 0, s>>>(rpp * kp, scratch, tbl);
     k_f16_fit<<<1, kBlock, 0, s>>>(rpp, kp, tbl, rowf, colf);
     const int64_t items = (int64_t)kNumM2LOps * rpp * m2lb_ksteps(nc) * 4;
-    k_f16_split_ops<<<grid_for(items, kBlock), kBlock, 0, s>>>(P->p, P->adaptive, m2l_f16_wide(P->p), items, scratch, rowf,
+    k_f16_split_ops<<<grid_for(items, kBlock), kBlock, 0, s>>>(P->p, P->adaptive, m2l_f16_wide(P->p),
+                                                               wide_ops(nc), items, scratch, rowf,
                                                                colf, wsp<u32x4>(P, lay.op_m2lb));
   } else if (P->m2l_np) {
     const int np = P->m2l_np;
     const int64_t words = (int64_t)kNumM2LOps * m2lb_op_quads(P->nc, np, P->adaptive) * 4;
-    fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads
+    hipError_t e = fill_u32(wsp<uint32_t>(P, lay.op_m2lb), words, 0u, s);  // pad quads
+    if (e != hipSuccess) return e;
     u32x4* ob = wsp<u32x4>(P, lay.op_m2lb);
     if (np == 2)
       k_gen_m2l_bf<2><<<kNumM2LOps, kBlock, 0, s>>>(P->p, P->adaptive, ob);

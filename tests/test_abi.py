@@ -159,6 +159,26 @@ def test_hilbert_prefix_is_the_ancestor_box(lib, bits):
         assert sorted(slots.values()) == list(range(8**level))
 
 
+@pytest.mark.parametrize("bits", [3, 4, 5])
+def test_hilbert_aligned_blocks_are_boxes(lib, bits):
+    """The M2L tiles rest on this: every aligned run of 128 consecutive
+    Hilbert slots is an 8 x 4 x 4 box (in some axis order), so the parents of a
+    full tile fill the bounding box of its targets (the source-reuse layout
+    assigns them to lanes by position in that box), and its sources lie in a
+    20 x 12 x 12 halo; runs of 32 are 4 x 4 x 2 boxes."""
+    nb = 1 << bits
+    coords = np.zeros((nb**3, 3), dtype=int)
+    for x in range(nb):
+        for y in range(nb):
+            for z in range(nb):
+                coords[B.fmm_hilbert_index(x, y, z, bits)] = (x, y, z)
+    for run, shape in ((32, (2, 4, 4)), (128, (4, 4, 8))):
+        for s0 in range(0, nb**3, run):
+            c = coords[s0:s0 + run]
+            ext = tuple(sorted((c.max(0) - c.min(0) + 1).tolist()))
+            assert ext == shape and len({tuple(v) for v in c}) == run
+
+
 def test_hilbert_rejects_out_of_range(lib):
     assert B.fmm_hilbert_index(8, 0, 0, 3) == 0
     assert B.fmm_hilbert_index(0, 0, 0, -1) == 0
