@@ -173,9 +173,14 @@ fmm_status fmm_replan(fmm_plan_t *plan, const double *d_pos, fmm_stream_t stream
  *     last work-groups of each XCD run as four parts over the offsets, added in
  *     part order afterwards (a shorter last round; the summation order of those
  *     tiles changes, within rounding).
+ *   FMM_SCHED_M2L_PERSISTENT: 0 (default) one work-group per M2L tile; 1 (the
+ *     scaled FP16 form at p <= 8 with an M2L pass, else FMM_E_UNSUPPORTED) a
+ *     persistent launch of two work-groups per CU, those of each XCD taking
+ *     the XCD's tiles in order from a counter; no tile is split, so results
+ *     equal bitwise those of FMM_SCHED_M2L_SPLIT 0 (which it overrides).
  * Kept by fmm_replan.  Errors: FMM_E_INVALID_ARG (plan NULL, unknown key or
  * value out of range), FMM_E_UNSUPPORTED. */
-enum { FMM_SCHED_P2P_PERSISTENT = 0, FMM_SCHED_M2L_SPLIT = 1 };
+enum { FMM_SCHED_P2P_PERSISTENT = 0, FMM_SCHED_M2L_SPLIT = 1, FMM_SCHED_M2L_PERSISTENT = 2 };
 fmm_status fmm_plan_set_schedule(fmm_plan_t *plan, int key, int value);
 
 /* Evaluate the FMM for charges d_q (device, n FP64, user order).  Any of

@@ -7,8 +7,9 @@ For a given charge set and tree family it searches
   * the M2L form (scaled split FP16, split BF16, FP32);
   * the schedule of the passes (``fmm_plan_set_schedule``): the adaptive P2P
     as one wave per box or as a persistent launch over a cost-ordered
-    work-list, and how many tail work-groups per XCD the split M2L forms run
-    in four parts.
+    work-list; how many tail work-groups per XCD the split M2L forms run in
+    four parts, or (the FP16 form at p <= 8) the M2L as a persistent launch
+    over per-XCD tile counters.
 Every candidate is measured on the GPU through the C ABI, the way the
 benchmark runs a step: one plan, then fmm_replan + fmm_evaluate timed with HIP
 events on the launch stream (median of ``reps``).  The gate is the library's:
@@ -19,7 +20,6 @@ against an independent reference on sampled systems) through ``reference``.
 ``select`` holds the decision rule alone (no GPU), so it can be tested on the
 host.
 """
-import itertools
 from dataclasses import dataclass, field
 
 from . import binding as B
@@ -28,7 +28,9 @@ KINDS = ("F16X2", "BF16X3", "F32")
 SPLIT_KINDS = ("F16X2", "BF16X3", "BF16X2")
 # schedule values searched (key -> values); the first value is the default
 SCHEDULES = {"p2p_persistent": (0, 1), "m2l_split": (16, 8, 0)}
-_SCHED_KEY = {"p2p_persistent": B.FMM_SCHED_P2P_PERSISTENT, "m2l_split": B.FMM_SCHED_M2L_SPLIT}
+_SCHED_KEY = {"p2p_persistent": B.FMM_SCHED_P2P_PERSISTENT, "m2l_split": B.FMM_SCHED_M2L_SPLIT,
+              "m2l_persistent": B.FMM_SCHED_M2L_PERSISTENT}
+WIDE_PMAX = 8  # the FP16 form's persistent M2L runs up to this order
 
 
 @dataclass
@@ -56,16 +58,15 @@ def select(results, gate_e=1e-6, gate_f=1e-5):
     return best
 
 
-def schedules_for(tree, kind):
-    """The schedule candidates that apply to a tree and an M2L form."""
-    keys = []
-    if tree.get("leaf_max", 0) > 0:
-        keys.append("p2p_persistent")
-    if kind in SPLIT_KINDS:
-        keys.append("m2l_split")
-    if not keys:
-        return [{}]
-    return [dict(zip(keys, vals)) for vals in itertools.product(*(SCHEDULES[k] for k in keys))]
+def schedules_for(tree, kind, p=None):
+    """The schedule candidates that apply to a tree, an M2L form and order p:
+    the adaptive tree's two P2P forms, times the split forms' tail splits and,
+    for the FP16 form at p <= WIDE_PMAX, the persistent M2L."""
+    p2p = [{"p2p_persistent": v} for v in SCHEDULES["p2p_persistent"]] if tree.get("leaf_max", 0) > 0 else [{}]
+    m2l = [{"m2l_split": v} for v in SCHEDULES["m2l_split"]] if kind in SPLIT_KINDS else [{}]
+    if kind == "F16X2" and p is not None and p <= WIDE_PMAX:
+        m2l.append({"m2l_persistent": 1})
+    return [dict(**a, **b) for a in p2p for b in m2l]
 
 
 def apply_schedule(plan, schedule):
@@ -121,7 +122,7 @@ def tune(pos, q, p, trees, kinds=KINDS, lo=(0.0, 0.0, 0.0), side=1.0, batch_leve
             cfg = B.make_config(p=p, precision=B.FMM_PREC_MIXED, m2l_kind=getattr(B, "FMM_M2L_" + kind),
                                 lo=lo, side=side, batch_level=batch_level, **tree)
             ws = torch.empty(B.fmm_workspace_size(cfg, n), dtype=torch.uint8, device=pos.device)
-            for sched in (schedules_for(tree, kind) if search_schedules else [{}]):
+            for sched in (schedules_for(tree, kind, p) if search_schedules else [{}]):
                 ms, phi, f, e = _time(torch, cfg, n, pos, q, ws, stream, reps, sched)
                 r = Result(tree=dict(tree), kind=kind, ms=ms, energy_err=abs(e - e64) / abs(e64),
                            force_err=float(torch.linalg.vector_norm(f - f64) / fnorm),

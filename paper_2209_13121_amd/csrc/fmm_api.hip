@@ -121,6 +121,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
       lay->multb = take(16 * NB * rq);
       lay->op_m2lb = take(16 * (size_t)kNumM2LOps * m2lb_op_quads(nc, np, adaptive));
       lay->m2l_half = take(sizeof(float) * 8 * kM2lSplitPerXcd * (kM2lParts - 1) * 128 * (size_t)nc);
+      lay->m2l_ctl = take(sizeof(uint32_t) * 8);
     }
     if (m2l_is_f16(cfg)) {
       const size_t rp = (size_t)m2lb_rows(nc), kp = (size_t)32 * m2lb_ksteps(nc);
@@ -237,9 +238,11 @@ fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, in
   const bool is_static = keep_operators && P->is_static;
   const int p2p_persistent = keep_operators ? P->p2p_persistent : 0;
   const int m2l_split = keep_operators ? P->m2l_split : kM2lSplitPerXcd;
+  const int m2l_persistent = keep_operators ? P->m2l_persistent : 0;
   memset(P, 0, sizeof(*P));
   P->p2p_persistent = p2p_persistent;
   P->m2l_split = m2l_split;
+  P->m2l_persistent = m2l_persistent;
   P->ops_ready = ops_ready;
   P->profile_mask = mask;
   P->nevents_created = nevents;
@@ -355,6 +358,11 @@ fmm_status fmm_plan_set_schedule(fmm_plan_t* P, int key, int value) {
     case FMM_SCHED_M2L_SPLIT:
       if (value < 0 || value > kM2lSplitPerXcd) return FMM_E_INVALID_ARG;
       P->m2l_split = value;
+      return FMM_OK;
+    case FMM_SCHED_M2L_PERSISTENT:
+      if (value != 0 && value != 1) return FMM_E_INVALID_ARG;
+      if (value && !(P->m2l_f16 && m2l_f16_wide(P->p) && P->L >= 2)) return FMM_E_UNSUPPORTED;
+      P->m2l_persistent = value;
       return FMM_OK;
   }
   return FMM_E_INVALID_ARG;

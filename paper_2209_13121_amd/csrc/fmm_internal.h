@@ -172,6 +172,7 @@ struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t multb;            // split M2L: multipoles as BF16 / FP16 pieces, all boxes
   size_t op_m2lb;          // split M2L: operators as BF16 / FP16 pieces
   size_t m2l_half;         // split M2L: parts 1.. of the split tail groups
+  size_t m2l_ctl;          // persistent M2L: per-XCD tile counters (8)
   size_t f16_lmax;         // FP16 M2L: per level, max |M_k colf_k| (float bits; the level's scale)
   size_t f16_rowf;         // FP16 M2L: per operator row, the inverse row scale
   size_t f16_colf;         // FP16 M2L: per k, the inverse column scale (applied to multipoles)
@@ -248,6 +249,7 @@ struct fmm_plan_s {
   // schedule (fmm_plan_set_schedule): work distribution only
   int p2p_persistent;  // adaptive P2P as a persistent kernel over the work-list
   int m2l_split;       // split-M2L tail work-groups per XCD (0 .. kM2lSplitPerXcd)
+  int m2l_persistent;  // wide FP16 M2L as a persistent launch over per-XCD tile counters
 };
 
 namespace fmm {

@@ -602,234 +602,267 @@ __device__ __forceinline__ void dpp_rows(const u32x4* bh, const u32x4* bl, u32x4
   }
 }
 
-template <int P, bool AD>
+// One tile of the wide form: logical group lg (part pt, split index si),
+// or, with lg < 0, the group the work-group's hardware index names
+// (m2l::decode_group).  Uniform over the work-group; contains barriers.
+// One tile of the wide form per call of `tile`: logical group lg (whole),
+// or, with lg < 0, the group the work-group's hardware index names
+// (m2l::decode_group, split parts included).  Plain launch (PERSIST false):
+// one tile per work-group.  Persistent form (FMM_SCHED_M2L_PERSISTENT):
+// two resident work-groups per CU; those of XCD x (hardware index % 8) take
+// the XCD's contiguous range of logical groups in order from counter
+// ticket[x], one whole tile at a time (a.ksplit = 0), so each tile is summed
+// as in the unsplit form; a work-group leaves when its XCD's range is spent.
+template <int P, bool AD, bool PERSIST>
 __global__ __launch_bounds__(kWideThreads, 2) void k_m2l_w(m2l::Args a, const u32x4* __restrict__ multq,
                                                          const u32x4* __restrict__ zero_q,
                                                          const u32x4* __restrict__ ops,
                                                          float* __restrict__ out,
                                                          const uint32_t* __restrict__ lmax,
                                                          const float* __restrict__ rowf,
-                                                         float* __restrict__ half_out) {
+                                                         float* __restrict__ half_out,
+                                                         uint32_t* __restrict__ ticket) {
   typedef WShape<P> S;
-  typedef Prod<2> PR;
-  typedef float f32x16 __attribute__((ext_vector_type(16)));
-  constexpr int NC = S::NC, RB = S::RB, KS = S::KS, QR = S::QR;
-  static_assert(S::NQ <= m2lb_op_quads(S::NC, 2, AD), "the wide operators fit the split-operator array");
   __shared__ u32x4 sT0[S::NQP];
   __shared__ u32x4 sT1[S::NQP];
   __shared__ uint32_t sSlot[AD ? 1 : m2l::kHalo];
   __shared__ int sBox[6];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int col = lane & 31, hk = lane >> 5;
-  m2l::TileT<AD, true> tl;
-  if (!tl.setup(a, wave * 32 + col, sSlot, sBox)) return;  // uniform over the work-group
-  const int pi = tl.pi;
-  const bool whole = tl.part < 0;
-  const int i0 = whole ? 0 : tl.part * kIL / kM2lParts;
-  const int i1 = whole ? kIL : (tl.part + 1) * kIL / kM2lParts;
-  const u32x4* mlev = multq + tl.lvl_off * QR;
+  const int64_t pt = -1, si = 0;
+  auto tile = [&](int64_t lg) {
+    typedef Prod<2> PR;
+    typedef float f32x16 __attribute__((ext_vector_type(16)));
+    constexpr int NC = S::NC, RB = S::RB, KS = S::KS, QR = S::QR;
+    static_assert(S::NQ <= m2lb_op_quads(S::NC, 2, AD), "the wide operators fit the split-operator array");
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int col = lane & 31, hk = lane >> 5;
+    m2l::TileT<AD, true> tl;
+    if (lg < 0 ? !tl.setup(a, wave * 32 + col, sSlot, sBox)
+               : !tl.setup_at(a, lg, pt, si, wave * 32 + col, sSlot, sBox))
+      return;  // uniform over the work-group
+    const int pi = tl.pi;
+    const bool whole = tl.part < 0;
+    const int i0 = whole ? 0 : tl.part * kIL / kM2lParts;
+    const int i1 = whole ? kIL : (tl.part + 1) * kIL / kM2lParts;
+    const u32x4* mlev = multq + tl.lvl_off * QR;
 
-  // Source reuse: a whole tile of the uniform tree whose parents form an
-  // 8 x 4 x 4 block (sBox holds 2 pmin - 2 and 2 pmax + 3 per axis).
-  bool chain = false;
-  int ax = 0;
-  if constexpr (!AD) {
-    int ext[3], lo[3], n8 = 0, n4 = 0;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      lo[k] = (sBox[k] + 2) / 2;
-      ext[k] = (sBox[3 + k] - 3) / 2 - lo[k] + 1;
-      n8 += ext[k] == 8;
-      n4 += ext[k] == 4;
-      if (ext[k] == 8) ax = k;
-    }
-    chain = __syncthreads_and(whole && n8 == 1 && n4 == 2 && tl.col_ok);  // a full tile
-    if (chain) {
-      // lane c = a + 4 b + 16 c': parent lo + (4 (w & 1) + a) e_A + b e_B + (2 (w >> 1) + c') e_C
-      const int B = chain_other(ax, 0);
-      const int ua = 4 * (wave & 1) + (col & 3), ub = (col >> 2) & 3, uc = 2 * (wave >> 1) + (col >> 4);
-      int pc[3];
-#pragma unroll
-      for (int k = 0; k < 3; ++k) pc[k] = lo[k] + (k == ax ? ua : (k == B ? ub : uc));
-      tl.tx = 2 * pc[0] + ((pi >> 2) & 1);
-      tl.ty = 2 * pc[1] + ((pi >> 1) & 1);
-      tl.tz = 2 * pc[2] + (pi & 1);
-      tl.col_ok = true;
-    }
-  }
-  const uint32_t* ord = kChainOrder.v[ax][pi];
-  // offset k of this work-group's order: its operator and (dx, dy, dz)
-  auto offset_at = [&](int k, int& dx, int& dy, int& dz) -> int {
-    if constexpr (AD) return m2l::il_offset(pi, k, dx, dy, dz);  // the source table's order
-    const uint32_t c = ord[k];
-    dx = (int)((c >> 9) & 15u) - 4;
-    dy = (int)((c >> 13) & 15u) - 4;
-    dz = (int)((c >> 17) & 15u) - 4;
-    return (int)(c & 511u);
-  };
-  auto move_at = [&](int k) -> int { return chain ? (int)((ord[k] >> 21) & 7u) : 0; };
-
-  f32x16 sum[RB], acc[RB];
-#pragma unroll
-  for (int r = 0; r < RB; ++r)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) sum[r][e] = acc[r][e] = 0.f;
-
-  // operator op into buf: wave w copies the 64-quad chunks w, w + 4, ...
-  // (reads past the operator's end are clamped to its last quad; they land
-  // in the buffer's padding)
-  auto stage = [&](int op, u32x4* buf) {
-    const u32x4* base = ops + (size_t)op * S::NQ;
-#pragma unroll
-    for (int j = 0; j < (S::NCHUNK + kWideWaves - 1) / kWideWaves; ++j) {
-      const int e0 = (j * kWideWaves + wave) * 64;
-      if (e0 < S::NQP) {
-        const int e = e0 + lane;
-        __builtin_amdgcn_global_load_lds(
-            (__attribute__((address_space(1))) void*)(base + (e < S::NQ ? e : S::NQ - 1)),
-            (__attribute__((address_space(3))) void*)(buf + e0), 16, 0, 0);
+    // Source reuse: a whole tile of the uniform tree whose parents form an
+    // 8 x 4 x 4 block (sBox holds 2 pmin - 2 and 2 pmax + 3 per axis).
+    bool chain = false;
+    int ax = 0;
+    if constexpr (!AD) {
+      int ext[3], lo[3], n8 = 0, n4 = 0;
+  #pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = (sBox[k] + 2) / 2;
+        ext[k] = (sBox[3 + k] - 3) / 2 - lo[k] + 1;
+        n8 += ext[k] == 8;
+        n4 += ext[k] == 4;
+        if (ext[k] == 8) ax = k;
+      }
+      chain = __syncthreads_and(whole && n8 == 1 && n4 == 2 && tl.col_ok);  // a full tile
+      if (chain) {
+        // lane c = a + 4 b + 16 c': parent lo + (4 (w & 1) + a) e_A + b e_B + (2 (w >> 1) + c') e_C
+        const int B = chain_other(ax, 0);
+        const int ua = 4 * (wave & 1) + (col & 3), ub = (col >> 2) & 3, uc = 2 * (wave >> 1) + (col >> 4);
+        int pc[3];
+  #pragma unroll
+        for (int k = 0; k < 3; ++k) pc[k] = lo[k] + (k == ax ? ua : (k == B ? ub : uc));
+        tl.tx = 2 * pc[0] + ((pi >> 2) & 1);
+        tl.ty = 2 * pc[1] + ((pi >> 1) & 1);
+        tl.tz = 2 * pc[2] + (pi & 1);
+        tl.col_ok = true;
       }
     }
-  };
-  auto row_of = [&](m2l::Src src) -> const u32x4* {
-    return src.ok ? mlev + (int64_t)src.slot * QR : zero_q;
-  };
-  // B quads of a source row for this lane: all k steps, both pieces (the
-  // quads past ncoef hold zeros)
-  auto load_b = [&](const u32x4* ms, u32x4* bh, u32x4* bl) {
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      bh[s] = ms[((s >> 1) * 2 + 0) * 4 + 2 * (s & 1) + hk];
-      bl[s] = ms[((s >> 1) * 2 + 1) * 4 + 2 * (s & 1) + hk];
-    }
-  };
-  // B of the next offset from this one's by a row shift
-  auto shift_b = [&](int mv, const u32x4* bh, const u32x4* bl, u32x4* nh, u32x4* nl) {
-    switch (mv) {
-      case 1:  // from lane a - 1 (row_shr:1)
-        dpp_rows<0x111, KS>(bh, bl, nh, nl);
-        break;
-      case 2:  // from lane a + 1 (row_shl:1)
-        dpp_rows<0x101, KS>(bh, bl, nh, nl);
-        break;
-      case 3:  // from lane b - 1 (row_shr:4)
-        dpp_rows<0x114, KS>(bh, bl, nh, nl);
-        break;
-      default:  // from lane b + 1 (row_shl:4)
-        dpp_rows<0x104, KS>(bh, bl, nh, nl);
-        break;
-    }
-  };
-  // lanes with no neighbour for move mv (they load)
-  const int la = col & 3, lb = (col >> 2) & 3;
-  auto face = [&](int mv) -> bool {
-    return mv == 0 || (mv == 1 && la == 0) || (mv == 2 && la == 3) || (mv == 3 && lb == 0) ||
-           (mv == 4 && lb == 3);
-  };
-  // this lane's operator rows (rows past ncoef read the block's last one),
-  // offset by its k half: + 2 h in the steps with both pieces, + h after
-  int arc[RB], arn[RB];
-#pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    const int row = 32 * r + col;
-    const int a0 = m2lw_block_base(NC, r) + ((row < NC ? row : NC - 1) - 32 * r) * m2lw_row_len(NC, r);
-    arc[r] = a0 + 2 * hk;
-    arn[r] = a0 + hk;
-  }
-  // the lanes whose k half of the last step lies past ncoef read the zero quad
-  const bool dead = !m2lw_half_live(NC, KS - 1, 1) && hk == 1;
-  auto compute = [&](const u32x4* buf, const u32x4* bh, const u32x4* bl) {
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      u32x4 ah[RB], al[RB];
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const bool cr = s < m2lw_cross_steps(NC, r);
-        int q0 = (cr ? arc[r] : arn[r]) + m2lw_pos(NC, r, s, 0, 0);
-        if (s == KS - 1 && dead) q0 = S::NQ - 1;
-        ah[r] = buf[q0];
-        if (f16_cross_w(r, s)) al[r] = buf[s == KS - 1 && dead ? S::NQ - 1 : q0 + 1];
-      }
-#pragma unroll
-      for (int t = 0; t < PR::N; ++t)
-#pragma unroll
-        for (int r = 0; r < RB; ++r)
-          if (t == PR::N - 1 || f16_cross_w(r, s))
-            acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                __builtin_bit_cast(f16x8, PR::a[t] ? al[r] : ah[r]),
-                __builtin_bit_cast(f16x8, PR::b[t] ? bl[s] : bh[s]), acc[r], 0, 0, 0);
-    }
-  };
+    const uint32_t* ord = kChainOrder.v[ax][pi];
+    // offset k of this work-group's order: its operator and (dx, dy, dz)
+    auto offset_at = [&](int k, int& dx, int& dy, int& dz) -> int {
+      if constexpr (AD) return m2l::il_offset(pi, k, dx, dy, dz);  // the source table's order
+      const uint32_t c = ord[k];
+      dx = (int)((c >> 9) & 15u) - 4;
+      dy = (int)((c >> 13) & 15u) - 4;
+      dz = (int)((c >> 17) & 15u) - 4;
+      return (int)(c & 511u);
+    };
+    auto move_at = [&](int k) -> int { return chain ? (int)((ord[k] >> 21) & 7u) : 0; };
 
-  u32x4 bh0[KS], bl0[KS], bh1[KS], bl1[KS];
-  int i = i0, ndx, ndy, ndz;
-  auto lookup_at = [&](int k) -> m2l::Src {
-    int ldx, ldy, ldz;
-    const int kk = k < i1 ? k : i1 - 1;
-    offset_at(kk, ldx, ldy, ldz);
-    return tl.lookup(sSlot, kk, ldx, ldy, ldz);
-  };
-  m2l::Src cur_src = lookup_at(i0), next_src = lookup_at(i0 + 1);
-  load_b(row_of(cur_src), bh0, bl0);
-  stage(offset_at(i0, ndx, ndy, ndz), sT0);
-  __builtin_amdgcn_s_waitcnt(kVmcntZero);
-  __syncthreads();
-  // offset i: its operator in bufc, its B in (bhc, blc); the next offset's B
-  // goes to (bhn, bln) (shifted from this one's and completed by the face
-  // lanes' loads, or loaded by every lane) and its operator to bufn.
-  auto do_offset = [&](const u32x4* bufc, u32x4* bufn, u32x4* bhc, u32x4* blc, u32x4* bhn,
-                       u32x4* bln) -> bool {
-    const bool more = i + 1 < i1;
-    const m2l::Src far_src = lookup_at(i + 2);
-    // this offset's source quads (loaded during the previous one) first: the
-    // copy and the loads issued below then need no wait until the barrier
+    f32x16 sum[RB], acc[RB];
+  #pragma unroll
+    for (int r = 0; r < RB; ++r)
+  #pragma unroll
+      for (int e = 0; e < 16; ++e) sum[r][e] = acc[r][e] = 0.f;
+
+    // operator op into buf: wave w copies the 64-quad chunks w, w + 4, ...
+    // (reads past the operator's end are clamped to its last quad; they land
+    // in the buffer's padding)
+    auto stage = [&](int op, u32x4* buf) {
+      const u32x4* base = ops + (size_t)op * S::NQ;
+  #pragma unroll
+      for (int j = 0; j < (S::NCHUNK + kWideWaves - 1) / kWideWaves; ++j) {
+        const int e0 = (j * kWideWaves + wave) * 64;
+        if (e0 < S::NQP) {
+          const int e = e0 + lane;
+          __builtin_amdgcn_global_load_lds(
+              (__attribute__((address_space(1))) void*)(base + (e < S::NQ ? e : S::NQ - 1)),
+              (__attribute__((address_space(3))) void*)(buf + e0), 16, 0, 0);
+        }
+      }
+    };
+    auto row_of = [&](m2l::Src src) -> const u32x4* {
+      return src.ok ? mlev + (int64_t)src.slot * QR : zero_q;
+    };
+    // B quads of a source row for this lane: all k steps, both pieces (the
+    // quads past ncoef hold zeros)
+    auto load_b = [&](const u32x4* ms, u32x4* bh, u32x4* bl) {
+  #pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        bh[s] = ms[((s >> 1) * 2 + 0) * 4 + 2 * (s & 1) + hk];
+        bl[s] = ms[((s >> 1) * 2 + 1) * 4 + 2 * (s & 1) + hk];
+      }
+    };
+    // B of the next offset from this one's by a row shift
+    auto shift_b = [&](int mv, const u32x4* bh, const u32x4* bl, u32x4* nh, u32x4* nl) {
+      switch (mv) {
+        case 1:  // from lane a - 1 (row_shr:1)
+          dpp_rows<0x111, KS>(bh, bl, nh, nl);
+          break;
+        case 2:  // from lane a + 1 (row_shl:1)
+          dpp_rows<0x101, KS>(bh, bl, nh, nl);
+          break;
+        case 3:  // from lane b - 1 (row_shr:4)
+          dpp_rows<0x114, KS>(bh, bl, nh, nl);
+          break;
+        default:  // from lane b + 1 (row_shl:4)
+          dpp_rows<0x104, KS>(bh, bl, nh, nl);
+          break;
+      }
+    };
+    // lanes with no neighbour for move mv (they load)
+    const int la = col & 3, lb = (col >> 2) & 3;
+    auto face = [&](int mv) -> bool {
+      return mv == 0 || (mv == 1 && la == 0) || (mv == 2 && la == 3) || (mv == 3 && lb == 0) ||
+             (mv == 4 && lb == 3);
+    };
+    // this lane's operator rows (rows past ncoef read the block's last one),
+    // offset by its k half: + 2 h in the steps with both pieces, + h after
+    int arc[RB], arn[RB];
+  #pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int row = 32 * r + col;
+      const int a0 = m2lw_block_base(NC, r) + ((row < NC ? row : NC - 1) - 32 * r) * m2lw_row_len(NC, r);
+      arc[r] = a0 + 2 * hk;
+      arn[r] = a0 + hk;
+    }
+    // the lanes whose k half of the last step lies past ncoef read the zero quad
+    const bool dead = !m2lw_half_live(NC, KS - 1, 1) && hk == 1;
+    auto compute = [&](const u32x4* buf, const u32x4* bh, const u32x4* bl) {
+  #pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        u32x4 ah[RB], al[RB];
+  #pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          const bool cr = s < m2lw_cross_steps(NC, r);
+          int q0 = (cr ? arc[r] : arn[r]) + m2lw_pos(NC, r, s, 0, 0);
+          if (s == KS - 1 && dead) q0 = S::NQ - 1;
+          ah[r] = buf[q0];
+          if (f16_cross_w(r, s)) al[r] = buf[s == KS - 1 && dead ? S::NQ - 1 : q0 + 1];
+        }
+  #pragma unroll
+        for (int t = 0; t < PR::N; ++t)
+  #pragma unroll
+          for (int r = 0; r < RB; ++r)
+            if (t == PR::N - 1 || f16_cross_w(r, s))
+              acc[r] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                  __builtin_bit_cast(f16x8, PR::a[t] ? al[r] : ah[r]),
+                  __builtin_bit_cast(f16x8, PR::b[t] ? bl[s] : bh[s]), acc[r], 0, 0, 0);
+      }
+    };
+
+    u32x4 bh0[KS], bl0[KS], bh1[KS], bl1[KS];
+    int i = i0, ndx, ndy, ndz;
+    auto lookup_at = [&](int k) -> m2l::Src {
+      int ldx, ldy, ldz;
+      const int kk = k < i1 ? k : i1 - 1;
+      offset_at(kk, ldx, ldy, ldz);
+      return tl.lookup(sSlot, kk, ldx, ldy, ldz);
+    };
+    m2l::Src cur_src = lookup_at(i0), next_src = lookup_at(i0 + 1);
+    load_b(row_of(cur_src), bh0, bl0);
+    stage(offset_at(i0, ndx, ndy, ndz), sT0);
     __builtin_amdgcn_s_waitcnt(kVmcntZero);
-    if (more) {
-      const int mv = move_at(i + 1);
-      if (mv != 0) shift_b(mv, bhc, blc, bhn, bln);
-      stage(offset_at(i + 1, ndx, ndy, ndz), bufn);
-      if (face(mv)) load_b(row_of(next_src), bhn, bln);
-    }
-    if (__any(cur_src.ok)) compute(bufc, bhc, blc);
-    if ((i + 1 - i0) % kGroupF16 == 0 || !more) {
-#pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        sum[r] += acc[r];
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[r][e] = 0.f;
+    __syncthreads();
+    // offset i: its operator in bufc, its B in (bhc, blc); the next offset's B
+    // goes to (bhn, bln) (shifted from this one's and completed by the face
+    // lanes' loads, or loaded by every lane) and its operator to bufn.
+    auto do_offset = [&](const u32x4* bufc, u32x4* bufn, u32x4* bhc, u32x4* blc, u32x4* bhn,
+                         u32x4* bln) -> bool {
+      const bool more = i + 1 < i1;
+      const m2l::Src far_src = lookup_at(i + 2);
+      // this offset's source quads (loaded during the previous one) first: the
+      // copy and the loads issued below then need no wait until the barrier
+      __builtin_amdgcn_s_waitcnt(kVmcntZero);
+      if (more) {
+        const int mv = move_at(i + 1);
+        if (mv != 0) shift_b(mv, bhc, blc, bhn, bln);
+        stage(offset_at(i + 1, ndx, ndy, ndz), bufn);
+        if (face(mv)) load_b(row_of(next_src), bhn, bln);
       }
+      if (__any(cur_src.ok)) compute(bufc, bhc, blc);
+      if ((i + 1 - i0) % kGroupF16 == 0 || !more) {
+  #pragma unroll
+        for (int r = 0; r < RB; ++r) {
+          sum[r] += acc[r];
+  #pragma unroll
+          for (int e = 0; e < 16; ++e) acc[r][e] = 0.f;
+        }
+      }
+      if (!more) return false;
+      // this wave's part of the copy has landed (the next offset's source
+      // loads, issued after it, may still be in flight), and every LDS read of
+      // this offset has returned (each fed a product); then the work-group's
+      // barrier, without the memory fence of __syncthreads (which would wait
+      // for the source loads too)
+      __builtin_amdgcn_s_waitcnt(vmcnt_op(M2LW_VMB ? 2 * KS : 0));
+      __asm__ volatile("" ::: "memory");
+      __builtin_amdgcn_s_barrier();
+      __asm__ volatile("" ::: "memory");
+      ++i;
+      cur_src = next_src;
+      next_src = far_src;
+      return true;
+    };
+    while (do_offset(sT0, sT1, bh0, bl0, bh1, bl1) && do_offset(sT1, sT0, bh1, bl1, bh0, bl0)) {
     }
-    if (!more) return false;
-    // this wave's part of the copy has landed (the next offset's source
-    // loads, issued after it, may still be in flight), and every LDS read of
-    // this offset has returned (each fed a product); then the work-group's
-    // barrier, without the memory fence of __syncthreads (which would wait
-    // for the source loads too)
-    __builtin_amdgcn_s_waitcnt(vmcnt_op(M2LW_VMB ? 2 * KS : 0));
-    __asm__ volatile("" ::: "memory");
-    __builtin_amdgcn_s_barrier();
-    __asm__ volatile("" ::: "memory");
-    ++i;
-    cur_src = next_src;
-    next_src = far_src;
-    return true;
-  };
-  while (do_offset(sT0, sT1, bh0, bl0, bh1, bl1) && do_offset(sT1, sT0, bh1, bl1, bh0, bl0)) {
-  }
 
-  if (!tl.col_ok) return;
-  float* o = !whole && tl.part > 0
-                 ? half_out + ((tl.sidx * (kM2lParts - 1) + tl.part - 1) * m2l::kTargetsPerGroup + wave * 32 + col) * NC
-                 : out + (tl.lvl_off + tl.target_slot(a)) * NC;
-  const float lsc = ldexpf(1.f, f16_level_exp(lmax[tl.l]) - 14);
-#pragma unroll
-  for (int r = 0; r < RB; ++r)
-#pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int row = 32 * r + 8 * (e / 4) + 4 * hk + e % 4;
-      if (row < NC) o[row] = sum[r][e] * (rowf[row] * lsc);
+    if (!tl.col_ok) return;
+    float* o = !whole && tl.part > 0
+                   ? half_out + ((tl.sidx * (kM2lParts - 1) + tl.part - 1) * m2l::kTargetsPerGroup + wave * 32 + col) * NC
+                   : out + (tl.lvl_off + tl.target_slot(a)) * NC;
+    const float lsc = ldexpf(1.f, f16_level_exp(lmax[tl.l]) - 14);
+  #pragma unroll
+    for (int r = 0; r < RB; ++r)
+  #pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = 32 * r + 8 * (e / 4) + 4 * hk + e % 4;
+        if (row < NC) o[row] = sum[r][e] * (rowf[row] * lsc);
+      }
+  };
+  if constexpr (!PERSIST) {
+    tile(-1);
+  } else {
+    __shared__ uint32_t sK;
+    const int xcd = (int)(blockIdx.x % 8);
+    const int64_t per_xcd = (a.ngroups + 7) / 8;
+    for (;;) {
+      if (threadIdx.x == 0) sK = atomicAdd(&ticket[xcd], 1u);
+      __syncthreads();
+      const int64_t k = sK;
+      __syncthreads();  // every lane has read sK before the next ticket
+      const int64_t lg = xcd * per_xcd + k;
+      if (k >= per_xcd || lg >= a.ngroups) return;  // uniform over the work-group
+      tile(lg);
     }
+  }
 }
 
 // Parts 1.. of the split groups into the M2L result: one wave per (split
@@ -940,14 +973,32 @@ struct M2LBfRun {
     const m2l::Args a = split_args(Pl);
     prof_begin(Pl, FMM_PHASE_M2L, s);
     if constexpr (m2l_f16_wide(P)) {
+      if (Pl->m2l_persistent) {
+        // two resident work-groups per CU, whole tiles from per-XCD counters
+        const m2l::Args ap = m2l::make_args(Pl);
+        uint32_t* ticket = wsp<uint32_t>(Pl, lay.m2l_ctl);
+        e = fill_u32(ticket, 8, 0u, s);
+        if (e != hipSuccess) return e;
+        const unsigned grid = 2 * 256;
+        if (Pl->adaptive)
+          k_m2l_w<P, true, true><<<grid, kWideThreads, 0, s>>>(
+              ap, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+              lmax, wsp<float>(Pl, lay.f16_rowf), nullptr, ticket);
+        else
+          k_m2l_w<P, false, true><<<grid, kWideThreads, 0, s>>>(
+              ap, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
+              lmax, wsp<float>(Pl, lay.f16_rowf), nullptr, ticket);
+        prof_end(Pl, s);
+        return hipGetLastError();
+      }
       if (Pl->adaptive)
-        k_m2l_w<P, true><<<m2l::grid_of(a), kWideThreads, 0, s>>>(
+        k_m2l_w<P, true, false><<<m2l::grid_of(a), kWideThreads, 0, s>>>(
             a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-            lmax, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
+            lmax, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half), nullptr);
       else
-        k_m2l_w<P, false><<<m2l::grid_of(a), kWideThreads, 0, s>>>(
+        k_m2l_w<P, false, false><<<m2l::grid_of(a), kWideThreads, 0, s>>>(
             a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),
-            lmax, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half));
+            lmax, wsp<float>(Pl, lay.f16_rowf), wsp<float>(Pl, lay.m2l_half), nullptr);
     } else if (Pl->adaptive)
       k_m2l_bf<P, 2, true, true><<<m2l::grid_of(a), kThreads, 0, s>>>(
           a, mq, wsp<u32x4>(Pl, lay.zero_row), wsp<u32x4>(Pl, lay.op_m2lb), wsp<float>(Pl, lay.m2l_out),

@@ -181,8 +181,10 @@ struct TileT {
   __device__ __forceinline__ bool setup(const Args& a, int tix, uint32_t* sSlot, int* sBox) {
     int64_t lg;
     if constexpr (SPLIT) {
-      decode_group(a, blockIdx.x, lg, part, sidx);
-      if (!locate(a, lg, tix)) return false;
+      int pt;
+      int64_t si;
+      decode_group(a, blockIdx.x, lg, pt, si);
+      return setup_at(a, lg, pt, si, tix, sSlot, sBox);
     } else {
       // (the same steps as locate, written out: the FP32 / FP64 kernel's main
       // loop was measured 7 % slower when they were shared)
@@ -204,15 +206,29 @@ struct TileT {
       const int64_t idx = lg - a.group_off[l];
       pi = (int)(idx % 8);
       tile = idx / 8;
-    }
-    if constexpr (AD) return true;  // no halo, the source rows come from the table
-    const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
-    if constexpr (!SPLIT) {
       nb = 1 << l;
       lvl_off = a.exp_off[l];
       dense_off = a.lvl_off[l];
       retarget(a, tix);
+      stage_halo(a, sSlot, sBox);
+      return true;
     }
+  }
+
+  // setup for logical group lg given by the caller (part pt, split index si;
+  // pt = -1 for a whole group): the persistent launches.
+  __device__ __forceinline__ bool setup_at(const Args& a, int64_t lg, int pt, int64_t si, int tix,
+                                           uint32_t* sSlot, int* sBox) {
+    part = pt;
+    sidx = si;
+    if (!locate(a, lg, tix)) return false;
+    if constexpr (!AD) stage_halo(a, sSlot, sBox);  // the adaptive tree's sources come from its table
+    return true;
+  }
+
+  // Uniform tree: the slots of the tile's halo into sSlot (barriers).
+  __device__ __forceinline__ void stage_halo(const Args& a, uint32_t* sSlot, int* sBox) {
+    const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
     const int tid = threadIdx.x;
     if (tid < 6) sBox[tid] = tid < 3 ? nb : -1;
     __syncthreads();
@@ -240,7 +256,6 @@ struct TileT {
       sSlot[e] = c2s[lex_index(x, y, z, l)];
     }
     __syncthreads();
-    return true;
   }
 
   // Level, class and tile of logical group lg, and this lane's target (number

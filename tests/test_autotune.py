@@ -32,6 +32,11 @@ def test_schedules_per_form_and_tree():
     assert len(T.schedules_for({"depth": 7, "leaf_max": 64}, "F32")) == 2
     s = T.schedules_for({"depth": 7, "leaf_max": 64}, "BF16X3")
     assert len(s) == 6 and all(set(x) == {"p2p_persistent", "m2l_split"} for x in s)
+    # the persistent M2L: FP16 form up to p = 8 only
+    s = T.schedules_for({"depth": 7, "leaf_max": 64}, "F16X2", p=6)
+    assert len(s) == 8 and sum("m2l_persistent" in x for x in s) == 2
+    assert len(T.schedules_for({"depth": 7, "leaf_max": 64}, "F16X2", p=10)) == 6
+    assert len(T.schedules_for({"depth": 7, "leaf_max": 64}, "BF16X3", p=6)) == 6
 
 
 def test_reference_check_excludes():
@@ -68,7 +73,7 @@ def test_tune_on_clusters():
 
     trees = [{"depth": 7, "leaf_max": 32}, {"depth": 7, "leaf_max": 64}]
     best, results = T.tune(tp, tq, 8, trees, side=0.0, reps=3, reference=reference)
-    assert len(results) == 2 * (6 + 6 + 2)
+    assert len(results) == 2 * (8 + 6 + 2)
     assert best is not None and best.meets(1e-6, 1e-5)
     assert all(best.ms <= r.ms for r in results if r.meets(1e-6, 1e-5))
     assert all(r.reference_ok for r in results)

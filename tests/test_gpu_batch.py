@@ -128,6 +128,39 @@ def test_schedules_give_the_same_result(prec):
     u.close()
 
 
+@pytest.mark.parametrize("tree", ["uniform", "adaptive"])
+def test_persistent_m2l_equals_unsplit(tree):
+    """The persistent M2L (FP16 form, p <= 8) sums every tile as the unsplit
+    launch does: bitwise equal to FMM_SCHED_M2L_SPLIT 0, on a uniform tree
+    with full tiles (levels 4-5) and on the batch forest; refused where the
+    form does not run."""
+    import torch
+    dev = torch.device("cuda:0")
+    if tree == "uniform":
+        pos, q = W.uniform_gauss(200_000, 131)
+        kw = dict(p=8, depth=5)
+    else:
+        pos, q, _ = small_batch()
+        kw = dict(p=6, depth=6, lo=(0.0, 0.0, 0.0), side=4.0, leaf_max=16, batch_level=2)
+    tp, tq = torch.from_numpy(pos).to(dev), torch.from_numpy(q).to(dev)
+    f = B.FMM(tp, precision=B.FMM_PREC_MIXED, m2l_kind=B.FMM_M2L_F16X2, **kw)
+    B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_M2L_SPLIT, 0)
+    a = f.evaluate(tq)
+    B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_M2L_PERSISTENT, 1)
+    b = f.evaluate(tq)
+    B.fmm_replan(f.plan, tp)  # the schedule survives a re-plan
+    c = f.evaluate(tq)
+    assert f.check() == 0
+    for x, y, z in zip(a, b, c):
+        assert torch.equal(x, y) and torch.equal(x, z)
+    f.close()
+    g = B.FMM(tp, precision=B.FMM_PREC_MIXED, m2l_kind=B.FMM_M2L_BF16X3, **kw)
+    with pytest.raises(B.FMMError) as ei:
+        B.fmm_plan_set_schedule(g.plan, B.FMM_SCHED_M2L_PERSISTENT, 1)
+    assert ei.value.status == 6
+    g.close()
+
+
 def test_graph_replay_equals_eager():
     import torch
     pos, q, counts = small_batch()
