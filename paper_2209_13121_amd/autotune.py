@@ -9,7 +9,9 @@ For a given charge set and tree family it searches
     as one wave per box or as a persistent launch over a cost-ordered
     work-list; how many tail work-groups per XCD the split M2L forms run in
     four parts, or (the FP16 form at p <= 8) the M2L as a persistent launch
-    over per-XCD tile counters.
+    over per-XCD tile counters;
+  * then, for the best candidate on an adaptive tree, the P2P tile (sources
+    staged in LDS at a time).
 Every candidate is measured on the GPU through the C ABI, the way the
 benchmark runs a step: one plan, then fmm_replan + fmm_evaluate timed with HIP
 events on the launch stream (median of ``reps``).  The gate is the library's:
@@ -29,7 +31,8 @@ SPLIT_KINDS = ("F16X2", "BF16X3", "BF16X2")
 # schedule values searched (key -> values); the first value is the default
 SCHEDULES = {"p2p_persistent": (0, 1), "m2l_split": (16, 8, 0)}
 _SCHED_KEY = {"p2p_persistent": B.FMM_SCHED_P2P_PERSISTENT, "m2l_split": B.FMM_SCHED_M2L_SPLIT,
-              "m2l_persistent": B.FMM_SCHED_M2L_PERSISTENT}
+              "m2l_persistent": B.FMM_SCHED_M2L_PERSISTENT, "p2p_tile": B.FMM_SCHED_P2P_TILE}
+P2P_TILES = (256, 128, 512)  # sources per staged P2P tile; the first is the default
 WIDE_PMAX = 8  # the FP16 form's persistent M2L runs up to this order
 
 
@@ -111,25 +114,37 @@ def tune(pos, q, p, trees, kinds=KINDS, lo=(0.0, 0.0, 0.0), side=1.0, batch_leve
     n = q.numel()
     stream = stream or torch.cuda.current_stream()
     results = []
+    refs = {}  # tree -> the FP64 forces and energy of that tree
+
+    def run(tree, kind, scheds):
+        f64, e64, ms64 = refs[tuple(sorted(tree.items()))]
+        fnorm = torch.linalg.vector_norm(f64)
+        cfg = B.make_config(p=p, precision=B.FMM_PREC_MIXED, m2l_kind=getattr(B, "FMM_M2L_" + kind),
+                            lo=lo, side=side, batch_level=batch_level, **tree)
+        ws = torch.empty(B.fmm_workspace_size(cfg, n), dtype=torch.uint8, device=pos.device)
+        for sched in scheds:
+            ms, phi, f, e = _time(torch, cfg, n, pos, q, ws, stream, reps, sched)
+            r = Result(tree=dict(tree), kind=kind, ms=ms, energy_err=abs(e - e64) / abs(e64),
+                       force_err=float(torch.linalg.vector_norm(f - f64) / fnorm),
+                       schedule=dict(sched), extra={"fp64_ms": ms64})
+            if reference is not None and r.meets(gate_e, gate_f):
+                r.reference_ok = bool(reference(tree, phi, f, e))
+            results.append(r)
+        del ws
+
     for tree in trees:
         ref_cfg = B.make_config(p=p, precision=B.FMM_PREC_FP64, lo=lo, side=side,
                                 batch_level=batch_level, **tree)
         ws = torch.empty(B.fmm_workspace_size(ref_cfg, n), dtype=torch.uint8, device=pos.device)
         ms64, _, f64, e64 = _time(torch, ref_cfg, n, pos, q, ws, stream, 1, {})
         del ws
-        fnorm = torch.linalg.vector_norm(f64)
+        refs[tuple(sorted(tree.items()))] = (f64, e64, ms64)
         for kind in kinds:
-            cfg = B.make_config(p=p, precision=B.FMM_PREC_MIXED, m2l_kind=getattr(B, "FMM_M2L_" + kind),
-                                lo=lo, side=side, batch_level=batch_level, **tree)
-            ws = torch.empty(B.fmm_workspace_size(cfg, n), dtype=torch.uint8, device=pos.device)
-            for sched in (schedules_for(tree, kind, p) if search_schedules else [{}]):
-                ms, phi, f, e = _time(torch, cfg, n, pos, q, ws, stream, reps, sched)
-                r = Result(tree=dict(tree), kind=kind, ms=ms, energy_err=abs(e - e64) / abs(e64),
-                           force_err=float(torch.linalg.vector_norm(f - f64) / fnorm),
-                           schedule=dict(sched), extra={"fp64_ms": ms64})
-                if reference is not None and r.meets(gate_e, gate_f):
-                    r.reference_ok = bool(reference(tree, phi, f, e))
-                results.append(r)
-            del ws
+            run(tree, kind, schedules_for(tree, kind, p) if search_schedules else [{}])
         torch.cuda.empty_cache()
-    return select(results, gate_e, gate_f), results
+    best = select(results, gate_e, gate_f)
+    # then the P2P tile of the best candidate (adaptive trees: the per-leaf kernels)
+    if search_schedules and best is not None and best.tree.get("leaf_max", 0) > 0:
+        run(best.tree, best.kind, [dict(best.schedule, p2p_tile=t) for t in P2P_TILES if t != 256])
+        best = select(results, gate_e, gate_f)
+    return best, results

@@ -28,7 +28,7 @@ EXPORTS = ["fmm_config_default", "fmm_workspace_size", "fmm_plan", "fmm_evaluate
            "fmm_check", "fmm_destroy", "fmm_status_string", "fmm_plan_leaves", "fmm_plan_cube",
            "fmm_hilbert_index", "fmm_profile_enable", "fmm_profile_read", "fmm_plan_work", "fmm_plan_tree_stats",
            "fmm_evaluate_static", "fmm_replan", "fmm_plan_set_schedule"]
-FMM_SCHED_P2P_PERSISTENT, FMM_SCHED_M2L_SPLIT, FMM_SCHED_M2L_PERSISTENT = 0, 1, 2
+FMM_SCHED_P2P_PERSISTENT, FMM_SCHED_M2L_SPLIT, FMM_SCHED_M2L_PERSISTENT, FMM_SCHED_P2P_TILE = 0, 1, 2, 3
 FMM_STATIC_SCRATCH_BYTES = 128 << 20
 
 

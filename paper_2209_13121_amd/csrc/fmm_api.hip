@@ -239,7 +239,9 @@ fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, in
   const int p2p_persistent = keep_operators ? P->p2p_persistent : 0;
   const int m2l_split = keep_operators ? P->m2l_split : kM2lSplitPerXcd;
   const int m2l_persistent = keep_operators ? P->m2l_persistent : 0;
+  const int p2p_tile = keep_operators ? P->p2p_tile : 256;
   memset(P, 0, sizeof(*P));
+  P->p2p_tile = p2p_tile;
   P->p2p_persistent = p2p_persistent;
   P->m2l_split = m2l_split;
   P->m2l_persistent = m2l_persistent;
@@ -358,6 +360,10 @@ fmm_status fmm_plan_set_schedule(fmm_plan_t* P, int key, int value) {
     case FMM_SCHED_M2L_SPLIT:
       if (value < 0 || value > kM2lSplitPerXcd) return FMM_E_INVALID_ARG;
       P->m2l_split = value;
+      return FMM_OK;
+    case FMM_SCHED_P2P_TILE:
+      if (value != 128 && value != 256 && value != 512) return FMM_E_INVALID_ARG;
+      P->p2p_tile = value;
       return FMM_OK;
     case FMM_SCHED_M2L_PERSISTENT:
       if (value != 0 && value != 1) return FMM_E_INVALID_ARG;

@@ -250,6 +250,7 @@ struct fmm_plan_s {
   int p2p_persistent;  // adaptive P2P as a persistent kernel over the work-list
   int m2l_split;       // split-M2L tail work-groups per XCD (0 .. kM2lSplitPerXcd)
   int m2l_persistent;  // wide FP16 M2L as a persistent launch over per-XCD tile counters
+  int p2p_tile;        // P2P sources per staged LDS tile (128, 256 or 512)
 };
 
 namespace fmm {

@@ -4,7 +4,8 @@
 // One wave per target leaf t.  The sources of t are the particles of its
 // neighbour leaves (uniform tree: the 27 leaves at Chebyshev distance <= 1;
 // adaptive tree: the leaves of U(t), t included).  They are staged in LDS in
-// tiles of kTile, each source as its offset from t's centre in t's box units,
+// tiles of TILE (kTile by default, 128 or 512 by schedule), each source as its
+// offset from t's centre in t's box units,
 // s_j = o_c + sc_c u_j (o_c the source leaf's centre offset, sc_c its size in
 // t's units, u_j the particle's offset in its own leaf, all exact in FP64),
 // then every lane reads the tile:
@@ -32,12 +33,14 @@
 // fixed tree order over the per-particle terms.
 #include <math.h>
 
+#include <type_traits>
+
 #include "fmm_internal.h"
 
 namespace fmm {
 namespace {
 
-constexpr int kTile = 256;   // sources per staged tile
+constexpr int kTile = 256;   // sources per staged tile (default; FMM_SCHED_P2P_TILE)
 constexpr int kNbBatch = 64;  // neighbour leaves handled per batch (one per lane)
 constexpr int kKMax = 4;      // targets per lane of a large leaf (groups of 64 kKMax targets)
 // occupancy the register budget is held to: FP32 4 waves per SIMD (128 VGPRs),
@@ -291,17 +294,17 @@ __device__ __forceinline__ void tile_big(Acc<T> (&acc)[kKMax], const Tgt<T> (&tg
   }
 }
 
-// LDS of one wave's leaf.
-template <typename T>
+// LDS of one wave's leaf (TILE sources per staged tile).
+template <typename T, int TILE>
 struct P2PShared {
-  SSrc<T> sS[kTile];
+  SSrc<T> sS[TILE];
   Nb sNb[kNbBatch];
   uint32_t sPre[kNbBatch + 1];
 };
 
 // The near field of target leaf b (one wave).
-template <typename T, typename NBS>
-__device__ __forceinline__ void p2p_leaf(const NBS& nbs, int64_t b, P2PShared<T>& sh,
+template <typename T, typename NBS, int TILE>
+__device__ __forceinline__ void p2p_leaf(const NBS& nbs, int64_t b, P2PShared<T, TILE>& sh,
                                          const DevParams* __restrict__ dp,
                                          const Rec<double>* __restrict__ src, const FinishArgs& fa) {
   SSrc<T>* sS = sh.sS;
@@ -349,8 +352,8 @@ __device__ __forceinline__ void p2p_leaf(const NBS& nbs, int64_t b, P2PShared<T>
       if (lane == 0) sPre[0] = 0;
       const uint32_t total = __shfl(c, 63, 64);
       __syncthreads();
-      for (uint32_t c0 = 0; c0 < total; c0 += kTile) {
-        const int ns = (int)(total - c0 < (uint32_t)kTile ? total - c0 : (uint32_t)kTile);
+      for (uint32_t c0 = 0; c0 < total; c0 += TILE) {
+        const int ns = (int)(total - c0 < (uint32_t)TILE ? total - c0 : (uint32_t)TILE);
         // stage: lane stages sources c0 + lane + 64 m of the batch
         for (int m = lane; m < ns; m += 64) {
           const uint32_t q = c0 + m;
@@ -404,12 +407,12 @@ __device__ __forceinline__ void p2p_leaf(const NBS& nbs, int64_t b, P2PShared<T>
 }
 
 // One wave per box (boxes that are no leaf, or empty, return at once).
-template <typename T, typename NBS>
+template <typename T, typename NBS, int TILE>
 __global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p(NBS nbs, int64_t nbox, const DevParams* __restrict__ dp,
                                             const Rec<double>* __restrict__ src, FinishArgs fa) {
-  __shared__ P2PShared<T> sh;
+  __shared__ P2PShared<T, TILE> sh;
   if ((int64_t)blockIdx.x >= nbox) return;
-  p2p_leaf<T, NBS>(nbs, blockIdx.x, sh, dp, src, fa);
+  p2p_leaf<T, NBS, TILE>(nbs, blockIdx.x, sh, dp, src, fa);
 }
 
 // Persistent form over a work-list: the non-empty leaves in order of
@@ -419,19 +422,19 @@ __global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p(NBS nbs, int64_
 // Every wave leaves once the tickets pass the list's length.  Each leaf's
 // outputs are written by its one task in a fixed order, so the result does
 // not depend on which wave takes it.
-template <typename T, typename NBS>
+template <typename T, typename NBS, int TILE>
 __global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p_persistent(
     NBS nbs, const uint32_t* __restrict__ worklist, const uint32_t* __restrict__ ntasks,
     uint32_t* __restrict__ ticket, const DevParams* __restrict__ dp, const Rec<double>* __restrict__ src,
     FinishArgs fa) {
-  __shared__ P2PShared<T> sh;
+  __shared__ P2PShared<T, TILE> sh;
   const uint32_t n = ntasks[0];
   for (;;) {
     uint32_t t = 0;
     if (threadIdx.x == 0) t = atomicAdd(ticket, 1u);
     t = __shfl(t, 0, 64);
     if (t >= n) break;  // uniform over the wave
-    p2p_leaf<T, NBS>(nbs, worklist[t], sh, dp, src, fa);
+    p2p_leaf<T, NBS, TILE>(nbs, worklist[t], sh, dp, src, fa);
     __syncthreads();  // the tile of this leaf is no longer read
   }
 }
@@ -642,6 +645,16 @@ AdaptiveNbs adaptive_nbs(fmm_plan_s* P) {
                      wsp<uint32_t>(P, lay.a_range), wsp<int32_t>(P, lay.a_child0),
                      wsp<uint32_t>(P, lay.a_off), wsp<uint32_t>(P, lay.a_uidx)};
 }
+// Calls f with std::integral_constant<int, TILE> for the plan's P2P tile.
+template <typename F>
+void launch_tile(int tile, F&& f) {
+  if (tile == 128)
+    f(std::integral_constant<int, 128>{});
+  else if (tile == 512)
+    f(std::integral_constant<int, 512>{});
+  else
+    f(std::integral_constant<int, kTile>{});
+}
 }  // namespace
 
 // Plan time (adaptive tree, after its lists): the P2P work-list of the
@@ -696,15 +709,22 @@ hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
       if (e != hipSuccess) return e;
       const uint32_t* wl = wsp<uint32_t>(P, lay.a_p2p_list);
       const uint32_t* nt = wsp<uint32_t>(P, lay.a_p2p_ctl) + 64;
-      const unsigned grid = 256 * 16;
-      if (P->mixed)
-        k_p2p_persistent<float, AdaptiveNbs><<<grid, 64, 0, s>>>(nb, wl, nt, ticket, dp, src, fa);
-      else
-        k_p2p_persistent<double, AdaptiveNbs><<<grid, 64, 0, s>>>(nb, wl, nt, ticket, dp, src, fa);
-    } else if (P->mixed) {
-      k_p2p<float, AdaptiveNbs><<<(unsigned)nbox, 64, 0, s>>>(nb, nbox, dp, src, fa);
+      launch_tile(P->p2p_tile, [&](auto tile) {
+        constexpr int TL = decltype(tile)::value;
+        const unsigned grid = 256 * 16;
+        if (P->mixed)
+          k_p2p_persistent<float, AdaptiveNbs, TL><<<grid, 64, 0, s>>>(nb, wl, nt, ticket, dp, src, fa);
+        else
+          k_p2p_persistent<double, AdaptiveNbs, TL><<<grid, 64, 0, s>>>(nb, wl, nt, ticket, dp, src, fa);
+      });
     } else {
-      k_p2p<double, AdaptiveNbs><<<(unsigned)nbox, 64, 0, s>>>(nb, nbox, dp, src, fa);
+      launch_tile(P->p2p_tile, [&](auto tile) {
+        constexpr int TL = decltype(tile)::value;
+        if (P->mixed)
+          k_p2p<float, AdaptiveNbs, TL><<<(unsigned)nbox, 64, 0, s>>>(nb, nbox, dp, src, fa);
+        else
+          k_p2p<double, AdaptiveNbs, TL><<<(unsigned)nbox, 64, 0, s>>>(nb, nbox, dp, src, fa);
+      });
     }
   } else {
     UniformNbs nb{L, wsp<uint32_t>(P, lay.leaf_start), wsp<uint32_t>(P, lay.coord2slot) + lay.lvl_off[L],
@@ -718,10 +738,15 @@ hipError_t launch_near_and_finish(fmm_plan_s* P, double* d_phi, double* d_force,
         k_p2p_group<float><<<(unsigned)npar, 64, 0, s>>>(L, nb.start, nb.c2s, nb.s2c, sl, dp, src, fa);
       else
         k_p2p_group<double><<<(unsigned)npar, 64, 0, s>>>(L, nb.start, nb.c2s, nb.s2c, sl, dp, src, fa);
-    } else if (P->mixed)
-      k_p2p<float, UniformNbs><<<(unsigned)nleaf, 64, 0, s>>>(nb, nleaf, dp, src, fa);
-    else
-      k_p2p<double, UniformNbs><<<(unsigned)nleaf, 64, 0, s>>>(nb, nleaf, dp, src, fa);
+    } else {
+      launch_tile(P->p2p_tile, [&](auto tile) {
+        constexpr int TL = decltype(tile)::value;
+        if (P->mixed)
+          k_p2p<float, UniformNbs, TL><<<(unsigned)nleaf, 64, 0, s>>>(nb, nleaf, dp, src, fa);
+        else
+          k_p2p<double, UniformNbs, TL><<<(unsigned)nleaf, 64, 0, s>>>(nb, nleaf, dp, src, fa);
+      });
+    }
   }
   prof_end(P, s);
   if (d_energy) {

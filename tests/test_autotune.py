@@ -73,7 +73,7 @@ def test_tune_on_clusters():
 
     trees = [{"depth": 7, "leaf_max": 32}, {"depth": 7, "leaf_max": 64}]
     best, results = T.tune(tp, tq, 8, trees, side=0.0, reps=3, reference=reference)
-    assert len(results) == 2 * (8 + 6 + 2)
+    assert len(results) == 2 * (8 + 6 + 2) + 2  # and the other two P2P tiles of the best
     assert best is not None and best.meets(1e-6, 1e-5)
     assert all(best.ms <= r.ms for r in results if r.meets(1e-6, 1e-5))
     assert all(r.reference_ok for r in results)

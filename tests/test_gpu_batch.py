@@ -95,8 +95,9 @@ def test_many_tiny_systems_depth_at_batch_level():
 
 @pytest.mark.parametrize("prec", [B.FMM_PREC_MIXED, B.FMM_PREC_FP64])
 def test_schedules_give_the_same_result(prec):
-    """The persistent work-list P2P equals the per-box launch bitwise; the M2L
-    tail split only reorders a sum (within rounding); bad keys are refused."""
+    """The persistent work-list P2P and every P2P tile equal the per-box
+    launch bitwise; the M2L tail split only reorders a sum (within rounding);
+    bad keys and values are refused."""
     import torch
     pos, q, counts = small_batch()
     dev = torch.device("cuda:0")
@@ -111,6 +112,12 @@ def test_schedules_give_the_same_result(prec):
     assert f.check() == 0
     for x, y, z in zip(a, b, c):
         assert torch.equal(x, y) and torch.equal(x, z)
+    for tile in (128, 512):  # the P2P tile: the same sums in the same order
+        B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_P2P_TILE, tile)
+        d = f.evaluate(tq)
+        for x, y in zip(a, d):
+            assert torch.equal(x, y)
+    B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_P2P_TILE, 256)
     for split in (0, 8):
         B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_M2L_SPLIT, split)
         d = f.evaluate(tq)
@@ -120,6 +127,8 @@ def test_schedules_give_the_same_result(prec):
         B.fmm_plan_set_schedule(f.plan, 7, 0)
     with pytest.raises(B.FMMError):
         B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_M2L_SPLIT, 17)
+    with pytest.raises(B.FMMError):
+        B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_P2P_TILE, 300)
     f.close()
     u = B.FMM(tp[:1000].contiguous(), p=4, depth=3, precision=prec, lo=(0.0, 0.0, 0.0), side=4.0)
     with pytest.raises(B.FMMError) as ei:  # the work-list exists for adaptive trees only
