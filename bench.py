@@ -90,6 +90,47 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_bytes_per_launch": n * 4, "launches": 5}), flush=True)
 
 
+def graph_step(B, torch, pos, q, cfg, ws, steps, warmup):
+    """The headline step (fmm_replan + fmm_evaluate; uniform tree: kernels
+    only) captured once as a hipGraph and replayed: ms per replay (HIP events
+    around the replays) and whether a replay equals the eager step bitwise."""
+    n = q.numel()
+    out = [torch.empty(n, dtype=torch.float64, device=pos.device),
+           torch.empty((n, 3), dtype=torch.float64, device=pos.device),
+           torch.empty(1, dtype=torch.float64, device=pos.device)]
+    plan = B.fmm_plan(cfg, n, pos, ws)
+    B.fmm_replan(plan, pos)
+    B.fmm_evaluate(plan, q, *out)
+    torch.cuda.synchronize()
+    eager = [o.clone() for o in out]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        B.fmm_replan(plan, pos)
+        B.fmm_evaluate(plan, q, *out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        B.fmm_replan(plan, pos)
+        B.fmm_evaluate(plan, q, *out)
+    for _ in range(warmup):
+        g.replay()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(steps):
+        g.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    same = all(torch.equal(o, e) for o, e in zip(out, eager))
+    st = B.fmm_check(plan)
+    B.fmm_destroy(plan)
+    return {"ms": t0.elapsed_time(t1) / steps, "value": n / (t0.elapsed_time(t1) / steps / 1e3),
+            "equals_eager_bitwise": bool(same), "status": st}
+
+
 def m2l_source_hash(variant):
     import hashlib
     h = hashlib.sha256()
@@ -484,6 +525,8 @@ def main():
                              force=force.cpu().numpy(),
                              energy=float(energy.cpu()[0]), m2l=m2l, phases=phases, status=st,
                              work=work, plan_ms=plan_ms)
+        if name == HEADLINE:
+            results[name]["graph_step"] = graph_step(B, torch, pos, q, cfg, ws, args.steps, args.warmup)
         print(f"[bench] {name}: {ms:.3f} ms/step, status {st}", file=sys.stderr, flush=True)
         del ws
         torch.cuda.empty_cache()
@@ -533,6 +576,8 @@ def main():
             "m2l": m2l_rate(name),
             "first_plan_ms": r["plan_ms"],
         }
+        if "graph_step" in r:
+            variants[name]["graph_step"] = r["graph_step"]
     golden = load_golden(wl)
     acc = {name: accuracy_vs_oracle(r, golden) for name, r in results.items()}
     for name in variants:
@@ -590,6 +635,8 @@ def main():
                            "m2l_frac": v["m2l"]["frac"], "dE": v["rel_energy_err_vs_oracle"],
                            "dF": v["rel_rms_force_err_vs_oracle_sampled"]}
                        for k, v in variants.items()}
+    if "graph_step" in hl:
+        out["variants"][HEADLINE]["graph_step_ms"] = hl["graph_step"]["ms"]
     out["p2p_depth4_frac"] = {k: v["frac"] for k, v in detail["p2p_depth4"].items()}
     out["small"] = detail["small"]
     for key in ("adaptive", "batch"):

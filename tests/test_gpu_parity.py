@@ -377,3 +377,54 @@ def test_replan_equals_fresh_plan(kw):
         assert torch.equal(x, y)
     f.close()
     g.close()
+
+
+@pytest.mark.parametrize("prec", [B.FMM_PREC_MIXED, B.FMM_PREC_FP64], ids=["mixed", "fp64"])
+def test_uniform_replan_and_evaluate_replay_as_one_graph(prec):
+    """On the uniform tree fmm_replan and fmm_evaluate enqueue kernels only (no
+    read-back, no memset node): the tree build for new positions and the
+    evaluation are captured together as one hipGraph.  The positions are
+    rewritten in place between replays, with unrelated eager work in between;
+    every replay equals the eager replan + evaluate of those positions
+    bitwise."""
+    import torch
+    dev = torch.device("cuda:0")
+    pos, q = W.uniform_gauss(50_000, 141)
+    rng = np.random.default_rng(142)
+    pos2 = np.clip(pos + 0.01 * rng.standard_normal(pos.shape), 0.0, np.nextafter(1.0, 0.0))
+    tp = torch.from_numpy(pos).to(dev)
+    tq = torch.from_numpy(q).to(dev)
+    f = B.FMM(tp, p=6, depth=4, precision=prec)
+    n = len(q)
+    out = [torch.empty(n, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev),
+           torch.empty(1, dtype=torch.float64, device=dev)]
+    ref = {}
+    for name, P in (("a", pos), ("b", pos2)):
+        tp.copy_(torch.from_numpy(P))
+        B.fmm_replan(f.plan, tp)
+        B.fmm_evaluate(f.plan, tq, *out)
+        torch.cuda.synchronize()
+        ref[name] = [o.clone() for o in out]
+    assert not torch.equal(ref["a"][0], ref["b"][0])
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream
+        B.fmm_replan(f.plan, tp)
+        B.fmm_evaluate(f.plan, tq, *out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        B.fmm_replan(f.plan, tp)
+        B.fmm_evaluate(f.plan, tq, *out)
+    for rep, (name, P) in enumerate((("a", pos), ("b", pos2), ("a", pos))):
+        tp.copy_(torch.from_numpy(P))
+        for o in out:
+            o.zero_()
+        _ = (tq * 2.0).sum()  # unrelated eager work between replays
+        g.replay()
+        torch.cuda.synchronize()
+        for o, r in zip(out, ref[name]):
+            assert torch.equal(o, r), (rep, name)
+    assert f.check() == 0
+    f.close()
