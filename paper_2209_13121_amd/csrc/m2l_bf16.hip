@@ -142,13 +142,18 @@ __global__ void k_f16_level_max(const float* __restrict__ m32, int ms, int nc,
   const int64_t n4 = (lb.box_off[l + 1] - lb.box_off[l]) * ms / 4;
   const float4* v4 = reinterpret_cast<const float4*>(m32 + lb.box_off[l] * ms);
   float m = 0.f;
-  for (int64_t t = (blockIdx.x - lb.blk_off[l]) * kBlock + threadIdx.x; t < n4; t += ngrp * kBlock) {
+  // k = 4 t mod ms, advanced by the stride's residue (no division per element)
+  const int64_t t0 = (blockIdx.x - lb.blk_off[l]) * kBlock + threadIdx.x, stride = ngrp * kBlock;
+  const int kinc = (int)((4 * stride) % ms);
+  int k = (int)((4 * t0) % ms);
+  for (int64_t t = t0; t < n4; t += stride) {
     const float4 v = v4[t];
-    const int k = (int)((4 * t) % ms);
     if (k < nc) m = fmaxf(m, fabsf(v.x * colf[k]));
     if (k + 1 < nc) m = fmaxf(m, fabsf(v.y * colf[k + 1]));
     if (k + 2 < nc) m = fmaxf(m, fabsf(v.z * colf[k + 2]));
     if (k + 3 < nc) m = fmaxf(m, fabsf(v.w * colf[k + 3]));
+    k += kinc;
+    if (k >= ms) k -= ms;
   }
 #pragma unroll
   for (int w = 32; w >= 1; w >>= 1) m = fmaxf(m, __shfl_xor(m, w, 64));
@@ -179,17 +184,25 @@ __global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, in
                                const float* __restrict__ colf, LevelBlocks lb,
                                const uint32_t* __restrict__ lmax, u32x4* __restrict__ out) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t box = lb.box_off[lb.l0] + t / lpb;
-  const int u = (int)(t % lpb);
+  const int sh = lpb == 16 ? 4 : 5;  // lpb is 16 or 32
+  const int64_t box = lb.box_off[lb.l0] + (t >> sh);
+  const int u = (int)(t & (lpb - 1));
   if (box >= lb.box_off[lb.l1 + 1] || u >= 4 * kst) return;
   int l = lb.l0;
   while (l < lb.l1 && box >= lb.box_off[l + 1]) ++l;
-  const int e = f16_level_exp(lmax[l]);
+  // 2^(14 - e): exact, so x colf_k sc equals ldexp(x colf_k, 14 - e)
+  const float sc = ldexpf(1.f, 14 - f16_level_exp(lmax[l]));
+  // the row's k = 8 u .. 8 u + 7 as two float4 loads (ms is a multiple of 4;
+  // quads past the row read as zero)
+  const float4* r4 = reinterpret_cast<const float4*>(m32 + box * ms);
+  const float4 z4 = make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4 v0 = 8 * u < ms ? r4[2 * u] : z4, v1 = 8 * u + 4 < ms ? r4[2 * u + 1] : z4;
+  const float x[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
   uint32_t pc[8][2];
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int k = 8 * u + j;
-    split_f16_f32(ldexpf(k < nc ? m32[box * ms + k] * colf[k] : 0.f, 14 - e), pc[j]);
+    split_f16_f32(k < nc ? x[j] * colf[k] * sc : 0.f, pc[j]);
   }
   u32x4 q[2];
   pack_quads<2>(pc, q);
@@ -570,9 +583,6 @@ constexpr bool chain_order_ok(const ChainOrder& t) {
 static_assert(chain_order_ok(make_chain_order()), "offset orders of the reuse form");
 static __constant__ ChainOrder kChainOrder = make_chain_order();
 
-#ifndef M2LW_VMB
-#define M2LW_VMB 1
-#endif
 template <int P>
 struct WShape {
   static constexpr int NC = (P + 1) * (P + 1);
@@ -822,7 +832,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void k_m2l_w(m2l::Args a, const u3
       // this offset has returned (each fed a product); then the work-group's
       // barrier, without the memory fence of __syncthreads (which would wait
       // for the source loads too)
-      __builtin_amdgcn_s_waitcnt(vmcnt_op(M2LW_VMB ? 2 * KS : 0));
+      __builtin_amdgcn_s_waitcnt(vmcnt_op(2 * KS));
       __asm__ volatile("" ::: "memory");
       __builtin_amdgcn_s_barrier();
       __asm__ volatile("" ::: "memory");
