@@ -133,10 +133,22 @@ __device__ __forceinline__ int level_of_block(const LevelBlocks& lb, int64_t b) 
 // lmax[l] by one atomicMax on the bits (non-negative floats order as their
 // bits; a maximum is exact in any order).
 constexpr int64_t kLevelMaxGroups = 1024;
+constexpr int kMaxColf = 192;  // >= 32 k steps of 32 at the largest p (12), >= its mstride
+static_assert(kMaxColf >= 32 * m2lb_ksteps(13 * 13) && kMaxColf >= mstride_of(13 * 13), "column factors fit");
 __global__ void k_f16_level_max(const float* __restrict__ m32, int ms, int nc,
                                 const float* __restrict__ colf, LevelBlocks lb,
                                 uint32_t* __restrict__ lmax) {
   __shared__ float sm[kBlock / 64];
+  __shared__ float4 sc4[kMaxColf / 4];  // the column factors, zero past ncoef
+  for (int k4 = threadIdx.x; k4 < ms / 4; k4 += kBlock) {
+    float4 c;
+    c.x = 4 * k4 < nc ? colf[4 * k4] : 0.f;
+    c.y = 4 * k4 + 1 < nc ? colf[4 * k4 + 1] : 0.f;
+    c.z = 4 * k4 + 2 < nc ? colf[4 * k4 + 2] : 0.f;
+    c.w = 4 * k4 + 3 < nc ? colf[4 * k4 + 3] : 0.f;
+    sc4[k4] = c;
+  }
+  __syncthreads();
   const int l = level_of_block(lb, blockIdx.x);
   const int64_t ngrp = lb.blk_off[l + 1] - lb.blk_off[l];
   const int64_t n4 = (lb.box_off[l + 1] - lb.box_off[l]) * ms / 4;
@@ -148,10 +160,8 @@ __global__ void k_f16_level_max(const float* __restrict__ m32, int ms, int nc,
   int k = (int)((4 * t0) % ms);
   for (int64_t t = t0; t < n4; t += stride) {
     const float4 v = v4[t];
-    if (k < nc) m = fmaxf(m, fabsf(v.x * colf[k]));
-    if (k + 1 < nc) m = fmaxf(m, fabsf(v.y * colf[k + 1]));
-    if (k + 2 < nc) m = fmaxf(m, fabsf(v.z * colf[k + 2]));
-    if (k + 3 < nc) m = fmaxf(m, fabsf(v.w * colf[k + 3]));
+    const float4 c = sc4[k >> 2];
+    m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x * c.x), fabsf(v.y * c.y)), fmaxf(fabsf(v.z * c.z), fabsf(v.w * c.w))));
     k += kinc;
     if (k >= ms) k -= ms;
   }
@@ -183,6 +193,9 @@ __device__ __forceinline__ int f16_level_exp(uint32_t lmax_bits) {
 __global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, int kst, int lpb,
                                const float* __restrict__ colf, LevelBlocks lb,
                                const uint32_t* __restrict__ lmax, u32x4* __restrict__ out) {
+  __shared__ float sColf[kMaxColf];  // the column factors, zero past ncoef
+  for (int k = threadIdx.x; k < 32 * kst && k < kMaxColf; k += blockDim.x) sColf[k] = k < nc ? colf[k] : 0.f;
+  __syncthreads();
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int sh = lpb == 16 ? 4 : 5;  // lpb is 16 or 32
   const int64_t box = lb.box_off[lb.l0] + (t >> sh);
@@ -202,7 +215,7 @@ __global__ void k_split_mult_h(const float* __restrict__ m32, int ms, int nc, in
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int k = 8 * u + j;
-    split_f16_f32(k < nc ? x[j] * colf[k] * sc : 0.f, pc[j]);
+    split_f16_f32(k < nc ? x[j] * sColf[k] * sc : 0.f, pc[j]);
   }
   u32x4 q[2];
   pack_quads<2>(pc, q);
