@@ -500,8 +500,11 @@ __global__ void k_p2p_worklist(int64_t nbox, const uint8_t* __restrict__ bucket,
 // kGroupTile) as offsets from P's centre in leaf units, leaf by leaf; each
 // target reads the 27 leaves around its own from the per-leaf table.  With at
 // most 32 targets, lanes t and t + 32 share a target, taking neighbour leaves
-// 0..13 and 14..26, combined by one xor shuffle.
-constexpr int kGroupTile = 512;
+// 0..13 and 14..26, combined by one xor shuffle.  Tiles of 256 sources (8 KB
+// of LDS in mixed mode) leave the occupancy to the registers (4 waves per
+// SIMD); tiles of 512 held all 64 leaves of a typical block at once but
+// limited it to 9 waves per CU: 0.37 -> 0.26 ms at 2^20 charges, depth 6.
+constexpr int kGroupTile = 256;
 template <typename T>
 __global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p_group(
     int L, const uint32_t* __restrict__ start, const uint32_t* __restrict__ c2s,
