@@ -178,9 +178,10 @@ fmm_status fmm_replan(fmm_plan_t *plan, const double *d_pos, fmm_stream_t stream
  *     persistent launch of two work-groups per CU, those of each XCD taking
  *     the XCD's tiles in order from a counter; no tile is split, so results
  *     equal bitwise those of FMM_SCHED_M2L_SPLIT 0 (which it overrides).
- *   FMM_SCHED_P2P_TILE: 128, 256 (default) or 512: sources a P2P wave stages
- *     in LDS at a time (the per-leaf kernels; the uniform tree's kernel for
- *     small leaves keeps its own).  Results are bitwise the same.
+ *   FMM_SCHED_P2P_TILE: 128, 256 or 512 (default 128 in mixed precision, 256
+ *     in FP64): sources a P2P wave stages in LDS at a time (the per-leaf
+ *     kernels; the uniform tree's kernel for small leaves keeps its own).
+ *     Results are bitwise the same.
  * Kept by fmm_replan.  Errors: FMM_E_INVALID_ARG (plan NULL, unknown key or
  * value out of range), FMM_E_UNSUPPORTED. */
 enum {

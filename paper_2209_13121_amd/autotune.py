@@ -32,7 +32,7 @@ SPLIT_KINDS = ("F16X2", "BF16X3", "BF16X2")
 SCHEDULES = {"p2p_persistent": (0, 1), "m2l_split": (16, 8, 0)}
 _SCHED_KEY = {"p2p_persistent": B.FMM_SCHED_P2P_PERSISTENT, "m2l_split": B.FMM_SCHED_M2L_SPLIT,
               "m2l_persistent": B.FMM_SCHED_M2L_PERSISTENT, "p2p_tile": B.FMM_SCHED_P2P_TILE}
-P2P_TILES = (256, 128, 512)  # sources per staged P2P tile; the first is the default
+P2P_TILES = (128, 256, 512)  # sources per staged P2P tile; the first is the mixed default
 WIDE_PMAX = 8  # the FP16 form's persistent M2L runs up to this order
 
 
@@ -145,6 +145,6 @@ def tune(pos, q, p, trees, kinds=KINDS, lo=(0.0, 0.0, 0.0), side=1.0, batch_leve
     best = select(results, gate_e, gate_f)
     # then the P2P tile of the best candidate (adaptive trees: the per-leaf kernels)
     if search_schedules and best is not None and best.tree.get("leaf_max", 0) > 0:
-        run(best.tree, best.kind, [dict(best.schedule, p2p_tile=t) for t in P2P_TILES if t != 256])
+        run(best.tree, best.kind, [dict(best.schedule, p2p_tile=t) for t in P2P_TILES[1:]])
         best = select(results, gate_e, gate_f)
     return best, results

@@ -239,7 +239,9 @@ fmm_status plan_into(fmm_plan_s* P, const fmm_config& cfg, const Layout& lay, in
   const int p2p_persistent = keep_operators ? P->p2p_persistent : 0;
   const int m2l_split = keep_operators ? P->m2l_split : kM2lSplitPerXcd;
   const int m2l_persistent = keep_operators ? P->m2l_persistent : 0;
-  const int p2p_tile = keep_operators ? P->p2p_tile : 256;
+  // P2P tile: 128 sources in mixed precision (the occupancy stays with the
+  // registers), 256 in FP64
+  const int p2p_tile = keep_operators ? P->p2p_tile : (cfg.precision == FMM_PREC_MIXED ? 128 : 256);
   memset(P, 0, sizeof(*P));
   P->p2p_tile = p2p_tile;
   P->p2p_persistent = p2p_persistent;

@@ -40,7 +40,7 @@
 namespace fmm {
 namespace {
 
-constexpr int kTile = 256;   // sources per staged tile (default; FMM_SCHED_P2P_TILE)
+constexpr int kTile = 256;   // sources per staged tile (FMM_SCHED_P2P_TILE: 128, 256, 512)
 constexpr int kNbBatch = 64;  // neighbour leaves handled per batch (one per lane)
 constexpr int kKMax = 4;      // targets per lane of a large leaf (groups of 64 kKMax targets)
 // occupancy the register budget is held to: FP32 4 waves per SIMD (128 VGPRs),

@@ -112,7 +112,7 @@ def test_schedules_give_the_same_result(prec):
     assert f.check() == 0
     for x, y, z in zip(a, b, c):
         assert torch.equal(x, y) and torch.equal(x, z)
-    for tile in (128, 512):  # the P2P tile: the same sums in the same order
+    for tile in (128, 256, 512):  # the P2P tile: the same sums in the same order
         B.fmm_plan_set_schedule(f.plan, B.FMM_SCHED_P2P_TILE, tile)
         d = f.evaluate(tq)
         for x, y in zip(a, d):
