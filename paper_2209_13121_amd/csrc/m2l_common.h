@@ -206,13 +206,43 @@ struct TileT {
       const int64_t idx = lg - a.group_off[l];
       pi = (int)(idx % 8);
       tile = idx / 8;
+    }
+    if constexpr (AD) return true;  // no halo, the source rows come from the table
+    const int px = (pi >> 2) & 1, py = (pi >> 1) & 1, pz = pi & 1;
+    if constexpr (!SPLIT) {
       nb = 1 << l;
       lvl_off = a.exp_off[l];
       dense_off = a.lvl_off[l];
       retarget(a, tix);
-      stage_halo(a, sSlot, sBox);
-      return true;
     }
+    const int tid = threadIdx.x;
+    if (tid < 6) sBox[tid] = tid < 3 ? nb : -1;
+    __syncthreads();
+    if (col_ok) {
+      atomicMin(&sBox[0], tx - px - 2);
+      atomicMin(&sBox[1], ty - py - 2);
+      atomicMin(&sBox[2], tz - pz - 2);
+      atomicMax(&sBox[3], tx - px + 3);
+      atomicMax(&sBox[4], ty - py + 3);
+      atomicMax(&sBox[5], tz - pz + 3);
+    }
+    __syncthreads();
+    hx0 = sBox[0] < 0 ? 0 : sBox[0];
+    hy0 = sBox[1] < 0 ? 0 : sBox[1];
+    hz0 = sBox[2] < 0 ? 0 : sBox[2];
+    hx1 = sBox[3] >= nb ? nb - 1 : sBox[3];
+    hy1 = sBox[4] >= nb ? nb - 1 : sBox[4];
+    hz1 = sBox[5] >= nb ? nb - 1 : sBox[5];
+    hey = hy1 - hy0 + 1;
+    hez = hz1 - hz0 + 1;
+    const int hn = (hx1 - hx0 + 1) * hey * hez;  // <= kHalo by the bound above
+    const uint32_t* c2s = a.c2s + dense_off;
+    for (int e = tid; e < hn && e < kHalo; e += (int)blockDim.x) {
+      const int x = hx0 + e / (hey * hez), y = hy0 + (e / hez) % hey, z = hz0 + e % hez;
+      sSlot[e] = c2s[lex_index(x, y, z, l)];
+    }
+    __syncthreads();
+    return true;
   }
 
   // setup for logical group lg given by the caller (part pt, split index si;
