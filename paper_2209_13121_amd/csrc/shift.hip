@@ -32,6 +32,13 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
+// 16-byte operator loads a thread has in flight while staging rows in LDS:
+// the loads of a batch are all issued before its first LDS store, so a
+// staging pass costs a memory round trip per batch, not per load.
+constexpr int kStageBatch = 8;
+// s_waitcnt operand: vector memory count 0, the other counters unconstrained
+// (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
+constexpr int kVmcntZero = 0x0F70;
 
 template <int P, int MODE>
 struct ShiftShape {
@@ -46,6 +53,10 @@ struct ShiftShape {
   static constexpr int OCT_STAGE = NOCT * 16 * RS * 16 <= 150 * 1024 ? NOCT : NOCT / 2;
   static_assert(RS % 4 == 2 && RS >= KP / 2, "LDS row stride");
 };
+// LDS units (16 bytes) of the all-rows form: every row of one octant, in
+// whole wave copies of 64 units
+template <int P>
+constexpr int kRowsUnits = ((ShiftShape<P, 0>::RB * 16 * ShiftShape<P, 0>::RS + 63) / 64) * 64;
 
 // Degree of packed coefficient index c (c = n^2 .. n^2 + 2n).
 __device__ __forceinline__ int degree_of(int c) {
@@ -130,11 +141,24 @@ __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
     // stage rows row0..row0+15, pairs q0..q1-1, of octants o0.. (M2M) or oct_l2l (L2L)
     if (o0 > 0) __syncthreads();
     const int npair = q1 - q0;  // 16-byte units per row = 4 per pair
-    for (int e = tid; e < OCT_STAGE * 16 * 4 * npair; e += kThreads) {
-      const int u = e % (4 * npair), r = e / (4 * npair) % 16, oo = e / (4 * npair * 16);
-      const int oct = MODE == 0 ? o0 + oo : oct_l2l;
-      sA[(oo * 16 + r) * RS + 4 * q0 + u] = *reinterpret_cast<const f64x2*>(
-          a.ops + ((size_t)oct * (RB * 16) + row0 + r) * KP + 8 * q0 + 2 * u);
+    const int ne = OCT_STAGE * 16 * 4 * npair;
+    for (int e0 = 0; e0 < ne; e0 += kStageBatch * kThreads) {
+      f64x2 st[kStageBatch];  // every load of the batch in flight before the first store
+#pragma unroll
+      for (int i = 0; i < kStageBatch; ++i) {
+        const int e = e0 + tid + i * kThreads;
+        const int u = e % (4 * npair), r = e / (4 * npair) % 16, oo = e / (4 * npair * 16);
+        const int oct = MODE == 0 ? o0 + oo : oct_l2l;
+        if (e < ne)
+          st[i] = *reinterpret_cast<const f64x2*>(a.ops + ((size_t)oct * (RB * 16) + row0 + r) * KP +
+                                                  8 * q0 + 2 * u);
+      }
+#pragma unroll
+      for (int i = 0; i < kStageBatch; ++i) {
+        const int e = e0 + tid + i * kThreads;
+        const int u = e % (4 * npair), r = e / (4 * npair) % 16, oo = e / (4 * npair * 16);
+        if (e < ne) sA[(oo * 16 + r) * RS + 4 * q0 + u] = st[i];
+      }
     }
     __syncthreads();
     // B pairs of octant oct: unconditional loads at clamped addresses (so
@@ -238,7 +262,7 @@ template <int P, int MODE>
 __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
   typedef ShiftShape<P, MODE> S;
   constexpr int NC = S::NC, RB = S::RB, MS = S::MS, KP = S::KP, NQ = S::NQ, RS = S::RS;
-  __shared__ f64x2 sA[RB * 16 * RS];
+  __shared__ f64x2 sA[kRowsUnits<P>];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
@@ -292,14 +316,21 @@ __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
   for (int o = 0; o < NOCT; ++o) {
     const int oct = MODE == 0 ? o : oct_l2l;
     if (o > 0) __syncthreads();  // the previous octant's rows are no longer read
-    // stage every row of octant oct, the k pairs of its row block only
-    for (int e = tid; e < RB * 16 * 4 * NQ; e += kThreads) {
-      const int u = e % (4 * NQ), row = e / (4 * NQ), q = u / 4;
+    // stage every row of octant oct, the k pairs of its row block only, by DMA
+    // from global memory into LDS, 64 units per wave instruction: LDS unit e
+    // is row e / RS, 16-byte unit e % RS; units outside the block's k pairs
+    // (never read) fetch the row's first unit.
+    for (int e0 = wave * 64; e0 < kRowsUnits<P>; e0 += kThreads) {
+      const int e = e0 + lane;
+      const int row = e / RS < RB * 16 ? e / RS : 0, u = e % RS, q = u / 4;
       int q0, q1;
       qrange(row / 16, q0, q1);
-      if (q >= q0 && q < q1)
-        sA[row * RS + u] = *reinterpret_cast<const f64x2*>(a.ops + ((size_t)oct * (RB * 16) + row) * KP + 2 * u);
+      const bool v = u < 4 * NQ && q >= q0 && q < q1;
+      __builtin_amdgcn_global_load_lds(
+          (__attribute__((address_space(1))) void*)(a.ops + ((size_t)oct * (RB * 16) + row) * KP + (v ? 2 * u : 0)),
+          (__attribute__((address_space(3))) void*)(sA + e0), 16, 0, 0);
     }
+    __builtin_amdgcn_s_waitcnt(kVmcntZero);  // this wave's copies have landed
     __syncthreads();
     if (MODE == 0 && o + 1 < NOCT) load_b(o + 1, bnext);  // next octant in flight
 #pragma unroll
