@@ -312,6 +312,22 @@ __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
   for (int r = 0; r < RB; ++r) acc0[r] = acc1[r] = f64x4{0, 0, 0, 0};
   f64x2 bcur[NQ], bnext[NQ];
   load_b(MODE == 0 ? 0 : oct_l2l, bcur);
+  const int64_t cs = MODE == 1 && ok ? 8 * ps + child_of(oct_l2l) : 0;
+  if (MODE == 1 && ok) {
+    // L2L: the child's (1/h) M2L result starts the accumulators (lane (col,
+    // kg) holds rows 16 rb + kg + 4 i of its column), so its loads are in
+    // flight while the operator rows are staged
+    const double inv_h = (double)(1 << a.l) / a.dp->side;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * rb + kg + 4 * i;
+        if (row < NC)
+          acc0[rb][i] = inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + row]
+                                         : static_cast<const double*>(a.m2l)[cs * NC + row]);
+      }
+  }
   constexpr int NOCT = MODE == 0 ? 8 : 1;
   for (int o = 0; o < NOCT; ++o) {
     const int oct = MODE == 0 ? o : oct_l2l;
@@ -352,8 +368,6 @@ __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
     }
   }
   if (!ok) return;
-  const int64_t cs = MODE == 1 ? 8 * ps + child_of(oct_l2l) : 0;
-  const double inv_h = MODE == 1 ? (double)(1 << a.l) / a.dp->side : 0.0;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
     const f64x4 acc = acc0[rb] + acc1[rb];
@@ -380,11 +394,6 @@ __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
         *reinterpret_cast<f32x4*>(a.dst32 + prow * MS + rr) =
             f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
     } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (rr + j < NC)
-          v[j] += inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + rr + j]
-                                   : static_cast<const double*>(a.m2l)[cs * NC + rr + j]);
       if (!(a.leaf && a.mixed)) {
         *reinterpret_cast<f64x2*>(a.dst64 + cs * MS + rr) = f64x2{v[0], v[1]};
         *reinterpret_cast<f64x2*>(a.dst64 + cs * MS + rr + 2) = f64x2{v[2], v[3]};
