@@ -303,7 +303,13 @@ __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
     for (int q = 0; q < NQ; ++q) {
       const int k = 8 * q + 2 * kg;
       const int k0 = k < MS ? k : MS - 2;
-      const f64x2 v = *reinterpret_cast<const f64x2*>(static_cast<const double*>(a.src) + srow * MS + k0);
+      f64x2 v;
+      if (MODE == 0 && a.mixed) {  // FP32 children (the uniform tree's mixed leaves)
+        const f32x2 w = *reinterpret_cast<const f32x2*>(static_cast<const float*>(a.src) + srow * MS + k0);
+        v = f64x2{(double)w[0], (double)w[1]};
+      } else {
+        v = *reinterpret_cast<const f64x2*>(static_cast<const double*>(a.src) + srow * MS + k0);
+      }
       bv[q] = (ok && k < MS) ? v : f64x2{0.0, 0.0};
     }
   };
@@ -461,11 +467,15 @@ hipError_t launch_m2m(fmm_plan_s* P, hipStream_t s) {
   for (int l = P->L - 1; l >= 2; --l) {
     ShiftArgs a = {};
     a.l = l;
-    a.mixed = 0;  // every multipole, the leaves' included, is kept in FP64
+    // mixed: the leaf multipoles exist in FP32 only (the P2M pass sums them in
+    // FP64 and rounds once); every level above is kept in FP64 as well
+    const bool leaf32 = m32 && l == P->L - 1;
+    a.mixed = leaf32 ? 1 : 0;
     a.nparent = (int64_t)1 << (3 * l);
     a.s2c_child = wsp<uint32_t>(P, lay.slot2coord) + lay.lvl_off[l + 1];
     a.ops = wsp<double>(P, lay.op_m2m);
-    a.src = m64 + lay.lvl_off[l + 1] * ms;
+    a.src = leaf32 ? static_cast<const void*>(m32 + lay.lvl_off[l + 1] * ms)
+                   : static_cast<const void*>(m64 + lay.lvl_off[l + 1] * ms);
     a.dst64 = m64 + lay.lvl_off[l] * ms;
     a.dst32 = m32 ? m32 + lay.lvl_off[l] * ms : nullptr;
     a.dp = wsp<DevParams>(P, lay.params);

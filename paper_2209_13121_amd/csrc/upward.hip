@@ -3,12 +3,14 @@
 //
 // P2M: M~_n^m = sum_j q_j conj(R_n^m(u_j)) with u_j the box-unit offset of
 // particle j from its leaf centre (computed by the tree pass), accumulated in
-// FP64 in both precision modes from the FP64 offsets; the mixed mode also
-// stores the result rounded to FP32 for the M2L pass.  (An FP32 sum of
-// neutral clusters of charges, one cluster after another, rounds every cluster's
-// partial sums the same way, so the leaf monopoles would drift by an amount
-// proportional to the particle count: a smooth, density-shaped error charge.
-// FP64 adds cost the same issue slots as FP32 ones here.)
+// FP64 in both precision modes from the FP64 offsets.  (An FP32 sum of
+// neutral clusters of charges, one cluster after another, rounds every
+// cluster's partial sums the same way, so the leaf monopoles would drift by an
+// amount proportional to the particle count: a smooth, density-shaped error
+// charge.  FP64 adds cost the same issue slots as FP32 ones here.)  The mixed
+// mode stores the sum rounded to FP32 only, read by the M2L pass and,
+// converted back, by the M2M pass: one rounding of the final value, with no
+// drift.
 // M2M (shift.hip): M~p = sum over the 8 children of A[octant] M~c with the
 // level-free octant matrices, always in FP64; in the mixed mode each parent is
 // also stored rounded to FP32 for the M2L pass.
@@ -58,9 +60,11 @@ __global__ __launch_bounds__(kBlock) void k_p2m(const uint32_t* __restrict__ sta
       }
     }
   }
-  T* out = mult + leaf * MS;
+  if (mult) {
+    T* out = mult + leaf * MS;
 #pragma unroll
-  for (int c = 0; c < MS; ++c) out[c] = c < NC ? acc[c] : T(0);
+    for (int c = 0; c < MS; ++c) out[c] = c < NC ? acc[c] : T(0);
+  }
   if (mult32) {
     float* o32 = mult32 + leaf * MS;
 #pragma unroll
@@ -75,7 +79,8 @@ struct P2MRun {
     const int64_t nleaf = lay.nleaf, row0 = lay.lvl_off[Pl->L] * mstride(Pl->p);
     k_p2m<P><<<grid_for(nleaf, 64), 64, 0, s>>>(
         wsp<uint32_t>(Pl, lay.leaf_start), wsp<Rec<double>>(Pl, Pl->mixed ? lay.src64 : lay.src), nleaf,
-        wsp<double>(Pl, lay.mult64) + row0, Pl->mixed ? wsp<float>(Pl, lay.mult32) + row0 : nullptr);
+        Pl->mixed ? nullptr : wsp<double>(Pl, lay.mult64) + row0,
+        Pl->mixed ? wsp<float>(Pl, lay.mult32) + row0 : nullptr);
     return hipGetLastError();
   }
 };
