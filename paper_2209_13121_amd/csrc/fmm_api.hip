@@ -63,6 +63,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   // scan scratch: block sums of every level of the recursive scan, for the
   // longest scan (leaf counts; adaptive: also the dense box flags and lists)
   int64_t longest = lay->nleaf + 1;
+  if (sort_two_level(L)) longest = std::max(longest, sort_hist_elems(n));
   if (adaptive) longest = std::max(longest, std::max(lay->nbox + 1, lay->bmax + 1));
   int64_t tmp = 0, m = longest;
   while (m > 1) {
@@ -89,6 +90,7 @@ bool make_layout(const fmm_config& cfg, int64_t n, Layout* lay) {
   lay->perm = take(sizeof(int32_t) * N);
   lay->perm_tmp = take(sizeof(int32_t) * N);
   lay->sorted_leaf = take(sizeof(uint32_t) * N);
+  lay->sort_hist = sort_two_level(L) ? take(sizeof(uint32_t) * (size_t)sort_hist_elems(n)) : 0;
   lay->leaf_count = take(sizeof(uint32_t) * NL);
   lay->leaf_start = take(sizeof(uint32_t) * (NL + 1));
   lay->leaf_fill = take(sizeof(uint32_t) * NL);

@@ -10,6 +10,14 @@
 namespace fmm {
 
 constexpr int kBlock = 256;          // default work-group size (4 wave64)
+// Leaf sort of the uniform tree (3 <= L <= 7): particles per work-group of
+// the coarse pass, and the coarse digit's 512 values (the key's top 9 bits)
+constexpr int kSortChunk = 4 * kBlock;
+constexpr int kSortCoarse = 512;
+inline bool sort_two_level(int L) { return L >= 3 && L <= 7; }
+inline int64_t sort_hist_elems(int64_t n) {
+  return (int64_t)kSortCoarse * ((n + kSortChunk - 1) / kSortChunk) + 1;
+}
 constexpr int kNumM2LOps = 316;      // offsets in [-3,3]^3 \ [-1,1]^3
 constexpr int kIL = 189;             // interaction-list offsets per parity class
 // Split M2L (split forms): at most this many work-groups per XCD, the
@@ -157,6 +165,7 @@ inline size_t zero_row_bytes(int p, int np) {
 struct Layout {  // byte offsets into the workspace, every one 256-aligned
   size_t params, flags, energy_part, bbox, zero_row;
   size_t keys, perm, perm_tmp, sorted_leaf;
+  size_t sort_hist;        // leaf sort: per-block counts of the coarse key digit, then their offsets
   size_t leaf_count, leaf_start, leaf_fill, scan_tmp;
   size_t coord2slot, slot2coord;
   size_t src;              // particle records {u_x, u_y, u_z, q} in the compute precision

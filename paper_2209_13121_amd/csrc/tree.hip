@@ -2,9 +2,10 @@
 //
 // Per particle: leaf cell of the root cube (FP64, correctly rounded division,
 // floor, clamp), validity flags, 3L-bit Hilbert key.  A counting sort over the
-// 8^L leaf slots (histogram, exclusive scan, scatter) puts particles in Hilbert
-// order; a per-leaf rank by user index makes the order inside each leaf, and so
-// every later summation order, deterministic.  Per level, maps between box
+// 8^L leaf slots puts particles in Hilbert order: for 3 <= L <= 7 in two levels
+// with LDS counters only (k_keys_hist .. k_fine), otherwise in one (histogram by
+// global atomics, exclusive scan, scatter); a per-leaf rank by user index makes
+// the order inside each leaf, and so every later summation order, deterministic.  Per level, maps between box
 // coordinates and Hilbert slots give neighbour lookups; a box's Hilbert slot at
 // level l is the top 3l bits of the leaf key of any of its cells, so children of
 // slot s are slots 8s .. 8s+7 and every box owns a contiguous range of leaves.
@@ -132,6 +133,109 @@ __global__ void k_keys(const double* __restrict__ pos, int64_t n, int L, int che
   const uint32_t key = (uint32_t)hilbert_index(cx, cy, cz, L);
   keys[i] = key;
   atomicAdd(&count[key], 1u);
+}
+
+// Two-level counting sort of the leaf keys (3 <= L <= 7), with no global
+// atomics: the coarse digit c = key >> (3L - 9) (the level-3 box) and the fine
+// digit f = the key's low 3L - 9 bits (the leaf inside it).
+//  1. k_keys_hist: keys as k_keys, and each work-group's count of every coarse
+//     value (LDS atomics) at hist[c * nblk + block];
+//  2. an exclusive scan of hist (coarse value major): the first position of
+//     each (coarse value, work-group) pair;
+//  3. k_coarse_scatter: each particle to its pair's range (LDS atomics give
+//     positions within the work-group), key and index;
+//  4. k_fine: one work-group per coarse value counts its fine digits in LDS,
+//     scans them into the leaf counts and starts, and places each particle in
+//     its leaf's range.
+// The order inside a leaf is then arbitrary, as after k_scatter, and k_rank
+// sorts it by user index: the tree is the same as the one-level sort's.
+__global__ __launch_bounds__(kBlock) void k_keys_hist(const double* __restrict__ pos, int64_t n, int L,
+                                                      int check_cube, const DevParams* __restrict__ dp,
+                                                      uint32_t* __restrict__ keys, int32_t* flags,
+                                                      uint32_t* __restrict__ hist, int64_t nblk) {
+  __shared__ uint32_t h[kSortCoarse];
+  for (int c = threadIdx.x; c < kSortCoarse; c += kBlock) h[c] = 0;
+  __syncthreads();
+  const int sh = 3 * L - 9;
+  const double side = dp->side;
+  int32_t flag = 0;
+  for (int r = 0; r < kSortChunk / kBlock; ++r) {
+    const int64_t i = (int64_t)blockIdx.x * kSortChunk + r * kBlock + threadIdx.x;
+    if (i >= n) break;
+    const int cx = leaf_cell(pos[3 * i + 0], dp->lo[0], side, L, check_cube, flag);
+    const int cy = leaf_cell(pos[3 * i + 1], dp->lo[1], side, L, check_cube, flag);
+    const int cz = leaf_cell(pos[3 * i + 2], dp->lo[2], side, L, check_cube, flag);
+    const uint32_t key = (uint32_t)hilbert_index(cx, cy, cz, L);
+    keys[i] = key;
+    atomicAdd(&h[key >> sh], 1u);
+  }
+  if (flag) atomicOr(flags, flag);
+  __syncthreads();
+  for (int c = threadIdx.x; c < kSortCoarse; c += kBlock) hist[(int64_t)c * nblk + blockIdx.x] = h[c];
+}
+
+__global__ __launch_bounds__(kBlock) void k_coarse_scatter(const uint32_t* __restrict__ keys, int64_t n, int L,
+                                                           const uint32_t* __restrict__ off, int64_t nblk,
+                                                           uint32_t* __restrict__ key_tmp,
+                                                           int32_t* __restrict__ idx_tmp) {
+  __shared__ uint32_t base[kSortCoarse];
+  for (int c = threadIdx.x; c < kSortCoarse; c += kBlock) base[c] = off[(int64_t)c * nblk + blockIdx.x];
+  __syncthreads();
+  const int sh = 3 * L - 9;
+  for (int r = 0; r < kSortChunk / kBlock; ++r) {
+    const int64_t i = (int64_t)blockIdx.x * kSortChunk + r * kBlock + threadIdx.x;
+    if (i >= n) break;
+    const uint32_t key = keys[i];
+    const uint32_t at = atomicAdd(&base[key >> sh], 1u);
+    key_tmp[at] = key;
+    idx_tmp[at] = (int32_t)i;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fine(int64_t n, int L, const uint32_t* __restrict__ off, int64_t nblk,
+                                                 const uint32_t* __restrict__ key_tmp,
+                                                 const int32_t* __restrict__ idx_tmp,
+                                                 uint32_t* __restrict__ count, uint32_t* __restrict__ start,
+                                                 int32_t* __restrict__ perm_tmp) {
+  __shared__ uint32_t cnt[1 << 12];  // fine values: 2^(3L - 9) <= 4096
+  __shared__ uint32_t ssum[kBlock];
+  const int tid = threadIdx.x;
+  const int64_t c = blockIdx.x;
+  const int fb = 1 << (3 * L - 9);
+  const uint32_t b0 = off[c * nblk], b1 = off[(c + 1) * nblk];
+  for (int f = tid; f < fb; f += kBlock) cnt[f] = 0;
+  __syncthreads();
+  for (uint32_t j = b0 + tid; j < b1; j += kBlock) atomicAdd(&cnt[key_tmp[j] & (uint32_t)(fb - 1)], 1u);
+  __syncthreads();
+  // exclusive scan of cnt: a chunk of consecutive values per thread, the
+  // chunk sums scanned across the work-group
+  const int per = (fb + kBlock - 1) / kBlock;
+  const int f0 = min(fb, tid * per), f1 = min(fb, f0 + per);
+  uint32_t mine = 0;
+  for (int f = f0; f < f1; ++f) mine += cnt[f];
+  ssum[tid] = mine;
+  __syncthreads();
+  for (int w = 1; w < kBlock; w <<= 1) {
+    const uint32_t add = tid >= w ? ssum[tid - w] : 0u;
+    __syncthreads();
+    ssum[tid] += add;
+    __syncthreads();
+  }
+  uint32_t run = b0 + ssum[tid] - mine;
+  const int64_t leaf0 = c * fb;
+  for (int f = f0; f < f1; ++f) {
+    const uint32_t k = cnt[f];
+    count[leaf0 + f] = k;
+    start[leaf0 + f] = run;
+    cnt[f] = run;  // now the next free position of leaf f
+    run += k;
+  }
+  if (c == kSortCoarse - 1 && tid == 0) start[(int64_t)kSortCoarse * fb] = (uint32_t)n;
+  __syncthreads();
+  for (uint32_t j = b0 + tid; j < b1; j += kBlock) {
+    const uint32_t at = atomicAdd(&cnt[key_tmp[j] & (uint32_t)(fb - 1)], 1u);
+    perm_tmp[at] = idx_tmp[j];
+  }
 }
 
 // Exclusive scan, 1024 elements per block of 256 threads; elements at index
@@ -354,20 +458,35 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
     k_bbox_partial<<<nparts, kBlock, 0, s>>>(d_pos, n, part);
     k_bbox_final<<<1, kBlock, 0, s>>>(part, nparts, dp, flags);
   }
-  k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(count, lay.nleaf, 0u);
   {  // the zero row M2L reads for sources outside the domain
     const int64_t words = (int64_t)(zero_row_bytes(P->p, P->m2l_np) / 4);
     k_fill_u32<<<grid_for(words, kBlock), kBlock, 0, s>>>(wsp<uint32_t>(P, lay.zero_row), words, 0u);
   }
-  k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(fill, lay.nleaf, 0u);
   k_luts<<<grid_for(lay.nbox, kBlock), kBlock, 0, s>>>(L, lay.nbox, lay, c2s, s2c);
-  k_keys<<<grid_for(n, kBlock), kBlock, 0, s>>>(d_pos, n, L, given ? 1 : 0, dp, keys, count, flags);
-  hipError_t e = scan_exclusive(count, lay.nleaf, lay.nleaf + 1, start,
-                                wsp<uint32_t>(P, lay.scan_tmp), s);
-  if (e != hipSuccess) return e;
   int32_t* perm_tmp = wsp<int32_t>(P, lay.perm_tmp);
   int32_t* perm = wsp<int32_t>(P, lay.perm);
-  k_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(keys, n, start, fill, perm_tmp);
+  if (sort_two_level(L)) {
+    // key and index by coarse digit in the sorted-leaf array and the
+    // permutation (both written again below)
+    const int64_t nblk = (n + kSortChunk - 1) / kSortChunk;
+    uint32_t* hist = wsp<uint32_t>(P, lay.sort_hist);
+    uint32_t* key_tmp = wsp<uint32_t>(P, lay.sorted_leaf);
+    k_keys_hist<<<(unsigned)nblk, kBlock, 0, s>>>(d_pos, n, L, given ? 1 : 0, dp, keys, flags, hist, nblk);
+    const int64_t nh = sort_hist_elems(n);  // the last element (0) becomes the total
+    k_fill_u32<<<1, 1, 0, s>>>(hist + nh - 1, 1, 0u);
+    hipError_t e = scan_exclusive(hist, nh, nh, hist, wsp<uint32_t>(P, lay.scan_tmp), s);
+    if (e != hipSuccess) return e;
+    k_coarse_scatter<<<(unsigned)nblk, kBlock, 0, s>>>(keys, n, L, hist, nblk, key_tmp, perm);
+    k_fine<<<kSortCoarse, kBlock, 0, s>>>(n, L, hist, nblk, key_tmp, perm, count, start, perm_tmp);
+  } else {
+    k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(count, lay.nleaf, 0u);
+    k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(fill, lay.nleaf, 0u);
+    k_keys<<<grid_for(n, kBlock), kBlock, 0, s>>>(d_pos, n, L, given ? 1 : 0, dp, keys, count, flags);
+    hipError_t e = scan_exclusive(count, lay.nleaf, lay.nleaf + 1, start,
+                                  wsp<uint32_t>(P, lay.scan_tmp), s);
+    if (e != hipSuccess) return e;
+    k_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(keys, n, start, fill, perm_tmp);
+  }
   k_rank<<<grid_for(n, kBlock), kBlock, 0, s>>>(perm_tmp, keys, n, start, count, perm);
   if (P->adaptive) {
     // leaves and box-unit offsets come from the adaptive tree (adaptive.hip)
