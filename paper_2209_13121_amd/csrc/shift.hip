@@ -249,6 +249,136 @@ __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
   }
 }
 
+// Coarse M2M levels (few parents): the 8 waves of a work-group take the 8
+// octants of one 16-row block for NT column tiles of 16 parents, so a level
+// spreads over (parents / 16 NT) x RB work-groups instead of k_shift's
+// (parents / 128) x RB, each wave running NT octant products instead of 8.
+// The octant partials of every column are then added in octant order through
+// LDS (the staged rows' space).  For p with all 8 octants' rows in LDS.
+template <int P, int NT>
+__global__ __launch_bounds__(kThreads) void k_shift_oct(ShiftArgs a) {
+  typedef ShiftShape<P, 0> S;
+  constexpr int NC = S::NC, RB = S::RB, MS = S::MS, KP = S::KP, NQ = S::NQ, RS = S::RS;
+  static_assert(S::OCT_STAGE == 8, "every octant's rows staged at once");
+  // 16-byte LDS units: the staged rows, then the partials (8 NT tiles of 64
+  // lanes x 32 bytes)
+  constexpr int kUnits = 8 * 16 * RS > 8 * NT * 64 * 2 ? 8 * 16 * RS : 8 * NT * 64 * 2;
+  __shared__ f64x2 sA[kUnits];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, kg = lane >> 4;
+  const int64_t per_xcd = (a.ngroups + 7) / 8;
+  const int64_t g = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+  if (g >= a.ngroups) return;  // uniform over the work-group
+  const int rb = (int)(g % RB);
+  const int64_t pgroup = g / RB;
+  const int row0 = 16 * rb;
+  const int d = degree_of(min(row0 + 15, NC - 1));
+  const int q1 = ((d + 1) * (d + 1) + 7) / 8;  // k pairs the block can touch (lower in degree)
+
+  // stage rows row0 .. row0 + 15 of the 8 octants, pairs 0 .. q1 - 1
+  const int ne = 8 * 16 * 4 * q1;
+  for (int e0 = 0; e0 < ne; e0 += kStageBatch * kThreads) {
+    f64x2 st[kStageBatch];  // every load of the batch in flight before the first store
+#pragma unroll
+    for (int i = 0; i < kStageBatch; ++i) {
+      const int e = e0 + tid + i * kThreads;
+      const int u = e % (4 * q1), r = e / (4 * q1) % 16, oo = e / (4 * q1 * 16);
+      if (e < ne)
+        st[i] = *reinterpret_cast<const f64x2*>(a.ops + ((size_t)oo * (RB * 16) + row0 + r) * KP + 2 * u);
+    }
+#pragma unroll
+    for (int i = 0; i < kStageBatch; ++i) {
+      const int e = e0 + tid + i * kThreads;
+      const int u = e % (4 * q1), r = e / (4 * q1) % 16, oo = e / (4 * q1 * 16);
+      if (e < ne) sA[(oo * 16 + r) * RS + u] = st[i];
+    }
+  }
+
+  // this wave's octant: the child of each parent in that octant
+  const int oct = wave;
+  auto load_b = [&](int t, f64x2* bv) {
+    const int64_t ps = (pgroup * NT + t) * 16 + col;
+    const bool ok = ps < a.nparent;
+    int child = 0;
+    if (ok)
+      for (int c = 0; c < 8; ++c) {
+        int x, y, z;
+        unpack_coord(a.s2c_child[8 * ps + c], x, y, z);
+        if ((((x & 1) << 2) | ((y & 1) << 1) | (z & 1)) == oct) child = c;
+      }
+    const int64_t srow = ok ? 8 * ps + child : 0;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int k = 8 * q + 2 * kg;
+      const int k0 = k < MS ? k : MS - 2;
+      f64x2 v;
+      if (a.mixed) {  // FP32 children (the uniform tree's mixed leaves)
+        const f32x2 w = *reinterpret_cast<const f32x2*>(static_cast<const float*>(a.src) + srow * MS + k0);
+        v = f64x2{(double)w[0], (double)w[1]};
+      } else {
+        v = *reinterpret_cast<const f64x2*>(static_cast<const double*>(a.src) + srow * MS + k0);
+      }
+      bv[q] = (ok && k < MS) ? v : f64x2{0.0, 0.0};
+    }
+  };
+  f64x2 bcur[NQ], bnext[NQ];
+  load_b(0, bcur);
+  __syncthreads();
+  f64x4 part[NT];
+  const f64x2* sa = sA + (oct * 16 + col) * RS + kg;
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    if (t + 1 < NT) load_b(t + 1, bnext);  // the next tile's sources in flight
+    f64x4 acc0 = f64x4{0, 0, 0, 0}, acc1 = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      if (q >= q1) continue;  // uniform over the work-group
+      const f64x2 av = sa[4 * q];
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bcur[q][0], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bcur[q][1], acc1, 0, 0, 0);
+    }
+    part[t] = acc0 + acc1;
+    if (t + 1 < NT) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) bcur[q] = bnext[q];
+    }
+  }
+  // the octant partials through LDS, added in octant order by waves 0 .. NT - 1
+  __syncthreads();  // every wave is done with the staged rows
+  f64x4* sP = reinterpret_cast<f64x4*>(sA);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) sP[(wave * NT + t) * 64 + lane] = part[t];
+  __syncthreads();
+  if (wave >= NT) return;  // uniform over the wave
+  const int t = wave;
+  f64x4 acc = sP[t * 64 + lane];
+#pragma unroll
+  for (int o = 1; o < 8; ++o) acc += sP[(o * NT + t) * 64 + lane];
+  // transpose across the 4 lanes of a column (as in k_shift): this lane then
+  // holds rows 16 rb + 4 kg + j, j = 0..3
+  double v[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int i_send = (kg - r) & 3;
+    const double send = i_send == 0 ? acc[0] : i_send == 1 ? acc[1] : i_send == 2 ? acc[2] : acc[3];
+    const double got = __shfl(send, ((kg + r) & 3) * 16 + col);
+    const int j = (kg + r) & 3;
+    if (j == 0) v[0] = got;
+    if (j == 1) v[1] = got;
+    if (j == 2) v[2] = got;
+    if (j == 3) v[3] = got;
+  }
+  const int64_t ps = (pgroup * NT + t) * 16 + col;
+  const int rr = row0 + 4 * kg;  // MS % 4 == 0: all 4 rows or none < MS
+  if (ps >= a.nparent || rr >= MS) return;
+  const int64_t prow = a.parent_of ? (int64_t)a.parent_of[8 * ps] : ps;
+  *reinterpret_cast<f64x2*>(a.dst64 + prow * MS + rr) = f64x2{v[0], v[1]};
+  *reinterpret_cast<f64x2*>(a.dst64 + prow * MS + rr + 2) = f64x2{v[2], v[3]};
+  if (a.dst32)
+    *reinterpret_cast<f32x4*>(a.dst32 + prow * MS + rr) = f32x4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
+}
+
 // Fine levels: one work-group per 128 target columns computes every row
 // block, so each source column is loaded once (the kernel above re-reads it
 // once per row block) and each target's rows are written together.  The
@@ -429,6 +559,20 @@ struct ShiftRun {
           k_shift_rows<P, 0><<<grid, kThreads, 0, s>>>(a);
         else
           k_shift_rows<P, 1><<<grid, kThreads, 0, s>>>(a);
+        return hipGetLastError();
+      }
+    }
+    if constexpr (S::OCT_STAGE == 8) {
+      if (mode == 0) {  // coarse M2M: octants over the waves, NT column tiles each
+        const int nt = a.nparent >= 2048 ? 4 : a.nparent >= 256 ? 2 : 1;
+        a.ngroups = ((a.nparent + 16 * nt - 1) / (16 * nt)) * S::RB;
+        const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
+        if (nt == 4)
+          k_shift_oct<P, 4><<<grid, kThreads, 0, s>>>(a);
+        else if (nt == 2)
+          k_shift_oct<P, 2><<<grid, kThreads, 0, s>>>(a);
+        else
+          k_shift_oct<P, 1><<<grid, kThreads, 0, s>>>(a);
         return hipGetLastError();
       }
     }
