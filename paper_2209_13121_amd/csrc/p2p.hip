@@ -497,10 +497,11 @@ __global__ void k_p2p_worklist(int64_t nbox, const uint8_t* __restrict__ bucket,
 // the targets being the particles of its 8 children (consecutive Hilbert
 // slots 8P .. 8P + 7, so a contiguous particle range).  The sources of all 8
 // are the 4 x 4 x 4 leaves around P, staged once in LDS (tiles of
-// kGroupTile) as offsets from P's centre in leaf units, leaf by leaf; each
-// target reads the 27 leaves around its own from the per-leaf table.  With at
-// most 32 targets, lanes t and t + 32 share a target, taking neighbour leaves
-// 0..13 and 14..26, combined by one xor shuffle.  Tiles of 256 sources (8 KB
+// kGroupTile) as offsets from P's centre in leaf units, leaf by leaf in
+// lexicographic order; each target reads the 27 leaves around its own as 9
+// runs of 3 leaves adjacent in z, each run's sources contiguous in LDS.  With
+// at most 32 targets, lanes t and t + 32 share a target, taking runs 0..4 and
+// 5..8, combined by one xor shuffle.  Tiles of 256 sources (8 KB
 // of LDS in mixed mode) leave the occupancy to the registers (4 waves per
 // SIMD); tiles of 512 held all 64 leaves of a typical block at once but
 // limited it to 9 waves per CU: 0.37 -> 0.26 ms at 2^20 charges, depth 6.
@@ -583,13 +584,16 @@ __global__ __launch_bounds__(64, waves_per_simd<T>()) void k_p2p_group(
       }
       __syncthreads();
       if (live) {
-        const int d0 = split ? 14 * h : 0, d1 = split ? (h ? 27 : 14) : 27;
-        for (int d = d0; d < d1; ++d) {
-          const int k = kown + 16 * (d / 9 - 1) + 4 * ((d / 3) % 3 - 1) + (d % 3 - 1);
-          // leaf k's sources within this tile: [a, e) (empty when e <= a)
+        // the 27 neighbour leaves as 9 runs of 3 consecutive block leaves (dz =
+        // -1, 0, 1 for each (dx, dy)), whose sources are contiguous in the
+        // staged order; split lanes take runs 0..4 and 5..8
+        const int r0 = split ? 5 * h : 0, r1 = split ? (h ? 9 : 5) : 9;
+        for (int r = r0; r < r1; ++r) {
+          const int k = kown + 16 * (r / 3 - 1) + 4 * (r % 3 - 1) - 1;  // first leaf of the run
+          // the run's sources within this tile: [a, e) (empty when e <= a)
           const int a = (int)(sPre[k] > c0 ? sPre[k] : c0) - (int)c0;
-          const int e = (int)(sPre[k + 1] < c0 + ns ? sPre[k + 1] : c0 + ns) - (int)c0;
-          if (k == kown)
+          const int e = (int)(sPre[k + 3] < c0 + ns ? sPre[k + 3] : c0 + ns) - (int)c0;
+          if (r == 4)  // the run through the target's own leaf (zero distances only there)
             for (int j = a; j < e; ++j) pair<T, true>(acc, tg, sS[j]);
           else
             for (int j = a; j < e; ++j) pair<T, false>(acc, tg, sS[j]);
