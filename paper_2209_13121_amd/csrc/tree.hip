@@ -329,17 +329,13 @@ __global__ void k_luts(int L, int64_t nbox, Layout lay,
   s2c[lay.lvl_off[l] + slot] = pack_coord(x, y, z);
 }
 
+// The particle record of sorted position d: box-unit offset from its leaf
+// centre (FP64; rounded to T), charge slot zero (filled by each evaluation).
 template <typename T>
-__global__ void k_gather(const double* __restrict__ pos, const int32_t* __restrict__ perm,
-                         const uint32_t* __restrict__ keys, int64_t n, int L,
-                         const DevParams* __restrict__ dp, const uint32_t* __restrict__ s2c_leaf,
-                         uint32_t* __restrict__ sorted_leaf, Rec<T>* __restrict__ src,
-                         Rec<double>* __restrict__ src64) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
-  const int32_t i = perm[s];
-  const uint32_t leaf = keys[i];
-  sorted_leaf[s] = leaf;
+__device__ __forceinline__ void write_record(const double* __restrict__ pos, int32_t i, uint32_t leaf,
+                                             int64_t d, int L, const DevParams* __restrict__ dp,
+                                             const uint32_t* __restrict__ s2c_leaf,
+                                             Rec<T>* __restrict__ src, Rec<double>* __restrict__ src64) {
   int c[3];
   unpack_coord(s2c_leaf[leaf], c[0], c[1], c[2]);
   const double h = dp->side / (double)(1 << L);
@@ -354,9 +350,31 @@ __global__ void k_gather(const double* __restrict__ pos, const int32_t* __restri
   r.x = (T)u[0];
   r.y = (T)u[1];
   r.z = (T)u[2];
-  r.q = T(0);  // filled by each evaluation
-  src[s] = r;
-  if (src64) src64[s] = Rec<double>{u[0], u[1], u[2], 0.0};
+  r.q = T(0);
+  src[d] = r;
+  if (src64) src64[d] = Rec<double>{u[0], u[1], u[2], 0.0};
+}
+
+// k_rank and k_gather in one pass (uniform tree): the particle's place in its
+// leaf, then its index, leaf and record at that sorted position.
+template <typename T>
+__global__ void k_rank_gather(const int32_t* __restrict__ perm_tmp, const uint32_t* __restrict__ keys,
+                              int64_t n, const uint32_t* __restrict__ start,
+                              const uint32_t* __restrict__ count, int32_t* __restrict__ perm,
+                              const double* __restrict__ pos, int L, const DevParams* __restrict__ dp,
+                              const uint32_t* __restrict__ s2c_leaf, uint32_t* __restrict__ sorted_leaf,
+                              Rec<T>* __restrict__ src, Rec<double>* __restrict__ src64) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const int32_t me = perm_tmp[s];
+  const uint32_t leaf = keys[me];
+  const uint32_t b = start[leaf], c = count[leaf];
+  uint32_t rank = 0;
+  for (uint32_t t = b; t < b + c; ++t) rank += (perm_tmp[t] < me) ? 1u : 0u;
+  const int64_t d = (int64_t)b + rank;
+  perm[d] = me;
+  sorted_leaf[d] = leaf;
+  write_record<T>(pos, me, leaf, d, L, dp, s2c_leaf, src, src64);
 }
 
 __global__ void k_leaves_out(const uint32_t* __restrict__ keys, int64_t n,
@@ -458,7 +476,7 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
     k_bbox_partial<<<nparts, kBlock, 0, s>>>(d_pos, n, part);
     k_bbox_final<<<1, kBlock, 0, s>>>(part, nparts, dp, flags);
   }
-  {  // the zero row M2L reads for sources outside the domain
+  if (!P->ops_ready) {  // the zero row M2L reads for sources outside the domain (kept by a re-plan)
     const int64_t words = (int64_t)(zero_row_bytes(P->p, P->m2l_np) / 4);
     k_fill_u32<<<grid_for(words, kBlock), kBlock, 0, s>>>(wsp<uint32_t>(P, lay.zero_row), words, 0u);
   }
@@ -487,17 +505,18 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
     if (e != hipSuccess) return e;
     k_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(keys, n, start, fill, perm_tmp);
   }
-  k_rank<<<grid_for(n, kBlock), kBlock, 0, s>>>(perm_tmp, keys, n, start, count, perm);
   if (P->adaptive) {
     // leaves and box-unit offsets come from the adaptive tree (adaptive.hip)
-  } else if (P->mixed)
-    k_gather<float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
-        d_pos, perm, keys, n, L, dp, s2c + lay.lvl_off[L], wsp<uint32_t>(P, lay.sorted_leaf),
-        wsp<Rec<float>>(P, lay.src), wsp<Rec<double>>(P, lay.src64));
-  else
-    k_gather<double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
-        d_pos, perm, keys, n, L, dp, s2c + lay.lvl_off[L], wsp<uint32_t>(P, lay.sorted_leaf),
-        wsp<Rec<double>>(P, lay.src), nullptr);
+    k_rank<<<grid_for(n, kBlock), kBlock, 0, s>>>(perm_tmp, keys, n, start, count, perm);
+  } else if (P->mixed) {
+    k_rank_gather<float><<<grid_for(n, kBlock), kBlock, 0, s>>>(
+        perm_tmp, keys, n, start, count, perm, d_pos, L, dp, s2c + lay.lvl_off[L],
+        wsp<uint32_t>(P, lay.sorted_leaf), wsp<Rec<float>>(P, lay.src), wsp<Rec<double>>(P, lay.src64));
+  } else {
+    k_rank_gather<double><<<grid_for(n, kBlock), kBlock, 0, s>>>(
+        perm_tmp, keys, n, start, count, perm, d_pos, L, dp, s2c + lay.lvl_off[L],
+        wsp<uint32_t>(P, lay.sorted_leaf), wsp<Rec<double>>(P, lay.src), nullptr);
+  }
   prof_end(P, s);
   return hipGetLastError();
 }
