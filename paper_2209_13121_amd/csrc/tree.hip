@@ -192,30 +192,34 @@ __global__ __launch_bounds__(kBlock) void k_coarse_scatter(const uint32_t* __res
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_fine(int64_t n, int L, const uint32_t* __restrict__ off, int64_t nblk,
+// One work-group of kFineThreads per coarse value: a value can hold most of
+// the particles (a dense system of a batch), and its two passes over them
+// are the longest work-group of the launch.
+constexpr int kFineThreads = 1024;
+__global__ __launch_bounds__(kFineThreads) void k_fine(int64_t n, int L, const uint32_t* __restrict__ off, int64_t nblk,
                                                  const uint32_t* __restrict__ key_tmp,
                                                  const int32_t* __restrict__ idx_tmp,
                                                  uint32_t* __restrict__ count, uint32_t* __restrict__ start,
                                                  int32_t* __restrict__ perm_tmp) {
   __shared__ uint32_t cnt[1 << 12];  // fine values: 2^(3L - 9) <= 4096
-  __shared__ uint32_t ssum[kBlock];
+  __shared__ uint32_t ssum[kFineThreads];
   const int tid = threadIdx.x;
   const int64_t c = blockIdx.x;
   const int fb = 1 << (3 * L - 9);
   const uint32_t b0 = off[c * nblk], b1 = off[(c + 1) * nblk];
-  for (int f = tid; f < fb; f += kBlock) cnt[f] = 0;
+  for (int f = tid; f < fb; f += kFineThreads) cnt[f] = 0;
   __syncthreads();
-  for (uint32_t j = b0 + tid; j < b1; j += kBlock) atomicAdd(&cnt[key_tmp[j] & (uint32_t)(fb - 1)], 1u);
+  for (uint32_t j = b0 + tid; j < b1; j += kFineThreads) atomicAdd(&cnt[key_tmp[j] & (uint32_t)(fb - 1)], 1u);
   __syncthreads();
   // exclusive scan of cnt: a chunk of consecutive values per thread, the
   // chunk sums scanned across the work-group
-  const int per = (fb + kBlock - 1) / kBlock;
+  const int per = (fb + kFineThreads - 1) / kFineThreads;
   const int f0 = min(fb, tid * per), f1 = min(fb, f0 + per);
   uint32_t mine = 0;
   for (int f = f0; f < f1; ++f) mine += cnt[f];
   ssum[tid] = mine;
   __syncthreads();
-  for (int w = 1; w < kBlock; w <<= 1) {
+  for (int w = 1; w < kFineThreads; w <<= 1) {
     const uint32_t add = tid >= w ? ssum[tid - w] : 0u;
     __syncthreads();
     ssum[tid] += add;
@@ -232,7 +236,7 @@ __global__ __launch_bounds__(kBlock) void k_fine(int64_t n, int L, const uint32_
   }
   if (c == kSortCoarse - 1 && tid == 0) start[(int64_t)kSortCoarse * fb] = (uint32_t)n;
   __syncthreads();
-  for (uint32_t j = b0 + tid; j < b1; j += kBlock) {
+  for (uint32_t j = b0 + tid; j < b1; j += kFineThreads) {
     const uint32_t at = atomicAdd(&cnt[key_tmp[j] & (uint32_t)(fb - 1)], 1u);
     perm_tmp[at] = idx_tmp[j];
   }
@@ -495,7 +499,7 @@ hipError_t launch_tree(fmm_plan_s* P, const double* d_pos, hipStream_t s) {
     hipError_t e = scan_exclusive(hist, nh, nh, hist, wsp<uint32_t>(P, lay.scan_tmp), s);
     if (e != hipSuccess) return e;
     k_coarse_scatter<<<(unsigned)nblk, kBlock, 0, s>>>(keys, n, L, hist, nblk, key_tmp, perm);
-    k_fine<<<kSortCoarse, kBlock, 0, s>>>(n, L, hist, nblk, key_tmp, perm, count, start, perm_tmp);
+    k_fine<<<kSortCoarse, kFineThreads, 0, s>>>(n, L, hist, nblk, key_tmp, perm, count, start, perm_tmp);
   } else {
     k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(count, lay.nleaf, 0u);
     k_fill_u32<<<grid_for(lay.nleaf, kBlock), kBlock, 0, s>>>(fill, lay.nleaf, 0u);
