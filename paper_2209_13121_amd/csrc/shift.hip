@@ -39,6 +39,8 @@ constexpr int kStageBatch = 8;
 // s_waitcnt operand: vector memory count 0, the other counters unconstrained
 // (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8)
 constexpr int kVmcntZero = 0x0F70;
+template <int N>
+constexpr int kVmcntNQ = 0x0F70 | (N & 15) | ((N >> 4) << 14);  // vector memory count N (< 64)
 
 template <int P, int MODE>
 struct ShiftShape {
@@ -255,9 +257,10 @@ __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
 // (parents / 128) x RB, each wave running NT octant products instead of 8.
 // The octant partials of every column are then added in octant order through
 // LDS (the staged rows' space).  For p with all 8 octants' rows in LDS.
-template <int P, int NT>
+template <int P, int NT, typename TS>
 __global__ __launch_bounds__(kThreads) void k_shift_oct(ShiftArgs a) {
   typedef ShiftShape<P, 0> S;
+  typedef TS TS2 __attribute__((ext_vector_type(2)));  // the sources' type, as loaded
   constexpr int NC = S::NC, RB = S::RB, MS = S::MS, KP = S::KP, NQ = S::NQ, RS = S::RS;
   static_assert(S::OCT_STAGE == 8, "every octant's rows staged at once");
   // 16-byte LDS units: the staged rows, then the partials (8 NT tiles of 64
@@ -297,7 +300,7 @@ __global__ __launch_bounds__(kThreads) void k_shift_oct(ShiftArgs a) {
 
   // this wave's octant: the child of each parent in that octant
   const int oct = wave;
-  auto load_b = [&](int t, f64x2* bv) {
+  auto load_b = [&](int t, TS2* bv) {
     const int64_t ps = (pgroup * NT + t) * 16 + col;
     const bool ok = ps < a.nparent;
     int child = 0;
@@ -312,17 +315,11 @@ __global__ __launch_bounds__(kThreads) void k_shift_oct(ShiftArgs a) {
     for (int q = 0; q < NQ; ++q) {
       const int k = 8 * q + 2 * kg;
       const int k0 = k < MS ? k : MS - 2;
-      f64x2 v;
-      if (a.mixed) {  // FP32 children (the uniform tree's mixed leaves)
-        const f32x2 w = *reinterpret_cast<const f32x2*>(static_cast<const float*>(a.src) + srow * MS + k0);
-        v = f64x2{(double)w[0], (double)w[1]};
-      } else {
-        v = *reinterpret_cast<const f64x2*>(static_cast<const double*>(a.src) + srow * MS + k0);
-      }
-      bv[q] = (ok && k < MS) ? v : f64x2{0.0, 0.0};
+      const TS2 v = *reinterpret_cast<const TS2*>(static_cast<const TS*>(a.src) + srow * MS + k0);
+      bv[q] = (ok && k < MS) ? v : TS2{TS(0), TS(0)};
     }
   };
-  f64x2 bcur[NQ], bnext[NQ];
+  TS2 bcur[NQ], bnext[NQ];
   load_b(0, bcur);
   __syncthreads();
   f64x4 part[NT];
@@ -335,8 +332,8 @@ __global__ __launch_bounds__(kThreads) void k_shift_oct(ShiftArgs a) {
     for (int q = 0; q < NQ; ++q) {
       if (q >= q1) continue;  // uniform over the work-group
       const f64x2 av = sa[4 * q];
-      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bcur[q][0], acc0, 0, 0, 0);
-      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bcur[q][1], acc1, 0, 0, 0);
+      acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], (double)bcur[q][0], acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], (double)bcur[q][1], acc1, 0, 0, 0);
     }
     part[t] = acc0 + acc1;
     if (t + 1 < NT) {
@@ -388,11 +385,15 @@ __global__ __launch_bounds__(kThreads) void k_shift_oct(ShiftArgs a) {
 // work-group.  Used where the row blocks' accumulators and the source
 // registers fit (at most 6 row blocks, p <= 8) and the level has enough
 // columns to fill the chip.
-template <int P, int MODE>
+// TS: the sources' type (float: the FP32 leaf multipoles of the mixed uniform
+// tree, kept as loaded until their products, so their loads stay in flight).
+template <int P, int MODE, typename TS>
 __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
   typedef ShiftShape<P, MODE> S;
+  typedef TS TS2 __attribute__((ext_vector_type(2)));
   constexpr int NC = S::NC, RB = S::RB, MS = S::MS, KP = S::KP, NQ = S::NQ, RS = S::RS;
-  __shared__ f64x2 sA[kRowsUnits<P>];
+  // M2M: two operator buffers (one work-group per CU); L2L: one (two per CU)
+  __shared__ f64x2 sA[(MODE == 0 ? 2 : 1) * kRowsUnits<P>];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, kg = lane >> 4;
@@ -427,51 +428,21 @@ __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
       q1 = NQ;
     }
   };
-  auto load_b = [&](int oct, f64x2* bv) {
+  auto load_b = [&](int oct, TS2* bv) {
     const int64_t srow = !ok ? 0 : (MODE == 0 ? 8 * ps + child_of(oct) : prow);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int k = 8 * q + 2 * kg;
       const int k0 = k < MS ? k : MS - 2;
-      f64x2 v;
-      if (MODE == 0 && a.mixed) {  // FP32 children (the uniform tree's mixed leaves)
-        const f32x2 w = *reinterpret_cast<const f32x2*>(static_cast<const float*>(a.src) + srow * MS + k0);
-        v = f64x2{(double)w[0], (double)w[1]};
-      } else {
-        v = *reinterpret_cast<const f64x2*>(static_cast<const double*>(a.src) + srow * MS + k0);
-      }
-      bv[q] = (ok && k < MS) ? v : f64x2{0.0, 0.0};
+      const TS2 v = *reinterpret_cast<const TS2*>(static_cast<const TS*>(a.src) + srow * MS + k0);
+      bv[q] = (ok && k < MS) ? v : TS2{TS(0), TS(0)};
     }
   };
-  f64x4 acc0[RB], acc1[RB];
-#pragma unroll
-  for (int r = 0; r < RB; ++r) acc0[r] = acc1[r] = f64x4{0, 0, 0, 0};
-  f64x2 bcur[NQ], bnext[NQ];
-  load_b(MODE == 0 ? 0 : oct_l2l, bcur);
-  const int64_t cs = MODE == 1 && ok ? 8 * ps + child_of(oct_l2l) : 0;
-  if (MODE == 1 && ok) {
-    // L2L: the child's (1/h) M2L result starts the accumulators (lane (col,
-    // kg) holds rows 16 rb + kg + 4 i of its column), so its loads are in
-    // flight while the operator rows are staged
-    const double inv_h = (double)(1 << a.l) / a.dp->side;
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = 16 * rb + kg + 4 * i;
-        if (row < NC)
-          acc0[rb][i] = inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + row]
-                                         : static_cast<const double*>(a.m2l)[cs * NC + row]);
-      }
-  }
-  constexpr int NOCT = MODE == 0 ? 8 : 1;
-  for (int o = 0; o < NOCT; ++o) {
-    const int oct = MODE == 0 ? o : oct_l2l;
-    if (o > 0) __syncthreads();  // the previous octant's rows are no longer read
-    // stage every row of octant oct, the k pairs of its row block only, by DMA
-    // from global memory into LDS, 64 units per wave instruction: LDS unit e
-    // is row e / RS, 16-byte unit e % RS; units outside the block's k pairs
-    // (never read) fetch the row's first unit.
+  // stage every row of octant oct, the k pairs of its row block only, by DMA
+  // from global memory into LDS buffer buf, 64 units per wave instruction: LDS
+  // unit e is row e / RS, 16-byte unit e % RS; units outside the block's k
+  // pairs (never read) fetch the row's first unit.
+  auto stage = [&](int oct, f64x2* buf) {
     for (int e0 = wave * 64; e0 < kRowsUnits<P>; e0 += kThreads) {
       const int e = e0 + lane;
       const int row = e / RS < RB * 16 ? e / RS : 0, u = e % RS, q = u / 4;
@@ -480,40 +451,92 @@ __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
       const bool v = u < 4 * NQ && q >= q0 && q < q1;
       __builtin_amdgcn_global_load_lds(
           (__attribute__((address_space(1))) void*)(a.ops + ((size_t)oct * (RB * 16) + row) * KP + (v ? 2 * u : 0)),
-          (__attribute__((address_space(3))) void*)(sA + e0), 16, 0, 0);
+          (__attribute__((address_space(3))) void*)(buf + e0), 16, 0, 0);
     }
-    __builtin_amdgcn_s_waitcnt(kVmcntZero);  // this wave's copies have landed
-    __syncthreads();
-    if (MODE == 0 && o + 1 < NOCT) load_b(o + 1, bnext);  // next octant in flight
+  };
+  // the products of one octant: rows of LDS buffer buf times sources b
+  f64x4 acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = f64x4{0, 0, 0, 0};
+  auto products = [&](const f64x2* buf, const TS2* b) {
+    f64x2 bq[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) bq[q] = f64x2{(double)b[q][0], (double)b[q][1]};
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
       int q0, q1;
       qrange(rb, q0, q1);
-      const f64x2* sa = sA + (16 * rb + col) * RS + kg;
+      const f64x2* sa = buf + (16 * rb + col) * RS + kg;
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         if (q < q0 || q >= q1) continue;  // uniform over the work-group
         const f64x2 av = sa[4 * q];
-        acc0[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bcur[q][0], acc0[rb], 0, 0, 0);
-        acc1[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bcur[q][1], acc1[rb], 0, 0, 0);
+        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0], bq[q][0], acc[rb], 0, 0, 0);
+        acc[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1], bq[q][1], acc[rb], 0, 0, 0);
       }
     }
-    if (MODE == 0 && o + 1 < NOCT) {
+  };
+  const int64_t cs = MODE == 1 && ok ? 8 * ps + child_of(oct_l2l) : 0;
+  if constexpr (MODE == 1) {
+    TS2 b[NQ];
+    load_b(oct_l2l, b);
+    if (ok) {
+      // L2L: the child's (1/h) M2L result starts the accumulators (lane (col,
+      // kg) holds rows 16 rb + kg + 4 i of its column), so its loads are in
+      // flight while the operator rows are staged
+      const double inv_h = (double)(1 << a.l) / a.dp->side;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) bcur[q] = bnext[q];
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * rb + kg + 4 * i;
+          if (row < NC)
+            acc[rb][i] = inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + row]
+                                          : static_cast<const double*>(a.m2l)[cs * NC + row]);
+        }
+    }
+    stage(oct_l2l, sA);
+    __builtin_amdgcn_s_waitcnt(kVmcntZero);  // this wave's copies have landed
+    __syncthreads();
+    products(sA, b);
+  } else {
+    // M2M, the 8 octants in turn: octant o + 1's rows are copied into the
+    // other LDS buffer while octant o's products run, and each octant's
+    // sources are loaded two octants ahead (three register buffers).  The wait
+    // at the end of octant o leaves only octant o + 2's source loads, issued
+    // after the copy, in flight.
+    TS2 b[3][NQ];
+    stage(0, sA);
+    load_b(0, b[0]);
+    load_b(1, b[1]);
+    __builtin_amdgcn_s_waitcnt(kVmcntZero);
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < 8; ++o) {
+      if (o + 1 < 8) stage(o + 1, sA + ((o + 1) & 1) * kRowsUnits<P>);
+      __builtin_amdgcn_sched_barrier(0);  // the copy is issued before the source loads
+      if (o + 2 < 8) load_b(o + 2, b[(o + 2) % 3]);
+      products(sA + (o & 1) * kRowsUnits<P>, b[o % 3]);
+      if (o + 1 < 8) {
+        if (o + 2 < 8)
+          __builtin_amdgcn_s_waitcnt(kVmcntNQ<NQ>);  // all but octant o + 2's NQ source loads
+        else
+          __builtin_amdgcn_s_waitcnt(kVmcntZero);
+        __syncthreads();  // octant o + 1's rows are in; octant o's buffer is free
+      }
     }
   }
   if (!ok) return;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) {
-    const f64x4 acc = acc0[rb] + acc1[rb];
+    const f64x4 acc_rb = acc[rb];
     // transpose across the 4 lanes of a column (as in k_shift): this lane then
     // holds rows 16 rb + 4 kg + j, j = 0..3
     double v[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const int i_send = (kg - t) & 3;
-      const double send = i_send == 0 ? acc[0] : i_send == 1 ? acc[1] : i_send == 2 ? acc[2] : acc[3];
+      const double send = i_send == 0 ? acc_rb[0] : i_send == 1 ? acc_rb[1] : i_send == 2 ? acc_rb[2] : acc_rb[3];
       const double got = __shfl(send, ((kg + t) & 3) * 16 + col);
       const int j = (kg + t) & 3;
       if (j == 0) v[0] = got;
@@ -555,10 +578,12 @@ struct ShiftRun {
       if (a.nparent * (mode == 1 ? 8 : 1) >= kRowsMinColumns) {
         a.ngroups = pgroups * (mode == 1 ? 8 : 1);
         const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
-        if (mode == 0)
-          k_shift_rows<P, 0><<<grid, kThreads, 0, s>>>(a);
+        if (mode == 1)
+          k_shift_rows<P, 1, double><<<grid, kThreads, 0, s>>>(a);
+        else if (a.mixed)
+          k_shift_rows<P, 0, float><<<grid, kThreads, 0, s>>>(a);
         else
-          k_shift_rows<P, 1><<<grid, kThreads, 0, s>>>(a);
+          k_shift_rows<P, 0, double><<<grid, kThreads, 0, s>>>(a);
         return hipGetLastError();
       }
     }
@@ -567,12 +592,19 @@ struct ShiftRun {
         const int nt = a.nparent >= 2048 ? 4 : a.nparent >= 256 ? 2 : 1;
         a.ngroups = ((a.nparent + 16 * nt - 1) / (16 * nt)) * S::RB;
         const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
-        if (nt == 4)
-          k_shift_oct<P, 4><<<grid, kThreads, 0, s>>>(a);
-        else if (nt == 2)
-          k_shift_oct<P, 2><<<grid, kThreads, 0, s>>>(a);
+        auto go = [&](auto ts) {
+          typedef decltype(ts) TS;
+          if (nt == 4)
+            k_shift_oct<P, 4, TS><<<grid, kThreads, 0, s>>>(a);
+          else if (nt == 2)
+            k_shift_oct<P, 2, TS><<<grid, kThreads, 0, s>>>(a);
+          else
+            k_shift_oct<P, 1, TS><<<grid, kThreads, 0, s>>>(a);
+        };
+        if (a.mixed)
+          go(float{});
         else
-          k_shift_oct<P, 1><<<grid, kThreads, 0, s>>>(a);
+          go(double{});
         return hipGetLastError();
       }
     }
