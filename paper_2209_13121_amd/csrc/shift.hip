@@ -87,7 +87,8 @@ struct ShiftArgs {
   const uint32_t* parent_of;
 };
 
-template <int P, int MODE>
+// TM: the L2L's M2L results' type (float in the mixed mode).
+template <int P, int MODE, typename TM = double>
 __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
   typedef ShiftShape<P, MODE> S;
   constexpr int NC = S::NC, RB = S::RB, MS = S::MS, KP = S::KP, NQ = S::NQ, RS = S::RS;
@@ -234,11 +235,12 @@ __global__ __launch_bounds__(kThreads) void k_shift(ShiftArgs a) {
   } else {
     const int64_t cs = 8 * ps + child_of(oct_l2l);
     const double inv_h = (double)(1 << a.l) / a.dp->side;
+    TM w[4];  // all four loads in flight before the first use
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = static_cast<const TM*>(a.m2l)[cs * NC + (rr + j < NC ? rr + j : 0)];
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (rr + j < NC)
-        v[j] += inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + rr + j]
-                                 : static_cast<const double*>(a.m2l)[cs * NC + rr + j]);
+      if (rr + j < NC) v[j] += inv_h * (double)w[j];
     // uniform leaf level (mixed): FP32 only; otherwise FP64, plus an FP32 copy
     // where dst32 is given (adaptive, mixed: every level holds leaves)
     if (!(a.leaf && a.mixed)) {
@@ -386,8 +388,9 @@ __global__ __launch_bounds__(kThreads) void k_shift_oct(ShiftArgs a) {
 // registers fit (at most 6 row blocks, p <= 8) and the level has enough
 // columns to fill the chip.
 // TS: the sources' type (float: the FP32 leaf multipoles of the mixed uniform
-// tree, kept as loaded until their products, so their loads stay in flight).
-template <int P, int MODE, typename TS>
+// tree, kept as loaded until their products, so their loads stay in flight);
+// TM: the L2L's M2L results' type (float in the mixed mode), likewise.
+template <int P, int MODE, typename TS, typename TM = double>
 __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
   typedef ShiftShape<P, MODE> S;
   typedef TS TS2 __attribute__((ext_vector_type(2)));
@@ -480,24 +483,27 @@ __global__ __launch_bounds__(kThreads) void k_shift_rows(ShiftArgs a) {
   if constexpr (MODE == 1) {
     TS2 b[NQ];
     load_b(oct_l2l, b);
-    if (ok) {
-      // L2L: the child's (1/h) M2L result starts the accumulators (lane (col,
-      // kg) holds rows 16 rb + kg + 4 i of its column), so its loads are in
-      // flight while the operator rows are staged
-      const double inv_h = (double)(1 << a.l) / a.dp->side;
+    // L2L: the child's (1/h) M2L result starts the accumulators (lane (col, kg)
+    // holds rows 16 rb + kg + 4 i of its column); loaded here, so the loads are
+    // in flight while the operator rows are staged (rows past ncoef, or a
+    // column past the level, read row 0 and are not used)
+    TM m2lv[RB][4];
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int row = 16 * rb + kg + 4 * i;
-          if (row < NC)
-            acc[rb][i] = inv_h * (a.mixed ? (double)static_cast<const float*>(a.m2l)[cs * NC + row]
-                                          : static_cast<const double*>(a.m2l)[cs * NC + row]);
-        }
-    }
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * rb + kg + 4 * i;
+        m2lv[rb][i] = static_cast<const TM*>(a.m2l)[cs * NC + (ok && row < NC ? row : 0)];
+      }
     stage(oct_l2l, sA);
     __builtin_amdgcn_s_waitcnt(kVmcntZero);  // this wave's copies have landed
     __syncthreads();
+    const double inv_h = (double)(1 << a.l) / a.dp->side;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (ok && 16 * rb + kg + 4 * i < NC) acc[rb][i] = inv_h * (double)m2lv[rb][i];
     products(sA, b);
   } else {
     // M2M, the 8 octants in turn: octant o + 1's rows are copied into the
@@ -578,8 +584,10 @@ struct ShiftRun {
       if (a.nparent * (mode == 1 ? 8 : 1) >= kRowsMinColumns) {
         a.ngroups = pgroups * (mode == 1 ? 8 : 1);
         const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
-        if (mode == 1)
-          k_shift_rows<P, 1, double><<<grid, kThreads, 0, s>>>(a);
+        if (mode == 1 && a.mixed)
+          k_shift_rows<P, 1, double, float><<<grid, kThreads, 0, s>>>(a);
+        else if (mode == 1)
+          k_shift_rows<P, 1, double, double><<<grid, kThreads, 0, s>>>(a);
         else if (a.mixed)
           k_shift_rows<P, 0, float><<<grid, kThreads, 0, s>>>(a);
         else
@@ -612,8 +620,10 @@ struct ShiftRun {
     const unsigned grid = (unsigned)(((a.ngroups + 7) / 8) * 8);
     if (mode == 0)
       k_shift<P, 0><<<grid, kThreads, 0, s>>>(a);
+    else if (a.mixed)
+      k_shift<P, 1, float><<<grid, kThreads, 0, s>>>(a);
     else
-      k_shift<P, 1><<<grid, kThreads, 0, s>>>(a);
+      k_shift<P, 1, double><<<grid, kThreads, 0, s>>>(a);
     return hipGetLastError();
   }
 };
