@@ -159,12 +159,21 @@ __global__ __launch_bounds__(kBlock) void k_keys_hist(const double* __restrict__
   const int sh = 3 * L - 9;
   const double side = dp->side;
   int32_t flag = 0;
-  for (int r = 0; r < kSortChunk / kBlock; ++r) {
+  constexpr int R = kSortChunk / kBlock;
+  double x[R][3];  // every position of the thread in flight before the first key
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = (int64_t)blockIdx.x * kSortChunk + r * kBlock + threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[r][a] = i < n ? pos[3 * i + a] : 0.0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
     const int64_t i = (int64_t)blockIdx.x * kSortChunk + r * kBlock + threadIdx.x;
     if (i >= n) break;
-    const int cx = leaf_cell(pos[3 * i + 0], dp->lo[0], side, L, check_cube, flag);
-    const int cy = leaf_cell(pos[3 * i + 1], dp->lo[1], side, L, check_cube, flag);
-    const int cz = leaf_cell(pos[3 * i + 2], dp->lo[2], side, L, check_cube, flag);
+    const int cx = leaf_cell(x[r][0], dp->lo[0], side, L, check_cube, flag);
+    const int cy = leaf_cell(x[r][1], dp->lo[1], side, L, check_cube, flag);
+    const int cz = leaf_cell(x[r][2], dp->lo[2], side, L, check_cube, flag);
     const uint32_t key = (uint32_t)hilbert_index(cx, cy, cz, L);
     keys[i] = key;
     atomicAdd(&h[key >> sh], 1u);
@@ -182,12 +191,19 @@ __global__ __launch_bounds__(kBlock) void k_coarse_scatter(const uint32_t* __res
   for (int c = threadIdx.x; c < kSortCoarse; c += kBlock) base[c] = off[(int64_t)c * nblk + blockIdx.x];
   __syncthreads();
   const int sh = 3 * L - 9;
-  for (int r = 0; r < kSortChunk / kBlock; ++r) {
+  constexpr int R = kSortChunk / kBlock;
+  uint32_t kk[R];  // every key of the thread in flight before the first placement
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int64_t i = (int64_t)blockIdx.x * kSortChunk + r * kBlock + threadIdx.x;
+    kk[r] = i < n ? keys[i] : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
     const int64_t i = (int64_t)blockIdx.x * kSortChunk + r * kBlock + threadIdx.x;
     if (i >= n) break;
-    const uint32_t key = keys[i];
-    const uint32_t at = atomicAdd(&base[key >> sh], 1u);
-    key_tmp[at] = key;
+    const uint32_t at = atomicAdd(&base[kk[r] >> sh], 1u);
+    key_tmp[at] = kk[r];
     idx_tmp[at] = (int32_t)i;
   }
 }
