@@ -281,23 +281,19 @@ __global__ __launch_bounds__(kThreads) void k_shift_oct(ShiftArgs a) {
   const int d = degree_of(min(row0 + 15, NC - 1));
   const int q1 = ((d + 1) * (d + 1) + 7) / 8;  // k pairs the block can touch (lower in degree)
 
-  // stage rows row0 .. row0 + 15 of the 8 octants, pairs 0 .. q1 - 1
-  const int ne = 8 * 16 * 4 * q1;
-  for (int e0 = 0; e0 < ne; e0 += kStageBatch * kThreads) {
-    f64x2 st[kStageBatch];  // every load of the batch in flight before the first store
-#pragma unroll
-    for (int i = 0; i < kStageBatch; ++i) {
-      const int e = e0 + tid + i * kThreads;
-      const int u = e % (4 * q1), r = e / (4 * q1) % 16, oo = e / (4 * q1 * 16);
-      if (e < ne)
-        st[i] = *reinterpret_cast<const f64x2*>(a.ops + ((size_t)oo * (RB * 16) + row0 + r) * KP + 2 * u);
-    }
-#pragma unroll
-    for (int i = 0; i < kStageBatch; ++i) {
-      const int e = e0 + tid + i * kThreads;
-      const int u = e % (4 * q1), r = e / (4 * q1) % 16, oo = e / (4 * q1 * 16);
-      if (e < ne) sA[(oo * 16 + r) * RS + u] = st[i];
-    }
+  // stage rows row0 .. row0 + 15 of the 8 octants, pairs 0 .. q1 - 1, by DMA
+  // from global memory into LDS, 64 units per wave instruction: LDS unit e is
+  // octant row e / RS (octant (e / RS) / 16, row row0 + (e / RS) % 16),
+  // 16-byte unit e % RS; units past the block's pairs (never read) fetch the
+  // row's first unit.  In flight together with the first tile's sources.
+  for (int e0 = wave * 64; e0 < 8 * 16 * RS; e0 += kThreads) {
+    const int e = e0 + lane;
+    const int orow = e / RS, u = e % RS;
+    const bool v = u < 4 * q1;
+    __builtin_amdgcn_global_load_lds(
+        (__attribute__((address_space(1))) void*)(a.ops + ((size_t)(orow >> 4) * (RB * 16) + row0 + (orow & 15)) * KP +
+                                                  (v ? 2 * u : 0)),
+        (__attribute__((address_space(3))) void*)(sA + e0), 16, 0, 0);
   }
 
   // this wave's octant: the child of each parent in that octant
@@ -323,6 +319,7 @@ __global__ __launch_bounds__(kThreads) void k_shift_oct(ShiftArgs a) {
   };
   TS2 bcur[NQ], bnext[NQ];
   load_b(0, bcur);
+  __builtin_amdgcn_s_waitcnt(kVmcntZero);  // this wave's copies have landed
   __syncthreads();
   f64x4 part[NT];
   const f64x2* sa = sA + (oct * 16 + col) * RS + kg;
