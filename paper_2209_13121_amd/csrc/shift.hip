@@ -4,13 +4,18 @@
 // each level is a set of dense products batched by octant:
 //   M2M  M~p[:, parents]          = sum_o A_o * M~[:, child of octant o]
 //   L2L  L~[:, children of oct o] = (1/h) M2L[:, ...] + B_o * L~[:, parents]
-// FP64 in both precision modes.
-//  * One work-group owns one 16-row block of the expansions and 8 tiles of
-//    16 targets, one tile per wave: 128 parents for M2M, the octant-o
-//    children of 128 parents for L2L.  The row block's rows of the operators
-//    it needs (all 8 octants for M2M, octant o for L2L) are staged in LDS
-//    once and shared by the 8 waves; the grid runs over (row block, tiles),
-//    so even the coarse levels spread over many work-groups.
+// FP64 in both precision modes.  Three forms:
+//  * k_shift (row-block form): one work-group owns one 16-row block of the
+//    expansions and 8 tiles of 16 targets, one tile per wave: 128 parents for
+//    M2M, the octant-o children of 128 parents for L2L.  The row block's rows
+//    of the operators it needs (all 8 octants for M2M, octant o for L2L) are
+//    staged in LDS once and shared by the 8 waves; the grid runs over (row
+//    block, tiles), so even the coarse levels spread over many work-groups.
+//    L2L's coarse levels (and M2M at p >= 12) run here.
+//  * k_shift_oct (coarse M2M, p <= 11): as above, but the 8 waves take the 8
+//    octants of 1-4 column tiles, whose partials are added through LDS.
+//  * k_shift_rows (fine levels, p <= 8): a work-group computes every row
+//    block of 128 columns, so each source column is loaded once.
 //  * The translations are triangular in degree: a parent multipole of degree
 //    n takes child degrees <= n only, a child local of degree n parent
 //    degrees >= n only (the addition theorems of the solid harmonics;
